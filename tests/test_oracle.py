@@ -1,0 +1,195 @@
+"""Pins for the CPU oracle (no GPU): hand-worked examples, a closed form,
+brute force on tiny inputs, invariants, and special cases."""
+
+from __future__ import annotations
+
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import brute
+import oracle
+from paper_1409_7208_amd import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _bits_to_int(words) -> int:
+    v = 0
+    for i, w in enumerate(words):
+        v |= int(w) << (64 * i)
+    return v
+
+
+def _edges_of(reads, k, d, mercy):
+    rs = synth.from_strings(reads, k, d, mercy)
+    return rs, oracle.count_solid(rs.seq, rs.offsets, k, d, mercy)
+
+
+with open(os.path.join(HERE, "golden", "toys.json")) as f:
+    TOYS = json.load(f)["toys"]
+
+
+@pytest.mark.parametrize("toy", TOYS, ids=[t["name"] for t in TOYS])
+def test_hand_worked_toys(toy):
+    k = toy["k"]
+    _, e = _edges_of(toy["reads"], k, toy["d"], toy["mercy"])
+    assert e.keys[:, -1].tolist() == toy["keys"]
+    assert e.counts.tolist() == toy["counts"]
+    assert e.n_mercy == toy["n_mercy"]
+    assert e.n_occ == toy["n_occ"]
+    g = oracle.build_graph(e.keys, e.counts, k)
+    assert g.m == toy["m"] and g.t == toy["t"]
+    assert g.W.tolist() == toy["W"]
+    assert _bits_to_int(g.last) == int(toy["last"], 16)
+    assert _bits_to_int(g.valid) == int(toy["valid"], 16)
+    assert _bits_to_int(g.tip) == int(toy["tip"], 16)
+    assert g.mult.tolist() == toy["mult"]
+    assert g.F.tolist() == toy["F"]
+    assert _bits_to_int(g.tip_seq) == int(toy["tip_seq"], 16)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5])
+def test_complete_graph_closed_form(k):
+    """Every (k+1)-mer read twice: each edge counted 4 times (palindromes
+    included), no '$' or dummy rows, and the arrays have a closed form."""
+    reads = ["".join(p) for p in itertools.product("ACGT", repeat=k + 1)] * 2
+    _, e = _edges_of(reads, k, 2, False)
+    n = 4 ** (k + 1)
+    assert e.keys.shape[0] == n
+    assert (e.counts == 4).all()
+    assert [brute.words_to_key(r) for r in e.keys] == list(range(n))
+    g = oracle.build_graph(e.keys, e.counts, k)
+    assert g.m == n and g.t == 0
+    i = np.arange(n)
+    W = (i % 4) + 1 + 8 * ((i // 4) % 4 != 0)
+    assert (g.W == W).all()
+    last = [(x % 4 == 3) for x in range(n)]
+    assert _bits_to_int(g.last) == sum(1 << x for x in range(n) if last[x])
+    assert _bits_to_int(g.valid) == (1 << n) - 1
+    assert _bits_to_int(g.tip) == 0
+    assert (g.mult == 4).all()
+    assert g.F.tolist() == [0, 0, 4**k, 2 * 4**k, 3 * 4**k, 4 ** (k + 1)]
+    assert g.tip_seq.size == 0
+
+
+def _random_cases():
+    cases = []
+    for seed in range(24):
+        k = [2, 3, 4, 5, 6, 7][seed % 6]
+        d = [1, 2, 3][seed % 3]
+        mercy = seed % 2 == 0
+        n_rate = 0.05 if seed % 4 == 1 else 0.0
+        cases.append((seed, k, d, mercy, n_rate))
+    # a few longer k covering two, three and four key words
+    cases += [(100, 33, 2, True, 0.0), (101, 47, 2, True, 0.02), (102, 70, 2, False, 0.0), (103, 99, 2, True, 0.0), (104, 127, 1, True, 0.0)]
+    return cases
+
+
+@pytest.mark.parametrize("seed,k,d,mercy,n_rate", _random_cases())
+def test_oracle_matches_brute_force(seed, k, d, mercy, n_rate):
+    glen = 40 if k < 8 else 4 * k
+    rs = synth.random_small(30, k, k + 20, glen, 0.03, seed, n_rate=n_rate)
+    reads = rs.reads()
+    E, M = brute.brute_edges(reads, k, d, mercy)
+    e = oracle.count_solid(rs.seq, rs.offsets, k, d, mercy)
+    got = {brute.key_to_edge(brute.words_to_key(r), k): int(c) for r, c in zip(e.keys, e.counts)}
+    assert got == E
+    assert e.n_mercy == len(M)
+    keys = [brute.words_to_key(r) for r in e.keys]
+    assert keys == sorted(keys) and len(set(keys)) == len(keys)
+    assert keys == sorted(brute.edge_key(x) for x in E)
+    # I1: every occurrence of every strand counted
+    assert e.n_occ == sum(brute.brute_counts(reads, k).values())
+    # graph: decode the arrays by navigation and compare to the explicit graph
+    g = oracle.build_graph(e.keys, e.counts, k)
+    nodes, edges = brute.decode_sdbg(g.W, g.last, g.valid, g.tip, g.mult, g.F, g.tip_seq, g.m, k)
+    exp_nodes, z_out, z_in = brute.expected_graph(E, k)
+    assert edges == E
+    assert nodes == exp_nodes
+    assert g.t == len(z_in)
+    assert g.m == len(E) + len(z_out) + len(z_in)
+
+
+def test_d1_no_mercy_is_all_windows():
+    rs = synth.random_small(40, 10, 30, 200, 0.05, 7)
+    k = 5
+    e = oracle.count_solid(rs.seq, rs.offsets, k, 1, False)
+    want = set()
+    for s in brute.segments(rs.reads()):
+        for i in range(len(s) - k):
+            want.add(s[i : i + k + 1])
+            want.add(brute.revcomp(s[i : i + k + 1]))
+    got = {brute.key_to_edge(brute.words_to_key(r), k) for r in e.keys}
+    assert got == want
+    assert int(e.counts.astype(np.uint64).sum()) == e.n_occ
+
+
+def test_invariants_on_tiny_workload():
+    rs = synth.tiny(scale=0.1)
+    k = rs.k
+    for mercy in (False, True):
+        e = oracle.count_solid(rs.seq, rs.offsets, k, 2, mercy)
+        keys = [brute.words_to_key(r) for r in e.keys]
+        assert all(a < b for a, b in zip(keys, keys[1:]))  # I2
+        edges = {brute.key_to_edge(x, k): int(c) for x, c in zip(keys, e.counts)}
+        for x, c in edges.items():  # I3: reverse-complement closure with equal counts
+            assert edges.get(brute.revcomp(x)) == c
+        assert e.n_occ == 2 * rs.n_windows(k)
+        if not mercy:
+            assert (e.counts >= 2).all() and e.n_mercy == 0
+        else:
+            assert int((e.counts < 2).sum()) == e.n_mercy
+        g = oracle.build_graph(e.keys, e.counts, k)
+        # I5-I8
+        P = {x[:k] for x in edges}
+        Q = {x[1:] for x in edges}
+        z_out, z_in = Q - P, P - Q
+        assert {brute.revcomp(v) for v in z_out} == z_in
+        assert g.m == len(edges) + 2 * len(z_in)
+        popc = lambda ws: sum(bin(int(w)).count("1") for w in ws)
+        assert popc(g.valid) == len(edges)
+        assert popc(g.tip) == g.t == len(z_in)
+        assert popc(g.last) == len(P) + len(z_out) + len({"$" + v[:-1] for v in z_in})
+        assert int(g.F[5]) == g.m
+
+
+def test_mercy_only_adds_low_count_edges():
+    rs = synth.random_small(60, 12, 40, 300, 0.04, 11)
+    k = 7
+    off = oracle.count_solid(rs.seq, rs.offsets, k, 2, False)
+    on = oracle.count_solid(rs.seq, rs.offsets, k, 2, True)
+    s_off = {brute.words_to_key(r) for r in off.keys}
+    s_on = {brute.words_to_key(r): int(c) for r, c in zip(on.keys, on.counts)}
+    assert s_off <= set(s_on)  # I11: S is a subset of E
+    added = {x: c for x, c in s_on.items() if x not in s_off}
+    assert len(added) == on.n_mercy
+    assert all(1 <= c < 2 for c in added.values())
+    added_e = {brute.key_to_edge(x, k) for x in added}
+    assert {brute.revcomp(x) for x in added_e} == added_e
+
+
+def test_count_keys_matches_counts():
+    rs = synth.tiny(scale=0.05)
+    e = oracle.count_solid(rs.seq, rs.offsets, rs.k, 1, False)
+    idx = np.random.default_rng(0).choice(e.keys.shape[0], size=200, replace=False)
+    got = oracle.count_keys(rs.seq, rs.offsets, rs.k, e.keys[idx], threads=4)
+    assert (got == e.counts[idx]).all()
+    # keys that never occur count zero
+    absent = e.keys[idx].copy()
+    absent[:, -1] ^= 1
+    present = {brute.words_to_key(r) for r in e.keys}
+    miss = np.array([r for r in absent if brute.words_to_key(r) not in present], dtype=np.uint64).reshape(-1, e.keys.shape[1])
+    assert (oracle.count_keys(rs.seq, rs.offsets, rs.k, miss, threads=2) == 0).all()
+
+
+def test_empty_and_short_inputs():
+    for reads in ([], ["ACG"], ["NNNN", "AC"]):
+        rs = synth.from_strings(reads, 3)
+        e = oracle.count_solid(rs.seq, rs.offsets, 3, 2, True)
+        assert e.keys.shape[0] == 0 and e.n_occ == 0
+        g = oracle.build_graph(e.keys, e.counts, 3)
+        assert g.m == 0 and g.t == 0 and g.F.tolist() == [0] * 6
