@@ -1,0 +1,175 @@
+"""Throughput of SdBG construction (count + solid filter + mercy + SdBG
+arrays) on one MI355X.
+
+One step = sdbg_count_solid + sdbg_build over the whole read set, reads
+already resident in HBM, outputs left in HBM.  Prints one JSON line.
+
+Workload (default): a synthetic metagenome shaped like the paper's soil
+data set (Section 3): 200 random genomes of log-uniform 1-5 Mb with
+log-normal abundances (sigma 1.5), 10M reads of 100 bp at 0.5% substitution
+errors, k=31, d=2, mercy-kmers on.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gmer/s sort+count+SdBG build (frac of HBM roofline); p99 job latency vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str, scale: float):
+    from paper_1409_7208_amd import synth
+
+    if name == "metagenome":
+        rs = synth.metagenome(scale=scale)
+        desc = "metagenome: 200 genomes log-uniform 1-5 Mb, log-normal abundance sigma 1.5, 10M reads x 100 bp, 0.5% err, k=31, d=2, mercy"
+    elif name == "tiny":
+        rs = synth.tiny(scale=scale)
+        desc = "tiny: 50 kb genome, 20k reads x 100 bp, 1% err, k=21, d=2"
+    elif name.startswith("long"):
+        k = int(name[4:] or 21)
+        rs = synth.metagenome_long(scale=scale, k=k)
+        desc = f"metagenome long reads: 20M reads x 150 bp, k={k}, d=2, mercy"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    if scale != 1.0:
+        desc += f" (scale {scale})"
+    return rs, desc
+
+
+def cpu_baseline(rs, n_reads: int):
+    """The oracle as it stands (single thread), on the first n_reads reads."""
+    import oracle
+
+    sub = rs.subset(n_reads)
+    t0 = time.perf_counter()
+    e = oracle.count_solid(sub.seq, sub.offsets, rs.k, rs.d, rs.mercy)
+    oracle.build_graph(e.keys, e.counts, rs.k)
+    dt = time.perf_counter() - t0
+    return {"value": e.n_occ / dt / 1e9, "unit": "Gmer/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sub.n_reads} reads of the workload ({e.n_occ} (k+1)-mer occurrences), count+build, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="metagenome")
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--cpu-reads", type=int, default=25000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--stages", action="store_true", help="print per-kernel breakdown to stderr")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1409_7208_amd import sdbg
+
+    sdbg.load()
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    rs, desc = make_workload(args.workload, args.scale)
+    log(f"generated {rs.n_reads} reads in {time.perf_counter() - t0:.1f} s")
+    seq = torch.from_numpy(rs.seq).to("cuda:0")
+    off = torch.from_numpy(rs.offsets.view(np.int64)).to("cuda:0")
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        e = sdbg.count_solid(seq, off, rs.k, rs.d, rs.mercy, stream=stream)
+        g = sdbg.build(e, stream=stream)
+        res = (e.n_occ, e.n, e.n_mercy, g.m, g.t)
+        g.close()
+        e.close()
+        return res
+
+    for i in range(args.warmup):
+        r = step()
+        log(f"warmup {i}: n_occ={r[0]} edges={r[1]} mercy={r[2]} m={r[3]} t={r[4]}")
+    torch.cuda.synchronize()
+    sdbg.profile_enable(True)
+    sdbg.profile_reset()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        r = step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    sdbg.profile_enable(False)
+    ms = ev0.elapsed_time(ev1) / args.steps
+    n_occ = r[0]
+    value = n_occ / (ms / 1e3) / 1e9
+    log(f"timed {args.steps} steps: {ms:.2f} ms/step (wall {wall / args.steps * 1e3:.2f} ms/step), {value:.2f} Gmer/s")
+
+    recs = sdbg.profile_records()
+    agg: dict[str, list] = {}
+    for name, t, b in recs:
+        a = agg.setdefault(name, [0, 0.0, 0])
+        a[0] += 1
+        a[1] += t
+        a[2] += b
+    total_prof = sum(a[1] for a in agg.values())
+    if args.stages or True:
+        for name, (n, t, b) in sorted(agg.items(), key=lambda x: -x[1][1]):
+            log(f"  {name:14s} launches={n // args.steps:3d}/step  {t / args.steps:8.3f} ms/step  "
+                f"{b / (t * 1e-3) / 1e9 if t > 0 else 0:8.1f} GB/s  ({100 * t / args.steps / ms:5.1f}% of step)")
+        log(f"  profiled kernels cover {100 * total_prof / args.steps / ms:.1f}% of the step")
+    dom = max(agg.items(), key=lambda x: x[1][1])
+    dn, (dcnt, dms, dbytes) = dom
+    achieved = dbytes / (dms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dn,
+                "avg_launch_ms": round(dms / dcnt, 4), "bytes_per_launch": int(dbytes / dcnt)}
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(rs, args.cpu_reads)
+        log(f"  {cpu}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gmer/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": desc, "k": rs.k, "d": rs.d, "mercy": rs.mercy, "reads": rs.n_reads,
+                   "n_occ": int(n_occ), "edges": int(r[1]), "mercy_edges": int(r[2]), "rows": int(r[3]),
+                   "tips": int(r[4])},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * sdbg.h -- succinct de Bruijn graph (SdBG) construction on one MI355X GPU.
+ *
+ * Computes what Section 2 ("Methods") of Li et al., "MEGAHIT: an
+ * ultra-fast single-node solution for large and complex metagenomics
+ * assembly via succinct de Bruijn graph", defines:
+ *
+ *   sdbg_count_solid  every (k+1)-mer of the reads, on both strands, is
+ *                     counted; those seen at least d times are solid; with
+ *                     mercy enabled, the mercy-kmers are added (Section 2,
+ *                     third paragraph).  Output: the edge set E sorted in
+ *                     the SdBG edge order (colex order of the k-prefix, then
+ *                     the last base; Section 2, second paragraph) with each
+ *                     edge's count.
+ *   sdbg_build        the SdBG arrays of an edge set: per-row label with a
+ *                     minus flag (W), the last bit vector, F, the
+ *                     edge-validity bit vector and the 2kt-bit vector of
+ *                     zero-indegree vertex k-mers (Section 2, first
+ *                     paragraph).
+ *
+ * All arithmetic is on integers; results are exact and do not depend on the
+ * memory budget, the prefix length used for block-wise partitioning, or the
+ * launch configuration.
+ *
+ * Encodings
+ *   Bases A, C, G, T have codes 0, 1, 2, 3 (either case is accepted in
+ *   reads).  Any other byte splits a read: no (k+1)-mer spans it.
+ *   w = ceil(2(k+1)/64) 64-bit words per key.  The key of edge
+ *   e = e[0..k] is the base-4 number with digits e[k-1], e[k-2], ..., e[0],
+ *   e[k] (most significant first), stored right-aligned in w words, word 0
+ *   most significant.  Ascending keys are the SdBG edge order.
+ *   Rows of the graph: one per edge of E ("real"), one '$' row per vertex
+ *   with no outgoing edge, and one dummy row per vertex v with no incoming
+ *   edge (source '$' v[0..k-2], label v[k-1]).  Rows are ordered by source
+ *   read from its last symbol to its first, then by label, with
+ *   $ < A < C < G < T.
+ *   W[i]   = label ($=0, A..T = 1..4) | 8 * minus[i]; minus[i] = 1 iff an
+ *            earlier row has the same source[1..k-1] and the same non-$
+ *            label.
+ *   last   bit i = 1 iff row i is the last row of its source vertex.
+ *   valid  bit i = 1 iff row i is a real edge.
+ *   tip    bit i = 1 iff row i is a dummy row (t of them).
+ *   mult[i] = count of a real row, 0 otherwise.
+ *   F[c]   = number of rows whose source ends in a symbol < c, for
+ *            c = $, A, C, G, T; F[5] = m.
+ *   tip_seq: the t dummy rows' vertices v in row order, base j of the r-th
+ *            at bits 2(k*r + j) (LSB first), ceil(2kt/64) words.
+ *   Bit vectors are LSB-first 64-bit words: bit i of the vector is bit
+ *   (i mod 64) of word i/64.
+ *
+ * Memory and ownership
+ *   Inputs are borrowed for the duration of a call.  Output objects are
+ *   allocated by the library, live in device memory (HBM) of the device
+ *   current at the call, and are released with sdbg_free.  The *_to_host
+ *   calls copy them into caller-provided host buffers.  Calls run on
+ *   params->stream (a hipStream_t; NULL = the null stream) and return after
+ *   the stream has completed the call's work.  Distinct calls may run
+ *   concurrently from different host threads on different streams.
+ *
+ * Errors
+ *   Every int-returning call returns SDBG_OK (0) or a negative code;
+ *   sdbg_last_error() then returns a message for the calling thread.
+ */
+#ifndef SDBG_H
+#define SDBG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDBG_OK 0
+#define SDBG_E_INVAL (-1)        /* bad k, d, prefix_len or pointer */
+#define SDBG_E_NOMEM (-2)        /* host allocation failed */
+#define SDBG_E_NOMEM_DEVICE (-3) /* device memory or mem_budget cannot hold one block */
+#define SDBG_E_HIP (-4)          /* HIP runtime error; message copied */
+#define SDBG_E_BUSY (-5)         /* reserved */
+#define SDBG_E_CANCELLED (-6)    /* reserved */
+
+/* Reads: seq[offsets[i] .. offsets[i+1]) is read i; offsets[0] = 0 and the
+ * offsets are non-decreasing.  on_device = 1: both pointers are device
+ * pointers; 0: host pointers (copied to the device by the call). */
+typedef struct sdbg_reads {
+  const uint8_t *seq;
+  const uint64_t *offsets;
+  uint64_t n_reads;
+  uint32_t on_device;
+  uint32_t reserved;
+} sdbg_reads;
+
+/* k in [2, 127]; d >= 1 (solid threshold, 2 in the paper); mercy 0/1;
+ * prefix_len l in [0, 8]: the key space is cut into 4^l blocks by the
+ * length-l colex prefix of the k-mer and consecutive blocks that fit
+ * mem_budget are processed together (Section 2, second paragraph; l = 0
+ * disables the cut); mem_budget: bytes of device memory the key buffers of
+ * one block group may use, 0 = 80% of free device memory. */
+typedef struct sdbg_params {
+  uint32_t k;
+  uint32_t d;
+  uint32_t mercy;
+  uint32_t prefix_len;
+  uint64_t mem_budget;
+  void *stream;
+} sdbg_params;
+
+/* Edge set E: n keys (n*w words, ascending) and counts, in device memory.
+ * n_mercy = edges added by the mercy rule (those with count < d);
+ * n_occ = (k+1)-mer occurrences counted over both strands. */
+typedef struct sdbg_edges {
+  uint32_t k, w;
+  uint64_t n, n_mercy, n_occ;
+  uint64_t *keys;
+  uint32_t *count;
+} sdbg_edges;
+
+/* SdBG arrays in device memory (F on the host). */
+typedef struct sdbg_graph {
+  uint32_t k, w;
+  uint64_t m, t;
+  uint8_t *W;        /* m bytes */
+  uint64_t *last;    /* ceil(m/64) words */
+  uint64_t *valid;   /* ceil(m/64) words */
+  uint64_t *tip;     /* ceil(m/64) words */
+  uint32_t *mult;    /* m */
+  uint64_t F[6];
+  uint64_t *tip_seq; /* tip_words words */
+  uint64_t tip_words;
+} sdbg_graph;
+
+/* Count, filter and mercy (Section 2, third paragraph) -> *out. */
+int sdbg_count_solid(const sdbg_reads *reads, const sdbg_params *params, sdbg_edges **out);
+
+/* SdBG arrays of an edge set (Section 2, first and second paragraphs).
+ * Uses params->stream only; the other fields are ignored. */
+int sdbg_build(const sdbg_edges *edges, const sdbg_params *params, sdbg_graph **out);
+
+/* Wraps host arrays (n*w key words ascending and unique, n counts) into a
+ * library-owned device edge set, e.g. to build a graph from edges computed
+ * elsewhere. */
+int sdbg_edges_from_host(const uint64_t *keys, const uint32_t *count, uint64_t n, uint32_t k, sdbg_edges **out);
+
+/* Copies an edge set to caller buffers of n*w words and n counts. */
+int sdbg_edges_to_host(const sdbg_edges *edges, uint64_t *keys, uint32_t *count);
+
+/* Copies graph arrays to caller buffers sized as in sdbg_graph; any pointer
+ * may be NULL to skip that array. */
+int sdbg_graph_to_host(const sdbg_graph *g, uint8_t *W, uint64_t *last, uint64_t *valid, uint64_t *tip, uint32_t *mult,
+                       uint64_t *tip_seq);
+
+/* Releases any object returned by the library; NULL is a no-op. */
+void sdbg_free(void *obj);
+
+/* Message of the calling thread's last failing call ("" if none). */
+const char *sdbg_last_error(void);
+
+/* Profiling.  While enabled (per host thread), each kernel a call launches
+ * is bracketed by HIP events on the call's stream -- no synchronisation is
+ * added -- and its elapsed time is read when the call completes.
+ * sdbg_profile_get returns record i: the kernel's name (static string), its
+ * duration in ms and the algorithmic bytes it reads and writes (the bytes
+ * its inputs and outputs occupy, each counted once).  Returns SDBG_E_INVAL
+ * if i is out of range. */
+void sdbg_profile_enable(int on);
+void sdbg_profile_reset(void);
+uint32_t sdbg_profile_count(void);
+int sdbg_profile_get(uint32_t i, const char **name, double *ms, uint64_t *bytes);
+
+/* Releases the library's cached device memory (kept between calls to avoid
+ * repeated allocation).  Objects not yet freed stay valid. */
+void sdbg_trim(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDBG_H */

@@ -1,0 +1,267 @@
+// C ABI of the SdBG library (declared in include/sdbg.h).
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_map>
+
+#include "../../include/sdbg.h"
+#include "engine.h"
+
+namespace {
+
+thread_local std::string t_err;
+
+enum ObjKind { kEdges = 1, kGraph = 2 };
+
+// Every object handed out is registered with its kind, so that sdbg_free
+// can release any of them and rejects unknown pointers.
+std::mutex g_reg_mu;
+std::unordered_map<void*, int>& registry() {
+  static std::unordered_map<void*, int> r;
+  return r;
+}
+
+void reg_add(void* p, int kind) {
+  std::lock_guard<std::mutex> lk(g_reg_mu);
+  registry()[p] = kind;
+}
+
+int reg_take(void* p) {
+  std::lock_guard<std::mutex> lk(g_reg_mu);
+  auto it = registry().find(p);
+  if (it == registry().end()) return 0;
+  int k = it->second;
+  registry().erase(it);
+  return k;
+}
+
+int reg_kind(const void* p) {
+  std::lock_guard<std::mutex> lk(g_reg_mu);
+  auto it = registry().find(const_cast<void*>(p));
+  return it == registry().end() ? 0 : it->second;
+}
+
+void pool_free(void* p) {
+  if (p) sdbg::Pool::get().release(p, nullptr, false);
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    t_err.clear();
+    return f();
+  } catch (const sdbg::Error& e) {
+    sdbg::prof_flush();
+    t_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    t_err = "host allocation failed";
+    return SDBG_E_NOMEM;
+  } catch (const std::exception& e) {
+    t_err = e.what();
+    return SDBG_E_HIP;
+  }
+}
+
+void check_k(uint32_t k) { SDBG_CHECK(k >= 2 && k <= 127, SDBG_E_INVAL, "k must be in [2, 127]"); }
+
+}  // namespace
+
+extern "C" {
+
+const char* sdbg_last_error(void) { return t_err.c_str(); }
+
+void sdbg_profile_enable(int on) { sdbg::prof_enable(on != 0); }
+
+void sdbg_profile_reset(void) {
+  sdbg::prof_flush();
+  sdbg::prof_records().clear();
+}
+
+uint32_t sdbg_profile_count(void) { return (uint32_t)sdbg::prof_records().size(); }
+
+int sdbg_profile_get(uint32_t i, const char** name, double* ms, uint64_t* bytes) {
+  auto& r = sdbg::prof_records();
+  if (i >= r.size()) return SDBG_E_INVAL;
+  if (name) *name = r[i].name;
+  if (ms) *ms = r[i].ms;
+  if (bytes) *bytes = r[i].bytes;
+  return SDBG_OK;
+}
+
+void sdbg_trim(void) {
+  try {
+    sdbg::Pool::get().trim();
+  } catch (...) {
+  }
+}
+
+int sdbg_count_solid(const sdbg_reads* reads, const sdbg_params* params, sdbg_edges** out) {
+  return guarded([&]() -> int {
+    SDBG_CHECK(reads && params && out, SDBG_E_INVAL, "null argument");
+    *out = nullptr;
+    check_k(params->k);
+    SDBG_CHECK(params->d >= 1, SDBG_E_INVAL, "d must be >= 1");
+    SDBG_CHECK(params->prefix_len <= 8, SDBG_E_INVAL, "prefix_len must be in [0, 8]");
+    SDBG_CHECK(reads->n_reads == 0 || (reads->offsets != nullptr), SDBG_E_INVAL, "null offsets");
+    sdbg::Ctx c(params->stream);
+    sdbg::DevReads R{};
+    R.n_reads = reads->n_reads;
+    sdbg::DBuf<uint8_t> seq_d;
+    sdbg::DBuf<uint64_t> off_d;
+    if (reads->n_reads == 0) {
+      off_d = c.buf<uint64_t>(1);
+      uint64_t z = 0;
+      c.h2d(off_d.get(), &z, 1);
+      R.offsets = off_d.get();
+      R.seq = nullptr;
+      R.n_bases = 0;
+    } else if (reads->on_device) {
+      R.offsets = reads->offsets;
+      R.seq = reads->seq;
+      uint64_t first = c.d2h_one(reads->offsets);
+      R.n_bases = c.d2h_one(reads->offsets + reads->n_reads);
+      SDBG_CHECK(first == 0, SDBG_E_INVAL, "offsets[0] must be 0");
+      SDBG_CHECK(R.n_bases == 0 || reads->seq, SDBG_E_INVAL, "null seq");
+    } else {
+      const uint64_t* o = reads->offsets;
+      SDBG_CHECK(o[0] == 0, SDBG_E_INVAL, "offsets[0] must be 0");
+      for (uint64_t i = 0; i < reads->n_reads; ++i)
+        SDBG_CHECK(o[i + 1] >= o[i], SDBG_E_INVAL, "offsets must be non-decreasing");
+      R.n_bases = o[reads->n_reads];
+      SDBG_CHECK(R.n_bases == 0 || reads->seq, SDBG_E_INVAL, "null seq");
+      seq_d = c.buf<uint8_t>(R.n_bases + 16);
+      off_d = c.buf<uint64_t>(reads->n_reads + 1);
+      c.h2d(seq_d.get(), reads->seq, R.n_bases);
+      c.h2d(off_d.get(), o, reads->n_reads + 1);
+      R.seq = seq_d.get();
+      R.offsets = off_d.get();
+    }
+    sdbg::CountParams P{(int)params->k, params->d, params->mercy != 0, (int)params->prefix_len, params->mem_budget};
+    sdbg::EdgesOut eo;
+    sdbg::count_solid(R, P, c, &eo);
+    c.sync();
+    sdbg::prof_flush();
+    sdbg_edges* e = new sdbg_edges();
+    e->k = params->k;
+    e->w = (uint32_t)sdbg::key_words((int)params->k);
+    e->n = eo.n;
+    e->n_mercy = eo.n_mercy;
+    e->n_occ = eo.n_occ;
+    e->keys = eo.keys;
+    e->count = eo.count;
+    reg_add(e, kEdges);
+    *out = e;
+    return SDBG_OK;
+  });
+}
+
+int sdbg_build(const sdbg_edges* edges, const sdbg_params* params, sdbg_graph** out) {
+  return guarded([&]() -> int {
+    SDBG_CHECK(edges && out, SDBG_E_INVAL, "null argument");
+    *out = nullptr;
+    SDBG_CHECK(reg_kind(edges) == kEdges, SDBG_E_INVAL, "not an edge set returned by this library");
+    check_k(edges->k);
+    sdbg::Ctx c(params ? params->stream : nullptr);
+    sdbg::GraphOut go;
+    sdbg::build_graph(edges->keys, edges->count, edges->n, (int)edges->k, c, &go);
+    c.sync();
+    sdbg::prof_flush();
+    sdbg_graph* g = new sdbg_graph();
+    g->k = edges->k;
+    g->w = edges->w;
+    g->m = go.m;
+    g->t = go.t;
+    g->W = go.W;
+    g->last = go.last;
+    g->valid = go.valid;
+    g->tip = go.tip;
+    g->mult = go.mult;
+    std::memcpy(g->F, go.F, sizeof(g->F));
+    g->tip_seq = go.tip_seq;
+    g->tip_words = go.tip_words;
+    reg_add(g, kGraph);
+    *out = g;
+    return SDBG_OK;
+  });
+}
+
+int sdbg_edges_from_host(const uint64_t* keys, const uint32_t* count, uint64_t n, uint32_t k, sdbg_edges** out) {
+  return guarded([&]() -> int {
+    SDBG_CHECK(out && (n == 0 || (keys && count)), SDBG_E_INVAL, "null argument");
+    *out = nullptr;
+    check_k(k);
+    const uint32_t w = (uint32_t)sdbg::key_words((int)k);
+    sdbg::Ctx c(nullptr);
+    sdbg::DBuf<uint64_t> kd = c.buf<uint64_t>(n * w);
+    sdbg::DBuf<uint32_t> cd = c.buf<uint32_t>(n);
+    c.h2d(kd.get(), keys, n * w);
+    c.h2d(cd.get(), count, n);
+    sdbg_edges* e = new sdbg_edges();
+    e->k = k;
+    e->w = w;
+    e->n = n;
+    e->n_mercy = 0;
+    e->n_occ = 0;
+    e->keys = kd.release_ownership();
+    e->count = cd.release_ownership();
+    reg_add(e, kEdges);
+    *out = e;
+    return SDBG_OK;
+  });
+}
+
+int sdbg_edges_to_host(const sdbg_edges* e, uint64_t* keys, uint32_t* count) {
+  return guarded([&]() -> int {
+    SDBG_CHECK(e && reg_kind(e) == kEdges, SDBG_E_INVAL, "not an edge set returned by this library");
+    sdbg::Ctx c(nullptr);
+    if (keys) c.d2h(keys, e->keys, e->n * e->w);
+    if (count) c.d2h(count, e->count, e->n);
+    return SDBG_OK;
+  });
+}
+
+int sdbg_graph_to_host(const sdbg_graph* g, uint8_t* W, uint64_t* last, uint64_t* valid, uint64_t* tip, uint32_t* mult,
+                       uint64_t* tip_seq) {
+  return guarded([&]() -> int {
+    SDBG_CHECK(g && reg_kind(g) == kGraph, SDBG_E_INVAL, "not a graph returned by this library");
+    sdbg::Ctx c(nullptr);
+    const uint64_t words = (g->m + 63) / 64;
+    if (W) c.d2h(W, g->W, g->m);
+    if (last) c.d2h(last, g->last, words);
+    if (valid) c.d2h(valid, g->valid, words);
+    if (tip) c.d2h(tip, g->tip, words);
+    if (mult) c.d2h(mult, g->mult, g->m);
+    if (tip_seq) c.d2h(tip_seq, g->tip_seq, g->tip_words);
+    return SDBG_OK;
+  });
+}
+
+void sdbg_free(void* obj) {
+  if (!obj) return;
+  int kind = reg_take(obj);
+  try {
+    if (kind == kEdges) {
+      sdbg_edges* e = static_cast<sdbg_edges*>(obj);
+      pool_free(e->keys);
+      pool_free(e->count);
+      delete e;
+    } else if (kind == kGraph) {
+      sdbg_graph* g = static_cast<sdbg_graph*>(obj);
+      pool_free(g->W);
+      pool_free(g->last);
+      pool_free(g->valid);
+      pool_free(g->tip);
+      pool_free(g->mult);
+      pool_free(g->tip_seq);
+      delete g;
+    }
+  } catch (...) {
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,405 @@
+// SdBG arrays of a sorted edge set (Section 2, first paragraph: edge labels
+// with minus flags, the last bit vector, F, the edge-validity bit vector
+// and the 2kt-bit vector of zero-indegree vertex k-mers).
+//
+// Rows are the real edges E (already in key order), one '$' row per vertex
+// with no outgoing edge (list Zout) and one dummy row per vertex with no
+// incoming edge (list Zin).  Each list is produced in row order, and every
+// row finds its final index as its index in its own list plus the number of
+// rows of the two other lists that sort before it (directory lookups), so
+// the merge is one scatter.  All row-order comparisons reduce to integer
+// comparisons of edge keys and vertex packings:
+//   real row of edge x, source v = x>>2 (a k-mer, forward packing P(v)):
+//       after '$' rows whose vertex z has P(z) < P(v), after dummy rows with
+//       v'[0..k-2] <= v[1..k-1];
+//   '$' row of z: after real rows with key < P(z)*4, after dummy rows with
+//       v'[0..k-2] <= z[1..k-1];
+//   dummy row of v': after real rows with key < v'[0..k-2]*16, after '$'
+//       rows with P(z) < v'[0..k-2]*4.
+// A dummy row is stored by its "dummy key" v'[0..k-2]*4 + v'[k-1]; dummy
+// rows sort by that key.
+
+#include "engine.h"
+#include "kernels.h"
+#include "prims.h"
+
+namespace sdbg {
+
+namespace {
+
+inline unsigned grid1(uint64_t n) {
+  uint64_t g = ceil_div(n, SDBG_BLOCK);
+  SDBG_CHECK(g < (1ull << 31), -1, "grid too large");
+  return (unsigned)(g ? g : 1);
+}
+
+// Per edge: bit0 minus, bit1 '$' row for its target (target has no
+// out-edge, and this is the first edge into it), bit2 dummy row for its
+// source (first edge of the source, source has no in-edge), bit3 last.
+template <int W>
+__global__ void k_row_flags(SortedView E, int k, uint8_t* __restrict__ fl) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= E.n) return;
+  const Key<W> x = key_load<W>(E.keys + i * W);
+  const uint64_t c = x.w[W - 1] & 3;
+  const Key<W> grp = key_shr<W>(x, 4), src = key_shr<W>(x, 2);
+  bool minus = false;
+  for (uint64_t j = i; j-- > 0;) {
+    Key<W> y = key_load<W>(E.keys + j * W);
+    if (!key_eq<W>(key_shr<W>(y, 4), grp)) break;
+    if ((y.w[W - 1] & 3) == c) {
+      minus = true;
+      break;
+    }
+  }
+  const bool first = i == 0 || !key_eq<W>(key_shr<W>(key_load<W>(E.keys + (i - 1) * W), 2), src);
+  const bool last = i + 1 == E.n || !key_eq<W>(key_shr<W>(key_load<W>(E.keys + (i + 1) * W), 2), src);
+  const bool zout = !minus && !sv_has_source<W>(E, edge_target<W>(x, k));
+  const bool zin = first && !sv_has_target<W>(E, src, k);
+  fl[i] = (uint8_t)((minus ? 1 : 0) | (zout ? 2 : 0) | (zin ? 4 : 0) | (last ? 8 : 0));
+}
+
+// Split of the flagged edges into 4 classes, keeping edge order within a
+// class.  mode 0: '$' rows, class = label, value = target vertex P(z);
+// mode 1: dummy rows, class = last base of the source, value = dummy key.
+constexpr int SPLIT_IPT = 8;
+constexpr int SPLIT_TILE = SDBG_BLOCK * SPLIT_IPT;
+
+template <int W>
+DEV bool split_item(const SortedView& E, const uint8_t* fl, int mode, int k, uint64_t i, uint32_t* cls, Key<W>* val) {
+  if (!(fl[i] & (mode ? 4 : 2))) return false;
+  Key<W> x = key_load<W>(E.keys + i * W);
+  if (mode == 0) {
+    *cls = (uint32_t)(x.w[W - 1] & 3);
+    *val = edge_target<W>(x, k);
+  } else {
+    Key<W> P = key_shr<W>(x, 2);
+    uint64_t top = key_bits<W>(P, 2 * k - 2, 2);
+    *cls = (uint32_t)top;
+    *val = key_or_low<W>(key_shl<W>(key_lowbits<W>(P, 2 * k - 2), 2), top);
+  }
+  return true;
+}
+
+template <int W>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_split_count(SortedView E, const uint8_t* __restrict__ fl, int mode,
+                                                            int k, uint64_t ntiles, uint64_t* __restrict__ tc) {
+  __shared__ uint32_t h[4];
+  if (threadIdx.x < 4) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t base = blockIdx.x * (uint64_t)SPLIT_TILE + threadIdx.x * SPLIT_IPT;
+  for (int q = 0; q < SPLIT_IPT; ++q) {
+    uint64_t i = base + q;
+    uint32_t cl;
+    Key<W> v;
+    if (i < E.n && split_item<W>(E, fl, mode, k, i, &cl, &v)) atomicAdd(&h[cl], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) tc[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+template <int W>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_split_write(SortedView E, const uint8_t* __restrict__ fl, int mode,
+                                                            int k, uint64_t ntiles, const uint64_t* __restrict__ tcs,
+                                                            uint64_t* __restrict__ out) {
+  __shared__ uint64_t sc[SDBG_WAVES + 1];
+  const uint64_t base = blockIdx.x * (uint64_t)SPLIT_TILE + threadIdx.x * SPLIT_IPT;
+  uint64_t packed = 0;  // 4 x 16-bit per-class counts of this thread
+  for (int q = 0; q < SPLIT_IPT; ++q) {
+    uint64_t i = base + q;
+    uint32_t cl;
+    Key<W> v;
+    if (i < E.n && split_item<W>(E, fl, mode, k, i, &cl, &v)) packed += 1ull << (16 * cl);
+  }
+  uint64_t tot;
+  uint64_t ex = block_excl_scan<uint64_t>(packed, sc, &tot);
+  uint64_t pos[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) pos[c] = tcs[c * ntiles + blockIdx.x] + ((ex >> (16 * c)) & 0xFFFF);
+  for (int q = 0; q < SPLIT_IPT; ++q) {
+    uint64_t i = base + q;
+    uint32_t cl;
+    Key<W> v;
+    if (i < E.n && split_item<W>(E, fl, mode, k, i, &cl, &v)) {
+      uint64_t p = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c == (int)cl) p = pos[c]++;
+      key_store<W>(out + p * W, v);
+    }
+  }
+}
+
+template <int W>
+DEV uint64_t lower_in(const uint64_t* keys, uint64_t lo, uint64_t hi, const Key<W>& q) {
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (key_less<W>(key_load<W>(keys + mid * W), q))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// The dummy rows arrive as 4 runs (by the source's last base), each sorted
+// by dummy key; merge them by rank.
+template <int W>
+__global__ void k_merge4(const uint64_t* __restrict__ in, uint64_t t, const uint64_t* __restrict__ run_start,
+                         uint64_t* __restrict__ out) {
+  uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (j >= t) return;
+  int c = 0;
+  while (c < 3 && j >= run_start[c + 1]) ++c;
+  Key<W> x = key_load<W>(in + j * W);
+  uint64_t r = j - run_start[c];
+  for (int o = 0; o < 4; ++o)
+    if (o != c) r += lower_in<W>(in, run_start[o], run_start[o + 1], x) - run_start[o];
+  key_store<W>(out + r * W, x);
+}
+
+// Row placement.  rf: bit0 last, bit1 valid, bit2 tip.
+template <int W>
+__global__ void k_place_real(SortedView E, const uint32_t* __restrict__ cnt, const uint8_t* __restrict__ fl,
+                             SortedView Zo, SortedView Zi, uint8_t* __restrict__ Wb, uint32_t* __restrict__ mult,
+                             uint8_t* __restrict__ rf) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= E.n) return;
+  const Key<W> x = key_load<W>(E.keys + i * W);
+  const Key<W> hi3 = key_or_low<W>(key_shl<W>(key_shr<W>(x, 4), 2), 3);
+  const uint64_t p = i + sv_lower<W>(Zo, key_shr<W>(x, 2)) + sv_upper<W>(Zi, hi3);
+  const uint8_t f = fl[i];
+  Wb[p] = (uint8_t)(((x.w[W - 1] & 3) + 1) | ((f & 1) ? 8 : 0));
+  mult[p] = cnt[i];
+  rf[p] = (uint8_t)(((f & 8) ? 1 : 0) | 2);
+}
+
+template <int W>
+__global__ void k_place_zout(SortedView E, SortedView Zo, SortedView Zi, uint8_t* __restrict__ Wb,
+                             uint32_t* __restrict__ mult, uint8_t* __restrict__ rf) {
+  uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (j >= Zo.n) return;
+  const Key<W> z = key_load<W>(Zo.keys + j * W);
+  const Key<W> hi3 = key_or_low<W>(key_shl<W>(key_shr<W>(z, 2), 2), 3);
+  const uint64_t p = j + sv_lower<W>(E, key_shl<W>(z, 2)) + sv_upper<W>(Zi, hi3);
+  Wb[p] = 0;
+  mult[p] = 0;
+  rf[p] = 1;
+}
+
+template <int W>
+__global__ void k_place_zin(SortedView E, SortedView Zo, SortedView Zi, uint8_t* __restrict__ Wb,
+                            uint32_t* __restrict__ mult, uint8_t* __restrict__ rf) {
+  uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (j >= Zi.n) return;
+  const Key<W> y = key_load<W>(Zi.keys + j * W);
+  const Key<W> hv = key_shr<W>(y, 2);
+  const uint64_t p = j + sv_lower<W>(E, key_shl<W>(hv, 4)) + sv_lower<W>(Zo, key_shl<W>(hv, 2));
+  const bool last = j + 1 == Zi.n || !key_eq<W>(key_shr<W>(key_load<W>(Zi.keys + (j + 1) * W), 2), hv);
+  Wb[p] = (uint8_t)((y.w[W - 1] & 3) + 1);
+  mult[p] = 0;
+  rf[p] = (uint8_t)(4 | (last ? 1 : 0));
+}
+
+// One wavefront ballot over 64 consecutive rows is one word of each vector.
+__global__ __launch_bounds__(SDBG_BLOCK) void k_pack_bits(const uint8_t* __restrict__ rf, uint64_t m,
+                                                          uint64_t* __restrict__ last, uint64_t* __restrict__ valid,
+                                                          uint64_t* __restrict__ tip) {
+  uint64_t i = blockIdx.x * (uint64_t)SDBG_BLOCK + threadIdx.x;
+  uint8_t f = i < m ? rf[i] : 0;
+  uint64_t bl = __ballot(f & 1), bv = __ballot(f & 2), bt = __ballot(f & 4);
+  if ((threadIdx.x & 63) == 0 && i < m) {
+    last[i >> 6] = bl;
+    valid[i >> 6] = bv;
+    tip[i >> 6] = bt;
+  }
+}
+
+// F: rows whose source ends in A, C, G (the last symbol of a source is the
+// top base of the key, of P(z), and of the dummy key).
+template <int W>
+__global__ void k_F(SortedView E, SortedView Zo, SortedView Zi, int k, uint64_t* __restrict__ F) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint64_t m = E.n + Zo.n + Zi.n;
+  F[0] = 0;
+  F[1] = 0;
+  for (int s = 1; s < 4; ++s) {
+    Key<W> one = key_zero<W>();
+    one.w[W - 1] = (uint64_t)s;
+    F[s + 1] = sv_lower<W>(E, key_shl<W>(one, 2 * k)) + sv_lower<W>(Zo, key_shl<W>(one, 2 * k - 2)) +
+               sv_lower<W>(Zi, key_shl<W>(one, 2 * k - 2));
+  }
+  F[5] = m;
+}
+
+// tip_seq word w gathers the 2k-bit packings of the dummy vertices that
+// overlap bits [64w, 64w+64).
+template <int W>
+__global__ void k_tipseq(const uint64_t* __restrict__ zi, uint64_t t, int k, uint64_t words, uint64_t* __restrict__ out) {
+  uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (w >= words) return;
+  const uint64_t fb = 2ull * k, b0 = 64 * w, b1 = b0 + 64;
+  uint64_t r0 = b0 / fb, r1 = (b1 - 1) / fb;
+  if (r1 >= t) r1 = t - 1;
+  uint64_t acc = 0;
+  for (uint64_t r = r0; r <= r1; ++r) {
+    const Key<W> y = key_load<W>(zi + r * W);
+    const Key<W> P = key_or2<W>(key_shr<W>(y, 2), 2 * k - 2, y.w[W - 1] & 3);
+    const uint64_t fs = fb * r;
+    const uint64_t lo = fs > b0 ? fs : b0, hi = (fs + fb) < b1 ? (fs + fb) : b1;
+    acc |= key_bits64<W>(P, (int)(lo - fs), (int)(hi - lo)) << (lo - b0);
+  }
+  out[w] = acc;
+}
+
+template <int W>
+__global__ void k_check_sorted_b(const uint64_t* __restrict__ keys, uint64_t n, int kbits, uint32_t* flags) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Key<W> x = key_load<W>(keys + i * W);
+  if (!key_eq<W>(key_lowbits<W>(x, kbits), x)) atomicOr(flags, 2u);
+  if (i > 0 && !key_less<W>(key_load<W>(keys + (i - 1) * W), x)) atomicOr(flags, 1u);
+}
+
+template <int W>
+__global__ void k_dir_b(const uint64_t* __restrict__ keys, uint64_t n, int kbits, int db, uint64_t* __restrict__ dir) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i > n) return;
+  uint64_t b = i < n ? key_bits<W>(key_load<W>(keys + i * W), kbits - db, db) : (1ull << db);
+  uint64_t from = i == 0 ? 0 : (uint64_t)key_bits<W>(key_load<W>(keys + (i - 1) * W), kbits - db, db) + 1;
+  for (uint64_t x = from; x <= b; ++x) dir[x] = i;
+}
+
+template <int W>
+struct Builder {
+  Ctx& c;
+  explicit Builder(Ctx& c_) : c(c_) {}
+
+  SortedView view(const uint64_t* keys, uint64_t n, int kbits, DBuf<uint64_t>& dir) {
+    int db = 1;
+    while (db < 24 && db < kbits && (n >> (db + 3)) > 0) ++db;
+    dir = c.buf<uint64_t>((1ull << db) + 1);
+    k_dir_b<W><<<grid1(n + 1), SDBG_BLOCK, 0, c.s>>>(keys, n, kbits, db, dir.get());
+    c.check_launch("dir");
+    return SortedView{keys, dir.get(), n, kbits, db};
+  }
+
+  // Compacts the flagged edges of one kind into `out` (row order within
+  // each class); returns the 5 class boundaries.
+  void split(const SortedView& E, const uint8_t* fl, int mode, int k, DBuf<uint64_t>& out, uint64_t bounds[5]) {
+    const uint64_t ntiles = ceil_div(E.n, SPLIT_TILE);
+    DBuf<uint64_t> tc = c.buf<uint64_t>(4 * ntiles + 1), tot = c.buf<uint64_t>(1);
+    {
+      Stage st_(c, "split_count", E.n);
+      k_split_count<W><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(E, fl, mode, k, ntiles, tc.get());
+      c.check_launch("split_count");
+    }
+    scan_excl<uint64_t, uint64_t>(tc.get(), tc.get(), 4 * ntiles, tc.get() + 4 * ntiles, c);
+    uint64_t h[5];
+    for (int q = 0; q < 4; ++q) h[q] = c.d2h_one(tc.get() + q * ntiles);
+    h[4] = c.d2h_one(tc.get() + 4 * ntiles);
+    for (int q = 0; q < 5; ++q) bounds[q] = h[q];
+    out = c.buf<uint64_t>(h[4] * W);
+    {
+      Stage st_(c, "split_write", E.n + h[4] * 16 * W);
+      k_split_write<W><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(E, fl, mode, k, ntiles, tc.get(), out.get());
+      c.check_launch("split_write");
+    }
+  }
+
+  void run(const uint64_t* keys, const uint32_t* count, uint64_t n, int k, GraphOut* g) {
+    const int kb = 2 * (k + 1);
+    *g = GraphOut{};
+    if (n == 0) return;
+    {
+      DBuf<uint32_t> flags = c.buf<uint32_t>(1);
+      fill<uint32_t>(flags.get(), 1, 0, c);
+      k_check_sorted_b<W><<<grid1(n), SDBG_BLOCK, 0, c.s>>>(keys, n, kb, flags.get());
+      c.check_launch("check_sorted");
+      uint32_t f = c.d2h_one(flags.get());
+      SDBG_CHECK(!(f & 2), -1, "edge key has bits above 2(k+1)");
+      SDBG_CHECK(!(f & 1), -1, "edge keys are not strictly ascending");
+    }
+    DBuf<uint64_t> edir;
+    SortedView E = view(keys, n, kb, edir);
+    DBuf<uint8_t> fl = c.buf<uint8_t>(n);
+    {
+      Stage st_(c, "row_flags", n * (8 * W + 1));
+      k_row_flags<W><<<grid1(n), SDBG_BLOCK, 0, c.s>>>(E, k, fl.get());
+      c.check_launch("row_flags");
+    }
+    DBuf<uint64_t> zo, zi_runs, zi;
+    uint64_t bo[5], bi[5];
+    split(E, fl.get(), 0, k, zo, bo);
+    split(E, fl.get(), 1, k, zi_runs, bi);
+    const uint64_t nzo = bo[4], t = bi[4];
+    zi = c.buf<uint64_t>(t * W);
+    if (t) {
+      DBuf<uint64_t> rs = c.buf<uint64_t>(5);
+      c.h2d(rs.get(), bi, 5);
+      k_merge4<W><<<grid1(t), SDBG_BLOCK, 0, c.s>>>(zi_runs.get(), t, rs.get(), zi.get());
+      c.check_launch("merge4");
+      c.sync();
+    }
+    zi_runs.free();
+    DBuf<uint64_t> odir, idir;
+    SortedView Zo = view(zo.get(), nzo, 2 * k, odir);
+    SortedView Zi = view(zi.get(), t, 2 * k, idir);
+    const uint64_t m = n + nzo + t;
+    const uint64_t words = ceil_div(m, 64);
+    DBuf<uint8_t> Wb = c.buf<uint8_t>(m), rf = c.buf<uint8_t>(m);
+    DBuf<uint32_t> mult = c.buf<uint32_t>(m);
+    {
+      Stage st_(c, "place_real", n * (8 * W + 4 + 1) + n * 6);
+      k_place_real<W><<<grid1(n), SDBG_BLOCK, 0, c.s>>>(E, count, fl.get(), Zo, Zi, Wb.get(), mult.get(), rf.get());
+      c.check_launch("place_real");
+    }
+    if (nzo) {
+      k_place_zout<W><<<grid1(nzo), SDBG_BLOCK, 0, c.s>>>(E, Zo, Zi, Wb.get(), mult.get(), rf.get());
+      c.check_launch("place_zout");
+    }
+    if (t) {
+      k_place_zin<W><<<grid1(t), SDBG_BLOCK, 0, c.s>>>(E, Zo, Zi, Wb.get(), mult.get(), rf.get());
+      c.check_launch("place_zin");
+    }
+    DBuf<uint64_t> last = c.buf<uint64_t>(words), valid = c.buf<uint64_t>(words), tip = c.buf<uint64_t>(words);
+    {
+      Stage st_(c, "pack_bits", m + 3 * words * 8);
+      k_pack_bits<<<grid1(m), SDBG_BLOCK, 0, c.s>>>(rf.get(), m, last.get(), valid.get(), tip.get());
+      c.check_launch("pack_bits");
+    }
+    DBuf<uint64_t> F = c.buf<uint64_t>(6);
+    k_F<W><<<1, 64, 0, c.s>>>(E, Zo, Zi, k, F.get());
+    c.check_launch("F");
+    const uint64_t tw = ceil_div(2ull * k * t, 64);
+    DBuf<uint64_t> ts = c.buf<uint64_t>(tw);
+    if (tw) {
+      k_tipseq<W><<<grid1(tw), SDBG_BLOCK, 0, c.s>>>(zi.get(), t, k, tw, ts.get());
+      c.check_launch("tipseq");
+    }
+    c.d2h(g->F, F.get(), 6);
+    g->m = m;
+    g->t = t;
+    g->tip_words = tw;
+    g->W = Wb.release_ownership();
+    g->mult = mult.release_ownership();
+    g->last = last.release_ownership();
+    g->valid = valid.release_ownership();
+    g->tip = tip.release_ownership();
+    g->tip_seq = ts.release_ownership();
+  }
+};
+
+}  // namespace
+
+void build_graph(const uint64_t* keys, const uint32_t* count, uint64_t n, int k, Ctx& c, GraphOut* out) {
+  switch (key_words(k)) {
+    case 1: Builder<1>(c).run(keys, count, n, k, out); break;
+    case 2: Builder<2>(c).run(keys, count, n, k, out); break;
+    case 3: Builder<3>(c).run(keys, count, n, k, out); break;
+    case 4: Builder<4>(c).run(keys, count, n, k, out); break;
+    default: throw Error(-1, "k out of range");
+  }
+}
+
+}  // namespace sdbg

@@ -1,0 +1,1160 @@
+// Counting path (Section 2, third paragraph): reads -> 2-bit packing ->
+// both-strand (k+1)-mer keys -> MSD radix partition in HBM -> per-leaf LDS
+// sort + run-length count + solid filter -> mercy-kmers -> sorted edge set.
+//
+// Keys are the colex edge keys (Section 2, second paragraph): digits
+// e[k-1], ..., e[0], e[k] of the (k+1)-mer e.  The partition cuts the key
+// space by its most significant bits; the first cut is taken straight from
+// the packed reads (keys are computed twice, once to histogram and once to
+// scatter, instead of being written and re-read), the later cuts are
+// segmented passes over the key buffers, and leaves small enough for LDS
+// are sorted and counted there.  Consecutive blocks of the top-bit prefix
+// space are grouped so that a group's key buffers fit the memory budget
+// (the block-wise strategy of Section 2, second paragraph).
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "engine.h"
+#include "kernels.h"
+#include "prims.h"
+
+namespace sdbg {
+
+// ------------------------------------------------------------ packing
+// Thread t packs bases [64t, 64t+64): two words of 2-bit codes (base j at
+// bits 2(j mod 32) of word j/32) and one word of "not ACGT" flags.
+__global__ __launch_bounds__(SDBG_BLOCK) void k_pack(const uint8_t* __restrict__ seq, uint64_t nb,
+                                                     uint64_t* __restrict__ packed, uint64_t* __restrict__ bad,
+                                                     uint32_t* __restrict__ any_bad) {
+  uint64_t t = blockIdx.x * (uint64_t)SDBG_BLOCK + threadIdx.x;
+  uint64_t base = t * 64;
+  if (base >= nb) return;
+  uint64_t p0 = 0, p1 = 0, bw = 0;
+  if (base + 64 <= nb && ((reinterpret_cast<uintptr_t>(seq + base)) & 15) == 0) {
+    const uint4* v = reinterpret_cast<const uint4*>(seq + base);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint4 x = v[q];
+      uint32_t wd[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = q * 16 + e * 4 + b;
+          bool ok;
+          uint64_t code = base_code((wd[e] >> (8 * b)) & 0xFFu, &ok);
+          if (i < 32)
+            p0 |= code << (2 * i);
+          else
+            p1 |= code << (2 * (i - 32));
+          bw |= (uint64_t)(!ok) << i;
+        }
+      }
+    }
+  } else {
+    for (int i = 0; i < 64 && base + i < nb; ++i) {
+      bool ok;
+      uint64_t code = base_code(seq[base + i], &ok);
+      if (i < 32)
+        p0 |= code << (2 * i);
+      else
+        p1 |= code << (2 * (i - 32));
+      bw |= (uint64_t)(!ok) << i;
+    }
+  }
+  packed[2 * t] = p0;
+  packed[2 * t + 1] = p1;
+  bad[t] = bw;
+  if (bw) atomicOr(any_bad, 1u);
+}
+
+// Windows (k+1-mer start positions) per read: max(0, len - k).
+__global__ void k_nwin(const uint64_t* __restrict__ offsets, uint64_t n_reads, int k, uint64_t* __restrict__ nwin) {
+  uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (r >= n_reads) return;
+  uint64_t a = offsets[r], b = offsets[r + 1];
+  uint64_t len = b > a ? b - a : 0;
+  nwin[r] = len > (uint64_t)k ? len - k : 0;
+}
+
+// ------------------------------------------------------------ extraction
+struct ExArgs {
+  const uint64_t* packed;
+  const uint64_t* bad;
+  const uint64_t* woff;     // n_reads + 1 window offsets
+  const uint64_t* offsets;  // read offsets
+  uint64_t n_reads, NW;
+  int any_bad;
+  int k, kb;
+  int pb;             // prefix bits used by the group filter
+  uint32_t glo, ghi;  // keep keys whose top pb bits are in [glo, ghi)
+  int dlo, dbits;     // partition digit = bits [dlo, dlo + dbits)
+};
+
+DEV uint64_t find_read(const uint64_t* __restrict__ woff, uint64_t n_reads, uint64_t g) {
+  uint64_t lo = 0, hi = n_reads;  // woff[lo] <= g < woff[hi]
+  while (hi - lo > 1) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (woff[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+struct WinIter {
+  uint64_t r, i, nw, rstart;
+  DEV void init(const ExArgs& a, uint64_t g) {
+    r = find_read(a.woff, a.n_reads, g);
+    rstart = a.offsets[r];
+    i = g - a.woff[r];
+    nw = a.woff[r + 1] - a.woff[r];
+  }
+  DEV uint64_t pos() const { return rstart + i; }
+  DEV void next(const ExArgs& a) {
+    ++i;
+    while (i >= nw && r + 1 < a.n_reads) {
+      ++r;
+      i = 0;
+      rstart = a.offsets[r];
+      nw = a.woff[r + 1] - a.woff[r];
+    }
+  }
+};
+
+// Are bits [j, j+len) of the flag stream all zero?  len <= 128.
+DEV bool window_clean(const uint64_t* __restrict__ bad, uint64_t j, int len) {
+  uint64_t q = j >> 6;
+  int s = (int)(j & 63);
+  uint64_t a = bad[q] >> s;
+  int got = 64 - s;
+  if (len <= got) return (len >= 64 ? a : (a & ((1ull << len) - 1))) == 0;
+  if (a) return false;
+  int need = len - got;
+  uint64_t b = bad[q + 1];
+  if (need <= 64) return (need >= 64 ? b : (b & ((1ull << need) - 1))) == 0;
+  if (b) return false;
+  need -= 64;
+  return (bad[q + 2] & ((1ull << need) - 1)) == 0;
+}
+
+// Keys of window at stream position j: forward strand and reverse complement.
+template <int W>
+DEV void window_keys(const ExArgs& a, uint64_t j, Key<W>* kf, Key<W>* kr) {
+  Key<W> F = stream_bits<W>(a.packed, 2 * j, a.kb);
+  *kf = key_from_fwd<W>(F, a.kb);
+  *kr = key_from_fwd<W>(revcomp_fwd<W>(F, a.kb), a.kb);
+}
+
+template <int W>
+DEV bool ex_pass(const ExArgs& a, const Key<W>& key) {
+  uint32_t p = key_bits<W>(key, a.kb - a.pb, a.pb);
+  return p >= a.glo && p < a.ghi;
+}
+
+// Histogram of the partition digit per tile of 256*IPT windows, written
+// digit-major: tab[d * ntiles + tile].  Also counts produced occurrences.
+template <int W, int IPT>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_ex_hist(ExArgs a, uint32_t* __restrict__ tab, uint64_t ntiles,
+                                                        unsigned long long* __restrict__ occ) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t produced = 0;
+  const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
+  if (g0 < a.NW) {
+    WinIter it;
+    it.init(a, g0);
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      if (g0 + q < a.NW) {
+        uint64_t j = it.pos();
+        if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
+          Key<W> kf, kr;
+          window_keys<W>(a, j, &kf, &kr);
+          produced += 2;
+          if (ex_pass<W>(a, kf)) atomicAdd(&h[key_bits<W>(kf, a.dlo, a.dbits)], 1u);
+          if (ex_pass<W>(a, kr)) atomicAdd(&h[key_bits<W>(kr, a.dlo, a.dbits)], 1u);
+        }
+        it.next(a);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < (1u << a.dbits)) tab[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+  if (occ) {
+    uint32_t s = wave_sum(produced);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(occ, (unsigned long long)s);
+  }
+}
+
+// Scatter: recompute the tile's keys, counting-sort them by digit in LDS and
+// write each digit's run to its place (tab holds the exclusive scan of the
+// digit-major histogram, i.e. each (digit, tile) run's first position).
+template <int W, int IPT>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_ex_scatter(ExArgs a, const uint32_t* __restrict__ tab, uint64_t ntiles,
+                                                           uint64_t* __restrict__ out) {
+  constexpr int NK = 2 * IPT;
+  __shared__ uint64_t lk[NK * SDBG_BLOCK * W];
+  __shared__ uint32_t cnt[256], lst[256], gb[256];
+  __shared__ uint32_t sc[SDBG_WAVES + 1];
+  const uint32_t nbins = 1u << a.dbits;
+  cnt[threadIdx.x] = 0;
+  gb[threadIdx.x] = threadIdx.x < nbins ? tab[(uint64_t)threadIdx.x * ntiles + blockIdx.x] : 0;
+  __syncthreads();
+  Key<W> keys[NK];
+  uint32_t pos[NK];
+#pragma unroll
+  for (int q = 0; q < NK; ++q) pos[q] = 0xFFFFFFFFu;
+  const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
+  if (g0 < a.NW) {
+    WinIter it;
+    it.init(a, g0);
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      if (g0 + q < a.NW) {
+        uint64_t j = it.pos();
+        if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
+          window_keys<W>(a, j, &keys[2 * q], &keys[2 * q + 1]);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            if (ex_pass<W>(a, keys[2 * q + h])) {
+              uint32_t d = key_bits<W>(keys[2 * q + h], a.dlo, a.dbits);
+              uint32_t s = atomicAdd(&cnt[d], 1u);
+              pos[2 * q + h] = (d << 16) | s;
+            }
+          }
+        }
+        it.next(a);
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t total;
+  uint32_t ex = block_excl_scan<uint32_t>(cnt[threadIdx.x], sc, &total);
+  lst[threadIdx.x] = ex;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NK; ++q) {
+    if (pos[q] != 0xFFFFFFFFu) {
+      uint32_t p = lst[pos[q] >> 16] + (pos[q] & 0xFFFFu);
+      key_store<W>(&lk[p * W], keys[q]);
+    }
+  }
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < total; p += SDBG_BLOCK) {
+    Key<W> key = key_load<W>(&lk[p * W]);
+    uint32_t d = key_bits<W>(key, a.dlo, a.dbits);
+    uint64_t dst = (uint64_t)gb[d] + (p - lst[d]);
+    key_store<W>(out + dst * W, key);
+  }
+}
+
+// 16-bit-prefix histogram with global atomics; only used to plan groups
+// when the memory budget forces splitting a first-digit block.
+template <int W, int IPT>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_ex_hist_prefix(ExArgs a, unsigned long long* __restrict__ h) {
+  const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
+  if (g0 >= a.NW) return;
+  WinIter it;
+  it.init(a, g0);
+  for (int q = 0; q < IPT && g0 + q < a.NW; ++q) {
+    uint64_t j = it.pos();
+    if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
+      Key<W> kf, kr;
+      window_keys<W>(a, j, &kf, &kr);
+      atomicAdd(&h[key_bits<W>(kf, a.kb - a.pb, a.pb)], 1ull);
+      atomicAdd(&h[key_bits<W>(kr, a.kb - a.pb, a.pb)], 1ull);
+    }
+    it.next(a);
+  }
+}
+
+// ------------------------------------------------------------ segments
+// An ordered list of key ranges ("segments"); all keys of a segment share
+// their bits above `bit`.  Segment s lives at [off, off+len) of buffer buf.
+struct SegView {
+  uint64_t* off;
+  uint64_t* len;
+  uint8_t* bit;
+  uint8_t* buf;
+  uint8_t* D;  // digit width of this level's cut (0 = not cut)
+  uint64_t n;
+};
+
+__global__ void k_seg_stats(SegView v, uint64_t cap, unsigned long long* st) {
+  uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (s >= v.n) return;
+  if (v.len[s] > cap && v.bit[s] > 0) {
+    atomicAdd(&st[0], 1ull);
+    atomicAdd(&st[1], (unsigned long long)v.len[s]);
+  }
+}
+
+__global__ void k_seg_mark(SegView v, uint64_t cap, int D, int tk, uint64_t* __restrict__ ntiles,
+                           uint64_t* __restrict__ tabsz) {
+  uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (s >= v.n) return;
+  int d = 0;
+  if (v.len[s] > cap && v.bit[s] > 0) d = min(D, (int)v.bit[s]);
+  v.D[s] = (uint8_t)d;
+  uint64_t nt = d ? (v.len[s] + tk - 1) / tk : 0;
+  ntiles[s] = nt;
+  tabsz[s] = nt << d;
+}
+
+__global__ void k_seg_tiles(SegView v, const uint64_t* __restrict__ tile_first, const uint64_t* __restrict__ ntiles,
+                            uint32_t* __restrict__ tile_seg) {
+  uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (s >= v.n) return;
+  uint64_t nt = ntiles[s], f = tile_first[s];
+  for (uint64_t i = 0; i < nt; ++i) tile_seg[f + i] = (uint32_t)s;
+}
+
+template <int W, int TK>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_seg_hist(SegView v, uint64_t* const* __restrict__ bufs,
+                                                         const uint32_t* __restrict__ tile_seg,
+                                                         const uint64_t* __restrict__ tile_first,
+                                                         const uint64_t* __restrict__ tab_base,
+                                                         uint32_t* __restrict__ tab) {
+  __shared__ uint32_t h[256];
+  const uint64_t tile = blockIdx.x;
+  const uint32_t s = tile_seg[tile];
+  const uint64_t i = tile - tile_first[s];
+  const uint64_t len = v.len[s];
+  const uint64_t nt = (len + TK - 1) / TK;
+  const int D = v.D[s], lo = (int)v.bit[s] - D;
+  const uint64_t* src = bufs[v.buf[s]] + (v.off[s] + i * TK) * W;
+  const uint32_t n = (uint32_t)min((uint64_t)TK, len - i * TK);
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < n; p += SDBG_BLOCK)
+    atomicAdd(&h[key_bits<W>(key_load<W>(src + (uint64_t)p * W), lo, D)], 1u);
+  __syncthreads();
+  if (threadIdx.x < (1u << D)) tab[tab_base[s] + (uint64_t)threadIdx.x * nt + i] = h[threadIdx.x];
+}
+
+template <int W, int TK>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_seg_scatter(SegView v, uint64_t* const* __restrict__ bufs,
+                                                            const uint32_t* __restrict__ tile_seg,
+                                                            const uint64_t* __restrict__ tile_first,
+                                                            const uint64_t* __restrict__ tab_base,
+                                                            const uint32_t* __restrict__ tabscan) {
+  constexpr int PER = TK / SDBG_BLOCK;
+  __shared__ uint64_t lk[TK * W];
+  __shared__ uint32_t cnt[256], lst[256], gb[256];
+  __shared__ uint32_t sc[SDBG_WAVES + 1];
+  const uint64_t tile = blockIdx.x;
+  const uint32_t s = tile_seg[tile];
+  const uint64_t i = tile - tile_first[s];
+  const uint64_t len = v.len[s];
+  const uint64_t nt = (len + TK - 1) / TK;
+  const int D = v.D[s], lo = (int)v.bit[s] - D;
+  const int b = v.buf[s];
+  const uint64_t* src = bufs[b] + (v.off[s] + i * TK) * W;
+  uint64_t* dst = bufs[b ^ 1] + v.off[s] * W;
+  const uint32_t n = (uint32_t)min((uint64_t)TK, len - i * TK);
+  const uint64_t tb = tab_base[s];
+  const uint32_t seg0 = tabscan[tb];
+  cnt[threadIdx.x] = 0;
+  gb[threadIdx.x] = threadIdx.x < (1u << D) ? tabscan[tb + (uint64_t)threadIdx.x * nt + i] - seg0 : 0;
+  __syncthreads();
+  Key<W> keys[PER];
+  uint32_t pos[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    uint32_t p = q * SDBG_BLOCK + threadIdx.x;
+    pos[q] = 0xFFFFFFFFu;
+    if (p < n) {
+      keys[q] = key_load<W>(src + (uint64_t)p * W);
+      uint32_t d = key_bits<W>(keys[q], lo, D);
+      pos[q] = (d << 16) | atomicAdd(&cnt[d], 1u);
+    }
+  }
+  __syncthreads();
+  uint32_t total;
+  lst[threadIdx.x] = block_excl_scan<uint32_t>(cnt[threadIdx.x], sc, &total);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q)
+    if (pos[q] != 0xFFFFFFFFu) key_store<W>(&lk[(lst[pos[q] >> 16] + (pos[q] & 0xFFFFu)) * W], keys[q]);
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < total; p += SDBG_BLOCK) {
+    Key<W> key = key_load<W>(&lk[p * W]);
+    uint32_t d = key_bits<W>(key, lo, D);
+    key_store<W>(dst + ((uint64_t)gb[d] + (p - lst[d])) * W, key);
+  }
+}
+
+
+// Entries of the next segment list contributed by segment s: itself if not
+// cut, else its non-empty children.
+__device__ __forceinline__ void child_range(const SegView& v, uint64_t s, int tk, const uint64_t* tab_base,
+                                            const uint32_t* tabscan, uint32_t d, uint64_t* start, uint64_t* end) {
+  const int D = v.D[s];
+  const uint64_t nt = (v.len[s] + tk - 1) / tk;
+  const uint64_t tb = tab_base[s];
+  const uint32_t s0 = tabscan[tb];
+  *start = tabscan[tb + d * nt] - s0;
+  *end = (d + 1 < (1u << D)) ? (uint64_t)(tabscan[tb + (uint64_t)(d + 1) * nt] - s0) : v.len[s];
+}
+
+__global__ void k_seg_newcount(SegView v, int tk, const uint64_t* __restrict__ tab_base,
+                               const uint32_t* __restrict__ tabscan, uint64_t* __restrict__ cnt) {
+  uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (s >= v.n) return;
+  const int D = v.D[s];
+  if (!D) {
+    cnt[s] = 1;
+    return;
+  }
+  uint64_t c = 0;
+  for (uint32_t d = 0; d < (1u << D); ++d) {
+    uint64_t a, b;
+    child_range(v, s, tk, tab_base, tabscan, d, &a, &b);
+    c += b > a;
+  }
+  cnt[s] = c;
+}
+
+__global__ void k_seg_newwrite(SegView v, int tk, const uint64_t* __restrict__ tab_base,
+                               const uint32_t* __restrict__ tabscan, const uint64_t* __restrict__ newpos, SegView nv) {
+  uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (s >= v.n) return;
+  uint64_t p = newpos[s];
+  const int D = v.D[s];
+  if (!D) {
+    nv.off[p] = v.off[s];
+    nv.len[p] = v.len[s];
+    nv.bit[p] = v.bit[s];
+    nv.buf[p] = v.buf[s];
+    return;
+  }
+  for (uint32_t d = 0; d < (1u << D); ++d) {
+    uint64_t a, b;
+    child_range(v, s, tk, tab_base, tabscan, d, &a, &b);
+    if (b > a) {
+      nv.off[p] = v.off[s] + a;
+      nv.len[p] = b - a;
+      nv.bit[p] = (uint8_t)(v.bit[s] - D);
+      nv.buf[p] = (uint8_t)(v.buf[s] ^ 1);
+      ++p;
+    }
+  }
+}
+
+// ------------------------------------------------------------ leaves
+// One workgroup per leaf segment: load its keys into LDS, counting-sort them
+// by the next B bits, finish each bin with an insertion sort (bins are tiny
+// and equal keys do not move), run-length count, and write the distinct
+// keys with count >= d (and, if want_low, those below d after them) back in
+// place at the segment's start, counts into cnt[] at the same positions.
+// A segment longer than CAP has no key bits left to cut, so all its keys
+// are equal.
+template <int W, int CAP>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const* __restrict__ bufs,
+                                                     uint32_t* __restrict__ cnt, uint32_t dmin, int want_low,
+                                                     uint64_t* __restrict__ nsolid, uint64_t* __restrict__ nlow) {
+  constexpr int PER = CAP / SDBG_BLOCK;
+  constexpr int MAXB = 12;
+  __shared__ uint64_t A[CAP * W];
+  __shared__ uint16_t idx[CAP];
+  __shared__ uint32_t bins[(1 << MAXB) + 1];
+  __shared__ uint32_t sc[SDBG_WAVES + 1];
+  const uint64_t s = blockIdx.x;
+  const uint64_t len = v.len[s];
+  uint64_t* keys = bufs[v.buf[s]] + v.off[s] * W;
+  uint32_t* cn = cnt + v.off[s];
+  if (len > CAP) {
+    if (threadIdx.x == 0) {
+      const uint32_t c = len > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)len;
+      const bool solid = len >= dmin;
+      if (solid || want_low) cn[0] = c;
+      nsolid[s] = solid;
+      nlow[s] = !solid && want_low;
+    }
+    return;
+  }
+  const int n = (int)len;
+  int B = 1;
+  while ((1 << B) < 2 * n && B < MAXB) ++B;
+  B = min(B, (int)v.bit[s]);
+  const int lo = (int)v.bit[s] - B;
+  const int nbins = 1 << B;
+  for (int i = threadIdx.x; i < n; i += SDBG_BLOCK) key_store<W>(&A[i * W], key_load<W>(keys + (uint64_t)i * W));
+  for (int i = threadIdx.x; i <= nbins; i += SDBG_BLOCK) bins[i] = 0;
+  __syncthreads();
+  uint32_t dg[PER], sl[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = q * SDBG_BLOCK + threadIdx.x;
+    if (i < n) {
+      dg[q] = B ? key_bits<W>(key_load<W>(&A[i * W]), lo, B) : 0;
+      sl[q] = atomicAdd(&bins[dg[q]], 1u);
+    }
+  }
+  __syncthreads();
+  // exclusive scan of the bins: each thread owns a contiguous run of bins
+  {
+    const int per = (nbins + SDBG_BLOCK - 1) / SDBG_BLOCK;
+    const int b0 = min(nbins, (int)threadIdx.x * per), b1 = min(nbins, b0 + per);
+    uint32_t run = 0;
+    for (int b = b0; b < b1; ++b) run += bins[b];
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<uint32_t>(run, sc, &tot);
+    for (int b = b0; b < b1; ++b) {
+      uint32_t t = bins[b];
+      bins[b] = ex;
+      ex += t;
+    }
+    if (threadIdx.x == 0) bins[nbins] = tot;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = q * SDBG_BLOCK + threadIdx.x;
+    if (i < n) idx[bins[dg[q]] + sl[q]] = (uint16_t)i;
+  }
+  __syncthreads();
+  // this thread's bins [b0, b1) = positions [r0, r1) of idx
+  const int b0 = (int)(((uint64_t)threadIdx.x * nbins) / SDBG_BLOCK);
+  const int b1 = (int)(((uint64_t)(threadIdx.x + 1) * nbins) / SDBG_BLOCK);
+  const int r0 = bins[b0], r1 = bins[b1];
+  for (int i = r0 + 1; i < r1; ++i) {
+    uint16_t x = idx[i];
+    Key<W> kx = key_load<W>(&A[x * W]);
+    int j = i - 1;
+    while (j >= r0 && key_less<W>(kx, key_load<W>(&A[idx[j] * W]))) {
+      idx[j + 1] = idx[j];
+      --j;
+    }
+    idx[j + 1] = x;
+  }
+  uint32_t ns = 0, nl = 0;
+  for (int i = r0; i < r1;) {
+    Key<W> kx = key_load<W>(&A[idx[i] * W]);
+    int j = i + 1;
+    while (j < r1 && key_eq<W>(kx, key_load<W>(&A[idx[j] * W]))) ++j;
+    if ((uint32_t)(j - i) >= dmin)
+      ++ns;
+    else if (want_low)
+      ++nl;
+    i = j;
+  }
+  uint32_t NS, NL;
+  uint32_t bs = block_excl_scan<uint32_t>(ns, sc, &NS);
+  uint32_t bl = block_excl_scan<uint32_t>(nl, sc, &NL);
+  for (int i = r0; i < r1;) {
+    Key<W> kx = key_load<W>(&A[idx[i] * W]);
+    int j = i + 1;
+    while (j < r1 && key_eq<W>(kx, key_load<W>(&A[idx[j] * W]))) ++j;
+    const uint32_t c = (uint32_t)(j - i);
+    if (c >= dmin) {
+      key_store<W>(keys + (uint64_t)bs * W, kx);
+      cn[bs] = c;
+      ++bs;
+    } else if (want_low) {
+      key_store<W>(keys + (uint64_t)(NS + bl) * W, kx);
+      cn[NS + bl] = c;
+      ++bl;
+    }
+    i = j;
+  }
+  if (threadIdx.x == 0) {
+    nsolid[s] = NS;
+    nlow[s] = NL;
+  }
+}
+
+// Gather the per-leaf outputs into dense arrays in leaf order (= key order).
+template <int W>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_compact(SegView v, uint64_t* const* __restrict__ bufs,
+                                                        const uint32_t* __restrict__ cnt,
+                                                        const uint64_t* __restrict__ nsolid,
+                                                        const uint64_t* __restrict__ spos,
+                                                        const uint64_t* __restrict__ nlow,
+                                                        const uint64_t* __restrict__ lpos, uint64_t* __restrict__ skeys,
+                                                        uint32_t* __restrict__ scnt, uint64_t* __restrict__ lkeys,
+                                                        uint32_t* __restrict__ lcnt) {
+  const uint64_t s = blockIdx.x;
+  const uint64_t off = v.off[s];
+  const uint64_t* src = bufs[v.buf[s]] + off * W;
+  const uint64_t a = nsolid[s], b = nlow ? nlow[s] : 0;
+  const uint64_t ps = spos[s];
+  for (uint64_t i = threadIdx.x; i < a; i += SDBG_BLOCK) {
+    key_store<W>(skeys + (ps + i) * W, key_load<W>(src + i * W));
+    scnt[ps + i] = cnt[off + i];
+  }
+  if (b) {
+    const uint64_t pl = lpos[s];
+    for (uint64_t i = threadIdx.x; i < b; i += SDBG_BLOCK) {
+      key_store<W>(lkeys + (pl + i) * W, key_load<W>(src + (a + i) * W));
+      lcnt[pl + i] = cnt[off + a + i];
+    }
+  }
+}
+
+// ------------------------------------------------------------ directory
+template <int W>
+__global__ void k_dir(const uint64_t* __restrict__ keys, uint64_t n, int kbits, int db, uint64_t* __restrict__ dir) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i > n) return;
+  uint64_t b = i < n ? key_bits<W>(key_load<W>(keys + i * W), kbits - db, db) : (1ull << db);
+  uint64_t from = i == 0 ? 0 : (uint64_t)key_bits<W>(key_load<W>(keys + (i - 1) * W), kbits - db, db) + 1;
+  for (uint64_t x = from; x <= b; ++x) dir[x] = i;
+}
+
+// Order check of a key array: flags[0] |= 1 if some key is not strictly
+// greater than its predecessor, |= 2 if a key has bits above kbits.
+template <int W>
+__global__ void k_check_sorted(const uint64_t* __restrict__ keys, uint64_t n, int kbits, uint32_t* flags) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Key<W> x = key_load<W>(keys + i * W);
+  if (!key_eq<W>(key_lowbits<W>(x, kbits), x)) atomicOr(flags, 2u);
+  if (i > 0 && !key_less<W>(key_load<W>(keys + (i - 1) * W), x)) atomicOr(flags, 1u);
+}
+
+// ------------------------------------------------------------ mercy
+// Dead-end flags of solid edges: bit1 = no outgoing solid edge, bit2 = no
+// incoming solid edge (degrees on the solid set), bit0 = solid.
+template <int W>
+__global__ void k_dead_ends(SortedView S, int k, uint8_t* __restrict__ fl) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= S.n) return;
+  Key<W> x = key_load<W>(S.keys + i * W);
+  bool out = sv_has_source<W>(S, edge_target<W>(x, k));
+  bool in = sv_has_target<W>(S, key_shr<W>(x, 2), k);
+  fl[i] = (uint8_t)(1 | (!out ? 2 : 0) | (!in ? 4 : 0));
+}
+
+// Per forward-strand window: 0x80 if it holds a non-ACGT base, else the
+// dead-end flags of its edge if solid, else 0.
+template <int W, int IPT>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags(ExArgs a, SortedView S, const uint8_t* __restrict__ sfl,
+                                                             uint8_t* __restrict__ wf) {
+  const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
+  if (g0 >= a.NW) return;
+  WinIter it;
+  it.init(a, g0);
+  for (int q = 0; q < IPT && g0 + q < a.NW; ++q) {
+    uint64_t j = it.pos();
+    uint8_t f = 0x80;
+    if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
+      Key<W> F = stream_bits<W>(a.packed, 2 * j, a.kb);
+      Key<W> kf = key_from_fwd<W>(F, a.kb);
+      uint64_t ix;
+      f = sv_find<W>(S, kf, &ix) ? sfl[ix] : 0;
+    }
+    wf[g0 + q] = f;
+    it.next(a);
+  }
+}
+
+// Mercy rule along each read (forward strand): consecutive solid windows
+// p < q of one ACGT stretch, q - p >= 2, p without outgoing and q without
+// incoming solid edge: windows p+1..q-1 and their reverse complements are
+// mercy edges.  Pass 0 counts keys per read, pass 1 writes them.
+template <int W>
+__global__ void k_mercy(ExArgs a, const uint8_t* __restrict__ wf, int pass, uint64_t* __restrict__ mcount,
+                        const uint64_t* __restrict__ mpos, uint64_t* __restrict__ cand) {
+  uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (r >= a.n_reads) return;
+  const uint64_t g0 = a.woff[r], g1 = a.woff[r + 1];
+  const uint64_t rs = a.offsets[r];
+  uint64_t out = pass ? mpos[r] : 0, c = 0;
+  int64_t p = -1;
+  bool p_noout = false;
+  for (uint64_t g = g0; g < g1; ++g) {
+    const uint8_t f = wf[g];
+    if (f & 0x80) {
+      p = -1;
+      continue;
+    }
+    if (!(f & 1)) continue;
+    const int64_t q = (int64_t)(g - g0);
+    if (p >= 0 && q - p >= 2 && p_noout && (f & 4)) {
+      if (!pass) {
+        c += 2 * (uint64_t)(q - p - 1);
+      } else {
+        for (int64_t i = p + 1; i < q; ++i) {
+          Key<W> kf, kr;
+          window_keys<W>(a, rs + (uint64_t)i, &kf, &kr);
+          key_store<W>(cand + out * W, kf);
+          key_store<W>(cand + (out + 1) * W, kr);
+          out += 2;
+        }
+      }
+    }
+    p = q;
+    p_noout = (f & 2) != 0;
+  }
+  if (!pass) mcount[r] = c;
+}
+
+// Counts of mercy edges from the low-count set (d > 2).
+template <int W>
+__global__ void k_lookup_counts(const uint64_t* __restrict__ keys, uint64_t n, SortedView L,
+                                const uint32_t* __restrict__ lcnt, uint32_t* __restrict__ out) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t ix;
+  out[i] = sv_find<W>(L, key_load<W>(keys + i * W), &ix) ? lcnt[ix] : 0;
+}
+
+// Merge of two disjoint sorted sets: element i of A goes to i + #(B < a_i).
+template <int W>
+__global__ void k_merge_place(const uint64_t* __restrict__ akeys, const uint32_t* __restrict__ acnt, uint64_t na,
+                              SortedView B, uint64_t* __restrict__ okeys, uint32_t* __restrict__ ocnt) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= na) return;
+  Key<W> x = key_load<W>(akeys + i * W);
+  uint64_t p = i + sv_lower<W>(B, x);
+  key_store<W>(okeys + p * W, x);
+  ocnt[p] = acnt[i];
+}
+
+}  // namespace sdbg
+
+// ================================================================ host side
+namespace sdbg {
+namespace {
+
+inline unsigned grid1(uint64_t n) {
+  uint64_t g = ceil_div(n, SDBG_BLOCK);
+  SDBG_CHECK(g < (1ull << 31), -1, "grid too large");
+  return (unsigned)(g ? g : 1);
+}
+
+struct SegList {
+  DBuf<uint64_t> off, len;
+  DBuf<uint8_t> bit, buf, D;
+  uint64_t n = 0;
+  void alloc(Ctx& c, uint64_t cnt) {
+    n = cnt;
+    off = c.buf<uint64_t>(cnt);
+    len = c.buf<uint64_t>(cnt);
+    bit = c.buf<uint8_t>(cnt);
+    buf = c.buf<uint8_t>(cnt);
+    D = c.buf<uint8_t>(cnt);
+  }
+  SegView view() const { return SegView{off.get(), len.get(), bit.get(), buf.get(), D.get(), n}; }
+};
+
+// Initial segments from the first cut: digit d covers [start_d, start_d+len_d).
+__global__ void k_seg_init(const uint32_t* __restrict__ tabscan, uint64_t ntiles, uint32_t nbins, uint64_t total,
+                           int bit, SegView v) {
+  uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= nbins) return;
+  uint64_t a = tabscan[(uint64_t)d * ntiles];
+  uint64_t b = d + 1 < nbins ? tabscan[(uint64_t)(d + 1) * ntiles] : total;
+  v.off[d] = a;
+  v.len[d] = b - a;
+  v.bit[d] = (uint8_t)bit;
+  v.buf[d] = 0;
+  v.D[d] = 0;
+}
+
+__global__ void k_gather_strided(const uint32_t* __restrict__ src, uint64_t stride, uint32_t n, uint64_t* dst) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[(uint64_t)i * stride];
+}
+
+template <int W>
+struct Counter {
+  static constexpr int IPT = Tune<W>::IPT, TK = Tune<W>::TK, CAP = Tune<W>::CAP;
+  Ctx& c;
+  explicit Counter(Ctx& c_) : c(c_) {}
+
+  // Cut every segment longer than CAP (while it has key bits left) until
+  // all fit a leaf; data ping-pongs between bufs[0] and bufs[1] at equal
+  // offsets.
+  void refine(SegList& L, uint64_t* const* d_bufs) {
+    DBuf<unsigned long long> st = c.buf<unsigned long long>(2);
+    for (int level = 0; level < 64; ++level) {
+      if (L.n == 0) return;
+      fill<uint64_t>(reinterpret_cast<uint64_t*>(st.get()), 2, 0, c);
+      k_seg_stats<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), CAP, st.get());
+      c.check_launch("seg_stats");
+      unsigned long long hs[2];
+      c.d2h(hs, st.get(), 2);
+      if (hs[0] == 0) return;
+      const uint64_t avg = hs[1] / hs[0];
+      int D = 1;
+      while (D < 8 && (avg >> D) > (uint64_t)CAP / 2) ++D;
+      DBuf<uint64_t> ntiles = c.buf<uint64_t>(L.n), tabsz = c.buf<uint64_t>(L.n);
+      DBuf<uint64_t> tile_first = c.buf<uint64_t>(L.n), tab_base = c.buf<uint64_t>(L.n);
+      DBuf<uint64_t> tot = c.buf<uint64_t>(2);
+      k_seg_mark<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), CAP, D, TK, ntiles.get(), tabsz.get());
+      c.check_launch("seg_mark");
+      scan_excl<uint64_t, uint64_t>(ntiles.get(), tile_first.get(), L.n, tot.get(), c);
+      scan_excl<uint64_t, uint64_t>(tabsz.get(), tab_base.get(), L.n, tot.get() + 1, c);
+      uint64_t ht[2];
+      c.d2h(ht, tot.get(), 2);
+      const uint64_t NT = ht[0], NTab = ht[1];
+      SDBG_CHECK(NT < (1ull << 31), -3, "too many partition tiles");
+      DBuf<uint32_t> tile_seg = c.buf<uint32_t>(NT), tab = c.buf<uint32_t>(NTab);
+      k_seg_tiles<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), tile_first.get(), ntiles.get(), tile_seg.get());
+      c.check_launch("seg_tiles");
+      {
+        Stage st_(c, "seg_hist", hs[1] * 8 * W + NTab * 4);
+        k_seg_hist<W, TK><<<(unsigned)NT, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, tile_seg.get(), tile_first.get(),
+                                                                  tab_base.get(), tab.get());
+        c.check_launch("seg_hist");
+      }
+      scan_excl<uint32_t, uint32_t>(tab.get(), tab.get(), NTab, nullptr, c);
+      {
+        Stage st_(c, "seg_scatter", hs[1] * 16 * W + NTab * 4);
+        k_seg_scatter<W, TK><<<(unsigned)NT, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, tile_seg.get(), tile_first.get(),
+                                                                     tab_base.get(), tab.get());
+        c.check_launch("seg_scatter");
+      }
+      DBuf<uint64_t> ncnt = c.buf<uint64_t>(L.n), npos = c.buf<uint64_t>(L.n);
+      k_seg_newcount<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), TK, tab_base.get(), tab.get(), ncnt.get());
+      c.check_launch("seg_newcount");
+      scan_excl<uint64_t, uint64_t>(ncnt.get(), npos.get(), L.n, tot.get(), c);
+      const uint64_t nn = c.d2h_one(tot.get());
+      SegList N;
+      N.alloc(c, nn);
+      k_seg_newwrite<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), TK, tab_base.get(), tab.get(), npos.get(), N.view());
+      c.check_launch("seg_newwrite");
+      L = std::move(N);
+    }
+    throw Error(-4, "partition did not converge");
+  }
+
+  // Leaves -> dense sorted (key, count) arrays of the distinct keys with
+  // count >= dmin, and (if want_low) of those below.
+  void leaves(SegList& L, uint64_t nkeys, uint64_t* const* d_bufs, uint32_t* cnt, uint32_t dmin, bool want_low,
+              DBuf<uint64_t>& skeys, DBuf<uint32_t>& scnt, uint64_t* ns_out, DBuf<uint64_t>& lkeys,
+              DBuf<uint32_t>& lcnt, uint64_t* nl_out) {
+    DBuf<uint64_t> nsolid = c.buf<uint64_t>(L.n), nlow = c.buf<uint64_t>(L.n);
+    DBuf<uint64_t> spos = c.buf<uint64_t>(L.n), lpos = c.buf<uint64_t>(L.n), tot = c.buf<uint64_t>(2);
+    if (L.n) {
+      Stage st_(c, "leaf", nkeys * 8 * W);
+      k_leaf<W, CAP><<<(unsigned)L.n, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, cnt, dmin, want_low ? 1 : 0,
+                                                              nsolid.get(), nlow.get());
+      c.check_launch("leaf");
+    }
+    scan_excl<uint64_t, uint64_t>(nsolid.get(), spos.get(), L.n, tot.get(), c);
+    scan_excl<uint64_t, uint64_t>(nlow.get(), lpos.get(), L.n, tot.get() + 1, c);
+    uint64_t ht[2];
+    c.d2h(ht, tot.get(), 2);
+    *ns_out = ht[0];
+    *nl_out = want_low ? ht[1] : 0;
+    const uint64_t outb = (*ns_out + *nl_out) * (8 * W + 4);
+    if (L.n) prof_set_last_bytes(nkeys * 8 * W + outb);
+    skeys = c.buf<uint64_t>(ht[0] * W);
+    scnt = c.buf<uint32_t>(ht[0]);
+    if (want_low) {
+      lkeys = c.buf<uint64_t>(ht[1] * W);
+      lcnt = c.buf<uint32_t>(ht[1]);
+    }
+    if (L.n) {
+      Stage st_(c, "compact", 2 * outb + L.n * 32);
+      k_compact<W><<<(unsigned)L.n, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, cnt, nsolid.get(), spos.get(),
+                                                            want_low ? nlow.get() : nullptr, lpos.get(), skeys.get(),
+                                                            scnt.get(), want_low ? lkeys.get() : nullptr,
+                                                            want_low ? lcnt.get() : nullptr);
+      c.check_launch("compact");
+    }
+  }
+
+  // Sorted distinct keys of an arbitrary key array (consumed).
+  void sort_unique(DBuf<uint64_t>& keys, uint64_t n, int kb, DBuf<uint64_t>& out, uint64_t* nout) {
+    SDBG_CHECK(n < (1ull << 32), -3, "key array too large for one partition group");
+    DBuf<uint64_t> other = c.buf<uint64_t>(n * W);
+    DBuf<uint32_t> cnt = c.buf<uint32_t>(n);
+    uint64_t* hb[2] = {keys.get(), other.get()};
+    DBuf<uint64_t*> db = c.buf<uint64_t*>(2);
+    c.h2d(db.get(), hb, 2);
+    SegList L;
+    L.alloc(c, 1);
+    uint64_t z = 0, nn = n;
+    uint8_t bit = (uint8_t)kb, b0 = 0;
+    c.h2d(L.off.get(), &z, 1);
+    c.h2d(L.len.get(), &nn, 1);
+    c.h2d(L.bit.get(), &bit, 1);
+    c.h2d(L.buf.get(), &b0, 1);
+    c.h2d(L.D.get(), &b0, 1);
+    refine(L, db.get());
+    DBuf<uint32_t> ocnt;
+    DBuf<uint64_t> lk;
+    DBuf<uint32_t> lc;
+    uint64_t nl;
+    leaves(L, n, db.get(), cnt.get(), 1, false, out, ocnt, nout, lk, lc, &nl);
+    c.sync();
+  }
+
+  SortedView make_view(const uint64_t* keys, uint64_t n, int kbits, DBuf<uint64_t>& dir) {
+    int db = 1;
+    while (db < 24 && db < kbits && (n >> (db + 3)) > 0) ++db;
+    dir = c.buf<uint64_t>((1ull << db) + 1);
+    k_dir<W><<<grid1(n + 1), SDBG_BLOCK, 0, c.s>>>(keys, n, kbits, db, dir.get());
+    c.check_launch("dir");
+    return SortedView{keys, dir.get(), n, kbits, db};
+  }
+
+  void run(const DevReads& R, const CountParams& P, EdgesOut* out) {
+    const int k = P.k, kb = 2 * (k + 1);
+    const uint64_t nb = R.n_bases;
+    // ---- pack
+    const uint64_t words = ceil_div(nb, 64);
+    DBuf<uint64_t> packed = c.buf<uint64_t>(2 * words + W + 8), bad = c.buf<uint64_t>(words + 8);
+    DBuf<uint32_t> anyb = c.buf<uint32_t>(1);
+    fill<uint64_t>(packed.get() + 2 * words, W + 8, 0, c);
+    fill<uint64_t>(bad.get() + words, 8, 0, c);
+    fill<uint32_t>(anyb.get(), 1, 0, c);
+    if (words) {
+      Stage st_(c, "pack", nb + 3 * words * 8);
+      k_pack<<<grid1(words), SDBG_BLOCK, 0, c.s>>>(R.seq, nb, packed.get(), bad.get(), anyb.get());
+      c.check_launch("pack");
+    }
+    // ---- windows per read
+    DBuf<uint64_t> woff = c.buf<uint64_t>(R.n_reads + 1);
+    {
+      DBuf<uint64_t> nwin = c.buf<uint64_t>(R.n_reads);
+      if (R.n_reads) {
+        k_nwin<<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(R.offsets, R.n_reads, k, nwin.get());
+        c.check_launch("nwin");
+      }
+      scan_excl<uint64_t, uint64_t>(nwin.get(), woff.get(), R.n_reads, woff.get() + R.n_reads, c);
+    }
+    const uint64_t NW = c.d2h_one(woff.get() + R.n_reads);
+    const uint32_t any_bad = c.d2h_one(anyb.get());
+    *out = EdgesOut{};
+    if (NW == 0) return;
+
+    ExArgs ea{};
+    ea.packed = packed.get();
+    ea.bad = bad.get();
+    ea.woff = woff.get();
+    ea.offsets = R.offsets;
+    ea.n_reads = R.n_reads;
+    ea.NW = NW;
+    ea.any_bad = any_bad ? 1 : 0;
+    ea.k = k;
+    ea.kb = kb;
+    ea.pb = std::min(16, kb);
+    ea.glo = 0;
+    ea.ghi = 1u << ea.pb;
+    ea.dbits = std::min(8, kb);
+    ea.dlo = kb - ea.dbits;
+    const uint32_t nbins = 1u << ea.dbits;
+    const uint64_t win_per_tile = (uint64_t)SDBG_BLOCK * IPT;
+    const uint64_t ntiles = ceil_div(NW, win_per_tile);
+    SDBG_CHECK(ntiles < (1ull << 31), -3, "too many reads for one launch");
+
+    // ---- first-digit histogram over all keys
+    DBuf<uint32_t> tab = c.buf<uint32_t>(ntiles * nbins);
+    DBuf<unsigned long long> occ = c.buf<unsigned long long>(1);
+    DBuf<uint64_t> tot = c.buf<uint64_t>(1);
+    fill<uint64_t>(reinterpret_cast<uint64_t*>(occ.get()), 1, 0, c);
+    {
+      Stage st_(c, "ex_hist", 3 * words * 8 + ntiles * nbins * 4);
+      k_ex_hist<W, IPT><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(ea, tab.get(), ntiles, occ.get());
+      c.check_launch("ex_hist");
+    }
+    const uint64_t N = c.d2h_one(reinterpret_cast<uint64_t*>(occ.get()));
+    out->n_occ = N;
+
+    // ---- groups of consecutive prefix blocks within the memory budget
+    uint64_t budget = P.mem_budget;
+    if (!budget) {
+      size_t fr = 0, totm = 0;
+      SDBG_HIP(hipMemGetInfo(&fr, &totm));
+      budget = (uint64_t)(0.8 * (double)(fr + Pool::get().cached_bytes()));
+    }
+    const uint64_t per_key = 16ull * W + 4;
+    uint64_t max_keys = std::min<uint64_t>(budget / per_key, 0xFFFFFFFFull);
+    std::vector<std::pair<uint32_t, uint32_t>> groups;
+    if (N <= max_keys || P.prefix_len == 0) {
+      SDBG_CHECK(N <= max_keys, -3, "memory budget cannot hold the keys and prefix_len is 0");
+      groups.push_back({0u, 1u << ea.pb});
+    } else {
+      DBuf<unsigned long long> ph = c.buf<unsigned long long>(1ull << ea.pb);
+      fill<uint64_t>(reinterpret_cast<uint64_t*>(ph.get()), 1ull << ea.pb, 0, c);
+      k_ex_hist_prefix<W, IPT><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(ea, ph.get());
+      c.check_launch("ex_hist_prefix");
+      std::vector<unsigned long long> h(1ull << ea.pb);
+      c.d2h(h.data(), ph.get(), h.size());
+      const int ub = std::max(0, ea.pb - 2 * P.prefix_len);  // block = 2^ub prefix values
+      const uint32_t unit = 1u << ub, nvals = 1u << ea.pb;
+      uint32_t g0 = 0;
+      uint64_t acc = 0;
+      for (uint32_t u = 0; u < nvals; u += unit) {
+        uint64_t bs = 0;
+        for (uint32_t x = u; x < u + unit; ++x) bs += h[x];
+        SDBG_CHECK(bs <= max_keys, -3, "one prefix block exceeds the memory budget");
+        if (acc + bs > max_keys) {
+          groups.push_back({g0, u});
+          g0 = u;
+          acc = 0;
+        }
+        acc += bs;
+      }
+      groups.push_back({g0, nvals});
+    }
+
+    // ---- per group: partition, leaves, compaction
+    std::vector<DBuf<uint64_t>> s_keys(groups.size()), l_keys(groups.size());
+    std::vector<DBuf<uint32_t>> s_cnt(groups.size()), l_cnt(groups.size());
+    std::vector<uint64_t> s_n(groups.size()), l_n(groups.size());
+    const bool want_low = P.mercy && P.d > 2;
+    {
+      const uint64_t cap_keys = groups.size() == 1 ? N : max_keys;
+      DBuf<uint64_t> bufA = c.buf<uint64_t>(cap_keys * W), bufB = c.buf<uint64_t>(cap_keys * W);
+      DBuf<uint32_t> cnt = c.buf<uint32_t>(cap_keys);
+      uint64_t* hb[2] = {bufA.get(), bufB.get()};
+      DBuf<uint64_t*> db = c.buf<uint64_t*>(2);
+      c.h2d(db.get(), hb, 2);
+      for (size_t gi = 0; gi < groups.size(); ++gi) {
+        ExArgs ga = ea;
+        ga.glo = groups[gi].first;
+        ga.ghi = groups[gi].second;
+        if (groups.size() > 1) {
+          k_ex_hist<W, IPT><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(ga, tab.get(), ntiles, nullptr);
+          c.check_launch("ex_hist(group)");
+        }
+        scan_excl<uint32_t, uint32_t>(tab.get(), tab.get(), ntiles * nbins, tot.get(), c);
+        const uint64_t NG = c.d2h_one(tot.get());
+        SDBG_CHECK(NG <= cap_keys, -4, "group larger than planned");
+        if (NG == 0) continue;
+        {
+          Stage st_(c, "ex_scatter", 3 * words * 8 + ntiles * nbins * 4 + NG * 8 * W);
+          k_ex_scatter<W, IPT><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(ga, tab.get(), ntiles, bufA.get());
+          c.check_launch("ex_scatter");
+        }
+        SegList L;
+        L.alloc(c, nbins);
+        k_seg_init<<<grid1(nbins), SDBG_BLOCK, 0, c.s>>>(tab.get(), ntiles, nbins, NG, kb - ea.dbits, L.view());
+        c.check_launch("seg_init");
+        refine(L, db.get());
+        leaves(L, NG, db.get(), cnt.get(), P.d, want_low, s_keys[gi], s_cnt[gi], &s_n[gi], l_keys[gi], l_cnt[gi],
+               &l_n[gi]);
+      }
+    }
+    tab.free();
+    // ---- concatenate groups
+    uint64_t nS = 0, nL = 0;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      nS += s_n[gi];
+      nL += l_n[gi];
+    }
+    DBuf<uint64_t> S, Lk;
+    DBuf<uint32_t> Sc, Lc;
+    if (groups.size() == 1) {
+      S = std::move(s_keys[0]);
+      Sc = std::move(s_cnt[0]);
+      Lk = std::move(l_keys[0]);
+      Lc = std::move(l_cnt[0]);
+    } else {
+      S = c.buf<uint64_t>(nS * W);
+      Sc = c.buf<uint32_t>(nS);
+      Lk = c.buf<uint64_t>(nL * W);
+      Lc = c.buf<uint32_t>(nL);
+      uint64_t ps = 0, pl = 0;
+      for (size_t gi = 0; gi < groups.size(); ++gi) {
+        c.d2d(S.get() + ps * W, s_keys[gi].get(), s_n[gi] * W);
+        c.d2d(Sc.get() + ps, s_cnt[gi].get(), s_n[gi]);
+        c.d2d(Lk.get() + pl * W, l_keys[gi].get(), l_n[gi] * W);
+        c.d2d(Lc.get() + pl, l_cnt[gi].get(), l_n[gi]);
+        ps += s_n[gi];
+        pl += l_n[gi];
+      }
+      c.sync();
+      s_keys.clear();
+      s_cnt.clear();
+      l_keys.clear();
+      l_cnt.clear();
+    }
+
+    // ---- mercy-kmers
+    DBuf<uint64_t> M;
+    DBuf<uint32_t> Mc;
+    uint64_t nM = 0;
+    if (P.mercy && P.d >= 2 && nS > 0) {
+      DBuf<uint64_t> sdir;
+      SortedView sv = make_view(S.get(), nS, kb, sdir);
+      DBuf<uint8_t> sfl = c.buf<uint8_t>(nS);
+      {
+        Stage st_(c, "dead_ends", nS * (8 * W + 1));
+        k_dead_ends<W><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(sv, k, sfl.get());
+        c.check_launch("dead_ends");
+      }
+      DBuf<uint8_t> wf = c.buf<uint8_t>(NW);
+      {
+        Stage st_(c, "window_flags", 3 * words * 8 + NW);
+        k_window_flags<W, IPT><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(ea, sv, sfl.get(), wf.get());
+        c.check_launch("window_flags");
+      }
+      DBuf<uint64_t> mcount = c.buf<uint64_t>(R.n_reads), mpos = c.buf<uint64_t>(R.n_reads);
+      {
+        Stage st_(c, "mercy_count", NW + R.n_reads * 24);
+        k_mercy<W><<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(ea, wf.get(), 0, mcount.get(), nullptr, nullptr);
+        c.check_launch("mercy_count");
+      }
+      scan_excl<uint64_t, uint64_t>(mcount.get(), mpos.get(), R.n_reads, tot.get(), c);
+      const uint64_t NC = c.d2h_one(tot.get());
+      if (NC) {
+        DBuf<uint64_t> cand = c.buf<uint64_t>(NC * W);
+        {
+          Stage st_(c, "mercy_emit", NW + R.n_reads * 24 + NC * 8 * W);
+          k_mercy<W><<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(ea, wf.get(), 1, nullptr, mpos.get(), cand.get());
+          c.check_launch("mercy_emit");
+        }
+        wf.free();
+        sort_unique(cand, NC, kb, M, &nM);
+        Mc = c.buf<uint32_t>(nM);
+        if (P.d <= 2) {
+          fill<uint32_t>(Mc.get(), nM, 1u, c);
+        } else {
+          DBuf<uint64_t> ldir;
+          SortedView lv = make_view(Lk.get(), nL, kb, ldir);
+          k_lookup_counts<W><<<grid1(nM), SDBG_BLOCK, 0, c.s>>>(M.get(), nM, lv, Lc.get(), Mc.get());
+          c.check_launch("lookup_counts");
+          c.sync();
+        }
+      }
+    }
+    // ---- E = S + M
+    out->n_mercy = nM;
+    out->n = nS + nM;
+    if (nM == 0) {
+      out->keys = S.release_ownership();
+      out->count = Sc.release_ownership();
+    } else {
+      Stage st_(c, "merge", 2 * (nS + nM) * (8 * W + 4));
+      DBuf<uint64_t> E = c.buf<uint64_t>((nS + nM) * W);
+      DBuf<uint32_t> Ec = c.buf<uint32_t>(nS + nM);
+      DBuf<uint64_t> sdir, mdir;
+      SortedView sv = make_view(S.get(), nS, kb, sdir);
+      SortedView mv = make_view(M.get(), nM, kb, mdir);
+      k_merge_place<W><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(S.get(), Sc.get(), nS, mv, E.get(), Ec.get());
+      c.check_launch("merge_s");
+      k_merge_place<W><<<grid1(nM), SDBG_BLOCK, 0, c.s>>>(M.get(), Mc.get(), nM, sv, E.get(), Ec.get());
+      c.check_launch("merge_m");
+      c.sync();
+      out->keys = E.release_ownership();
+      out->count = Ec.release_ownership();
+    }
+    c.sync();
+  }
+};
+
+}  // namespace
+
+void count_solid(const DevReads& r, const CountParams& p, Ctx& c, EdgesOut* out) {
+  switch (key_words(p.k)) {
+    case 1: Counter<1>(c).run(r, p, out); break;
+    case 2: Counter<2>(c).run(r, p, out); break;
+    case 3: Counter<3>(c).run(r, p, out); break;
+    case 4: Counter<4>(c).run(r, p, out); break;
+    default: throw Error(-1, "k out of range");
+  }
+}
+
+}  // namespace sdbg

@@ -1,0 +1,80 @@
+// Internal interface between the C ABI and the device pipeline.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "runtime.h"
+
+namespace sdbg {
+
+inline int key_words(int k) { return (2 * (k + 1) + 63) / 64; }
+
+// Reads resident on the device (borrowed).
+struct DevReads {
+  const uint8_t* seq;
+  const uint64_t* offsets;
+  uint64_t n_reads;
+  uint64_t n_bases;  // offsets[n_reads]
+};
+
+struct CountParams {
+  int k;
+  uint32_t d;
+  bool mercy;
+  int prefix_len;
+  uint64_t mem_budget;  // bytes, 0 = auto
+};
+
+// Result of counting: device arrays owned by the caller afterwards.
+struct EdgesOut {
+  uint64_t* keys = nullptr;   // n * w words
+  uint32_t* count = nullptr;  // n
+  uint64_t n = 0, n_mercy = 0, n_occ = 0;
+};
+
+struct GraphOut {
+  uint64_t m = 0, t = 0;
+  uint8_t* W = nullptr;
+  uint64_t* last = nullptr;
+  uint64_t* valid = nullptr;
+  uint64_t* tip = nullptr;
+  uint32_t* mult = nullptr;
+  uint64_t F[6] = {0, 0, 0, 0, 0, 0};
+  uint64_t* tip_seq = nullptr;
+  uint64_t tip_words = 0;
+};
+
+// Kernel timings for profiling: when enabled, kernels of the calling
+// thread's calls are bracketed by HIP events on the call's stream (no extra
+// synchronisation); elapsed times are read when the call completes.
+struct ProfRecord {
+  const char* name;
+  double ms;
+  uint64_t bytes;  // algorithmic bytes read + written by the launch
+};
+void prof_enable(bool on);
+bool prof_enabled();
+std::vector<ProfRecord>& prof_records();
+void prof_flush();  // resolve pending events (stream must be complete)
+void prof_set_last_bytes(uint64_t bytes);  // bytes of the most recent stage
+
+class Stage {
+ public:
+  Stage(Ctx& c, const char* name, uint64_t bytes);
+  ~Stage();
+  Stage(const Stage&) = delete;
+  Stage& operator=(const Stage&) = delete;
+
+ private:
+  Ctx& c_;
+  const char* name_;
+  uint64_t bytes_;
+  hipEvent_t a_ = nullptr;
+};
+
+void count_solid(const DevReads& r, const CountParams& p, Ctx& c, EdgesOut* out);
+void build_graph(const uint64_t* keys, const uint32_t* count, uint64_t n, int k, Ctx& c, GraphOut* out);
+
+}  // namespace sdbg

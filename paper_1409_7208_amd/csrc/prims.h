@@ -1,0 +1,19 @@
+// Device-wide helpers callable from host code.
+#pragma once
+
+#include "device.h"
+#include "runtime.h"
+
+namespace sdbg {
+
+// p[0..n) = v, with a kernel (no memset nodes, so the call is safe inside
+// captured graphs).
+template <typename T>
+void fill(T* p, uint64_t n, T v, Ctx& c);
+
+// out[i] = sum of in[0..i) (in-place allowed).  If d_total is non-null,
+// *d_total = sum of all n elements.
+template <typename Tin, typename Tout>
+void scan_excl(const Tin* in, Tout* out, uint64_t n, uint64_t* d_total, Ctx& c);
+
+}  // namespace sdbg

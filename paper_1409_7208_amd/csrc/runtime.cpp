@@ -1,0 +1,138 @@
+#include "runtime.h"
+
+#include "engine.h"
+
+namespace sdbg {
+
+namespace {
+constexpr int kMaxDevices = 64;
+Pool g_pools[kMaxDevices];
+
+size_t round_size(size_t b) {
+  if (b <= (1u << 20)) return (b + 255) & ~size_t(255);
+  return (b + (2u << 20) - 1) & ~size_t((2u << 20) - 1);
+}
+}  // namespace
+
+Pool& Pool::get() {
+  int dev = 0;
+  SDBG_HIP(hipGetDevice(&dev));
+  SDBG_CHECK(dev >= 0 && dev < kMaxDevices, -4, "device index out of range");
+  return g_pools[dev];
+}
+
+void* Pool::alloc(size_t bytes, hipStream_t s) {
+  size_t want = round_size(bytes);
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto it = free_.lower_bound(want); it != free_.end() && it->first <= want + want / 2 + (4u << 20); ++it) {
+      if (it->second.tagged && it->second.s != s) continue;
+      void* p = it->second.p;
+      cached_ -= it->first;
+      free_.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    trim();
+    e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(-3, "device allocation of " + std::to_string(want) + " bytes failed: " + hipGetErrorString(e));
+    }
+  }
+  std::lock_guard<std::mutex> lk(mu_);
+  size_[p] = want;
+  return p;
+}
+
+void Pool::release(void* p, hipStream_t s, bool tagged) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = size_.find(p);
+  if (it == size_.end()) return;
+  free_.emplace(it->second, Blk{p, s, tagged});
+  cached_ += it->second;
+}
+
+void Pool::untag(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(mu_);
+  for (auto& kv : free_)
+    if (kv.second.tagged && kv.second.s == s) kv.second.tagged = false;
+}
+
+void Pool::trim() {
+  std::lock_guard<std::mutex> lk(mu_);
+  for (auto it = free_.begin(); it != free_.end();) {
+    if (it->second.tagged) {
+      ++it;
+      continue;
+    }
+    (void)hipFree(it->second.p);
+    size_.erase(it->second.p);
+    cached_ -= it->first;
+    it = free_.erase(it);
+  }
+}
+
+size_t Pool::cached_bytes() {
+  std::lock_guard<std::mutex> lk(mu_);
+  return cached_;
+}
+
+}  // namespace sdbg
+
+namespace sdbg {
+
+namespace {
+struct Pending {
+  const char* name;
+  uint64_t bytes;
+  hipEvent_t a, b;
+};
+thread_local bool t_prof = false;
+thread_local std::vector<Pending> t_pending;
+thread_local std::vector<ProfRecord> t_records;
+}  // namespace
+
+void prof_enable(bool on) { t_prof = on; }
+bool prof_enabled() { return t_prof; }
+std::vector<ProfRecord>& prof_records() { return t_records; }
+
+void prof_flush() {
+  for (auto& p : t_pending) {
+    float ms = 0;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess)
+      t_records.push_back(ProfRecord{p.name, (double)ms, p.bytes});
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  t_pending.clear();
+}
+
+void prof_set_last_bytes(uint64_t bytes) {
+  if (!t_pending.empty()) t_pending.back().bytes = bytes;
+}
+
+Stage::Stage(Ctx& c, const char* name, uint64_t bytes) : c_(c), name_(name), bytes_(bytes) {
+  if (t_prof) {
+    SDBG_HIP(hipEventCreate(&a_));
+    SDBG_HIP(hipEventRecord(a_, c_.s));
+  }
+}
+
+Stage::~Stage() {
+  if (!a_) return;
+  hipEvent_t b = nullptr;
+  if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, c_.s) == hipSuccess) {
+    t_pending.push_back(Pending{name_, bytes_, a_, b});
+  } else {
+    (void)hipEventDestroy(a_);
+    if (b) (void)hipEventDestroy(b);
+  }
+}
+
+}  // namespace sdbg

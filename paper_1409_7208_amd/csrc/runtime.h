@@ -1,0 +1,158 @@
+// Host runtime for the SdBG library: error handling, a caching device
+// memory pool, and a per-call context bound to one HIP stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+namespace sdbg {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SDBG_HIP(expr)                                                                                  \
+  do {                                                                                                  \
+    hipError_t e_ = (expr);                                                                             \
+    if (e_ != hipSuccess)                                                                               \
+      throw ::sdbg::Error(-4, std::string(#expr) + ": " + hipGetErrorString(e_) + " at " + __FILE__ + \
+                                  ":" + std::to_string(__LINE__));                                      \
+  } while (0)
+
+#define SDBG_CHECK(cond, code, msg)                     \
+  do {                                                  \
+    if (!(cond)) throw ::sdbg::Error((code), (msg));    \
+  } while (0)
+
+// Caching allocator: device blocks are kept after release and handed out
+// again to requests of similar size, so that repeated calls do not pay for
+// hipMalloc/hipFree.  One pool per device.
+//
+// A released block may still be read or written by work queued on the
+// stream that used it; it is tagged with that stream and handed out again
+// only to the same stream (stream order makes that safe) until the stream
+// has been synchronised, after which untag() makes it free for any stream.
+class Pool {
+ public:
+  void* alloc(size_t bytes, hipStream_t s);
+  void release(void* p, hipStream_t s, bool tagged);
+  void untag(hipStream_t s);
+  void trim();
+  size_t cached_bytes();
+  static Pool& get();  // pool of the current device
+
+ private:
+  struct Blk {
+    void* p;
+    hipStream_t s;
+    bool tagged;
+  };
+  std::mutex mu_;
+  std::multimap<size_t, Blk> free_;
+  std::unordered_map<void*, size_t> size_;
+  size_t cached_ = 0;
+};
+
+// Device buffer owned by the calling scope, returned to the pool (tagged
+// with its stream) on destruction.
+template <typename T>
+class DBuf {
+ public:
+  DBuf() = default;
+  DBuf(size_t n, hipStream_t s) { reset(n, s); }
+  ~DBuf() { free(); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p_(o.p_), n_(o.n_), s_(o.s_) { o.p_ = nullptr; o.n_ = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      free();
+      p_ = o.p_; n_ = o.n_; s_ = o.s_;
+      o.p_ = nullptr; o.n_ = 0;
+    }
+    return *this;
+  }
+  void reset(size_t n, hipStream_t s) {
+    free();
+    n_ = n;
+    s_ = s;
+    p_ = static_cast<T*>(Pool::get().alloc(sizeof(T) * (n ? n : 1), s));
+  }
+  void free() {
+    if (p_) Pool::get().release(p_, s_, true);
+    p_ = nullptr;
+    n_ = 0;
+  }
+  T* release_ownership() {
+    T* p = p_;
+    p_ = nullptr;
+    n_ = 0;
+    return p;
+  }
+  T* get() const { return p_; }
+  size_t size() const { return n_; }
+
+ private:
+  T* p_ = nullptr;
+  size_t n_ = 0;
+  hipStream_t s_ = nullptr;
+};
+
+// Per-call context.  Declared before any DBuf of the call, so that it is
+// destroyed after them: its destructor waits for the stream (also on the
+// error path) and then frees the call's released blocks for other streams.
+struct Ctx {
+  hipStream_t s;
+  explicit Ctx(void* stream) : s(static_cast<hipStream_t>(stream)) {}
+  ~Ctx() {
+    (void)hipStreamSynchronize(s);
+    Pool::get().untag(s);
+  }
+  Ctx(const Ctx&) = delete;
+  Ctx& operator=(const Ctx&) = delete;
+  template <typename T>
+  DBuf<T> buf(size_t n) { return DBuf<T>(n, s); }
+  void sync() { SDBG_HIP(hipStreamSynchronize(s)); }
+  template <typename T>
+  T d2h_one(const T* dev) {
+    T v;
+    SDBG_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+    sync();
+    return v;
+  }
+  template <typename T>
+  void d2h(T* host, const T* dev, size_t n) {
+    if (!n) return;
+    SDBG_HIP(hipMemcpyAsync(host, dev, sizeof(T) * n, hipMemcpyDeviceToHost, s));
+    sync();
+  }
+  // Host-to-device copy; waits for it, so `host` may be released at once.
+  template <typename T>
+  void h2d(T* dev, const T* host, size_t n) {
+    if (!n) return;
+    SDBG_HIP(hipMemcpyAsync(dev, host, sizeof(T) * n, hipMemcpyHostToDevice, s));
+    sync();
+  }
+  template <typename T>
+  void d2d(T* dst, const T* src, size_t n) {
+    if (!n) return;
+    SDBG_HIP(hipMemcpyAsync(dst, src, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+  }
+  void check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error(-4, std::string("launch of ") + what + ": " + hipGetErrorString(e));
+  }
+};
+
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+}  // namespace sdbg

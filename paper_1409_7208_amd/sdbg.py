@@ -1,0 +1,298 @@
+"""ctypes binding of libsdbg.so (the C ABI declared in include/sdbg.h).
+
+Argument marshalling only: every step of the construction runs in the HIP
+library.  Device inputs are torch tensors (torch supplies device memory and
+streams); host inputs are numpy arrays.  There is no CPU fallback: if the
+library is missing, loading fails with an error.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsdbg.so")
+
+SDBG_OK = 0
+
+
+class SdbgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sdbg error {code}: {msg}")
+        self.code = code
+
+
+class _Reads(ctypes.Structure):
+    _fields_ = [
+        ("seq", ctypes.c_void_p),
+        ("offsets", ctypes.c_void_p),
+        ("n_reads", ctypes.c_uint64),
+        ("on_device", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_uint32),
+        ("d", ctypes.c_uint32),
+        ("mercy", ctypes.c_uint32),
+        ("prefix_len", ctypes.c_uint32),
+        ("mem_budget", ctypes.c_uint64),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class _Edges(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_uint32),
+        ("w", ctypes.c_uint32),
+        ("n", ctypes.c_uint64),
+        ("n_mercy", ctypes.c_uint64),
+        ("n_occ", ctypes.c_uint64),
+        ("keys", ctypes.c_void_p),
+        ("count", ctypes.c_void_p),
+    ]
+
+
+class _Graph(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_uint32),
+        ("w", ctypes.c_uint32),
+        ("m", ctypes.c_uint64),
+        ("t", ctypes.c_uint64),
+        ("W", ctypes.c_void_p),
+        ("last", ctypes.c_void_p),
+        ("valid", ctypes.c_void_p),
+        ("tip", ctypes.c_void_p),
+        ("mult", ctypes.c_void_p),
+        ("F", ctypes.c_uint64 * 6),
+        ("tip_seq", ctypes.c_void_p),
+        ("tip_words", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Loads libsdbg.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is not built; run paper_1409_7208_amd/build.py (or __graft_entry__.build())")
+    lib = ctypes.CDLL(p)
+    P = ctypes.POINTER
+    lib.sdbg_count_solid.argtypes = [P(_Reads), P(_Params), P(P(_Edges))]
+    lib.sdbg_count_solid.restype = ctypes.c_int
+    lib.sdbg_build.argtypes = [P(_Edges), P(_Params), P(P(_Graph))]
+    lib.sdbg_build.restype = ctypes.c_int
+    lib.sdbg_edges_from_host.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, P(P(_Edges))]
+    lib.sdbg_edges_from_host.restype = ctypes.c_int
+    lib.sdbg_edges_to_host.argtypes = [P(_Edges), ctypes.c_void_p, ctypes.c_void_p]
+    lib.sdbg_edges_to_host.restype = ctypes.c_int
+    lib.sdbg_graph_to_host.argtypes = [P(_Graph)] + [ctypes.c_void_p] * 6
+    lib.sdbg_graph_to_host.restype = ctypes.c_int
+    lib.sdbg_free.argtypes = [ctypes.c_void_p]
+    lib.sdbg_free.restype = None
+    lib.sdbg_last_error.argtypes = []
+    lib.sdbg_last_error.restype = ctypes.c_char_p
+    lib.sdbg_trim.argtypes = []
+    lib.sdbg_trim.restype = None
+    lib.sdbg_profile_enable.argtypes = [ctypes.c_int]
+    lib.sdbg_profile_enable.restype = None
+    lib.sdbg_profile_reset.argtypes = []
+    lib.sdbg_profile_reset.restype = None
+    lib.sdbg_profile_count.argtypes = []
+    lib.sdbg_profile_count.restype = ctypes.c_uint32
+    lib.sdbg_profile_get.argtypes = [ctypes.c_uint32, P(ctypes.c_char_p), P(ctypes.c_double), P(ctypes.c_uint64)]
+    lib.sdbg_profile_get.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != SDBG_OK:
+        raise SdbgError(rc, load().sdbg_last_error().decode(errors="replace"))
+
+
+def key_words(k: int) -> int:
+    return (2 * (k + 1) + 63) // 64
+
+
+def _stream_ptr(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Edges:
+    """Edge set E in device memory (owned; freed by close() or on GC)."""
+
+    def __init__(self, ptr):
+        self._p = ptr
+
+    @property
+    def raw(self) -> _Edges:
+        return self._p.contents
+
+    k = property(lambda s: s.raw.k)
+    w = property(lambda s: s.raw.w)
+    n = property(lambda s: s.raw.n)
+    n_mercy = property(lambda s: s.raw.n_mercy)
+    n_occ = property(lambda s: s.raw.n_occ)
+
+    def to_host(self) -> tuple[np.ndarray, np.ndarray]:
+        r = self.raw
+        keys = np.zeros(r.n * r.w + 1, dtype=np.uint64)
+        cnt = np.zeros(r.n + 1, dtype=np.uint32)
+        _check(load().sdbg_edges_to_host(self._p, keys.ctypes.data, cnt.ctypes.data))
+        return keys[: r.n * r.w].reshape(r.n, r.w), cnt[: r.n]
+
+    def close(self):
+        if self._p:
+            load().sdbg_free(ctypes.cast(self._p, ctypes.c_void_p))
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class HostGraph:
+    k: int
+    m: int
+    t: int
+    W: np.ndarray
+    last: np.ndarray
+    valid: np.ndarray
+    tip: np.ndarray
+    mult: np.ndarray
+    F: np.ndarray
+    tip_seq: np.ndarray
+
+
+class Graph:
+    """SdBG arrays in device memory (owned)."""
+
+    def __init__(self, ptr):
+        self._p = ptr
+
+    @property
+    def raw(self) -> _Graph:
+        return self._p.contents
+
+    m = property(lambda s: s.raw.m)
+    t = property(lambda s: s.raw.t)
+
+    @property
+    def F(self) -> np.ndarray:
+        return np.array(list(self.raw.F), dtype=np.uint64)
+
+    def to_host(self) -> HostGraph:
+        r = self.raw
+        words = (r.m + 63) // 64
+        W = np.zeros(r.m + 1, dtype=np.uint8)
+        last = np.zeros(words + 1, dtype=np.uint64)
+        valid = np.zeros(words + 1, dtype=np.uint64)
+        tip = np.zeros(words + 1, dtype=np.uint64)
+        mult = np.zeros(r.m + 1, dtype=np.uint32)
+        ts = np.zeros(r.tip_words + 1, dtype=np.uint64)
+        _check(load().sdbg_graph_to_host(self._p, W.ctypes.data, last.ctypes.data, valid.ctypes.data, tip.ctypes.data,
+                                         mult.ctypes.data, ts.ctypes.data))
+        return HostGraph(r.k, r.m, r.t, W[: r.m], last[:words], valid[:words], tip[:words], mult[: r.m], self.F,
+                         ts[: r.tip_words])
+
+    def close(self):
+        if self._p:
+            load().sdbg_free(ctypes.cast(self._p, ctypes.c_void_p))
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _reads_struct(seq, offsets):
+    """torch device tensors -> device pointers; numpy -> host pointers."""
+    keep = []
+    if hasattr(seq, "data_ptr"):
+        assert seq.is_cuda and offsets.is_cuda, "torch inputs must be device tensors"
+        assert seq.dtype.itemsize == 1 and offsets.dtype.itemsize == 8
+        assert seq.is_contiguous() and offsets.is_contiguous()
+        n_reads = offsets.numel() - 1
+        r = _Reads(seq.data_ptr() if seq.numel() else None, offsets.data_ptr(), n_reads, 1, 0)
+    else:
+        s = np.ascontiguousarray(seq, dtype=np.uint8)
+        o = np.ascontiguousarray(offsets, dtype=np.uint64)
+        keep += [s, o]
+        r = _Reads(s.ctypes.data if s.size else None, o.ctypes.data, o.shape[0] - 1, 0, 0)
+    return r, keep
+
+
+def count_solid(seq, offsets, k: int, d: int = 2, mercy: bool = False, prefix_len: int = 8, mem_budget: int = 0,
+                stream=None) -> Edges:
+    lib = load()
+    r, keep = _reads_struct(seq, offsets)
+    p = _Params(k, d, 1 if mercy else 0, prefix_len, mem_budget, _stream_ptr(stream))
+    out = ctypes.POINTER(_Edges)()
+    _check(lib.sdbg_count_solid(ctypes.byref(r), ctypes.byref(p), ctypes.byref(out)))
+    del keep
+    return Edges(out)
+
+
+def build(edges: Edges, stream=None) -> Graph:
+    lib = load()
+    p = _Params(edges.k, 0, 0, 0, 0, _stream_ptr(stream))
+    out = ctypes.POINTER(_Graph)()
+    _check(lib.sdbg_build(edges._p, ctypes.byref(p), ctypes.byref(out)))
+    return Graph(out)
+
+
+def edges_from_host(keys: np.ndarray, counts: np.ndarray, k: int) -> Edges:
+    lib = load()
+    w = key_words(k)
+    kk = np.ascontiguousarray(keys, dtype=np.uint64).reshape(-1, w)
+    cc = np.ascontiguousarray(counts, dtype=np.uint32)
+    out = ctypes.POINTER(_Edges)()
+    _check(lib.sdbg_edges_from_host(kk.ctypes.data if kk.size else None, cc.ctypes.data if cc.size else None,
+                                    kk.shape[0], k, ctypes.byref(out)))
+    return Edges(out)
+
+
+def trim():
+    load().sdbg_trim()
+
+
+def profile_enable(on: bool = True):
+    load().sdbg_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    load().sdbg_profile_reset()
+
+
+def profile_records() -> list[tuple[str, float, int]]:
+    """(kernel name, ms, algorithmic bytes) per profiled launch."""
+    lib = load()
+    out = []
+    for i in range(lib.sdbg_profile_count()):
+        name = ctypes.c_char_p()
+        ms = ctypes.c_double()
+        b = ctypes.c_uint64()
+        _check(lib.sdbg_profile_get(i, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(b)))
+        out.append((name.value.decode(), ms.value, b.value))
+    return out

@@ -1,0 +1,79 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/sdbg.h declares, and rejects invalid arguments before touching a
+device.  No compute call is made here."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1409_7208_amd import sdbg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _ensure_built():
+    if not os.path.exists(sdbg.LIB_PATH):
+        from paper_1409_7208_amd import build
+
+        build.build()
+
+
+def _declared_functions() -> set[str]:
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*?[\s\*]+(sdbg_[A-Za-z0-9_]+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_exports_every_declared_function():
+    _ensure_built()
+    declared = _declared_functions()
+    assert {"sdbg_count_solid", "sdbg_build", "sdbg_free", "sdbg_last_error"} <= declared
+    out = subprocess.run(["nm", "-D", "--defined-only", sdbg.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert declared <= exported, declared - exported
+    lib = sdbg.load()
+    for name in declared:
+        assert hasattr(lib, name)
+
+
+@pytest.mark.parametrize("k,d,pl,msg", [(1, 2, 8, "k must"), (128, 2, 8, "k must"), (21, 0, 8, "d must"), (21, 2, 9, "prefix_len")])
+def test_invalid_params_rejected(k, d, pl, msg):
+    _ensure_built()
+    lib = sdbg.load()
+    p = sdbg._Params(k, d, 0, pl, 0, None)
+    r = sdbg._Reads(None, None, 0, 0, 0)
+    out = ctypes.POINTER(sdbg._Edges)()
+    rc = lib.sdbg_count_solid(ctypes.byref(r), ctypes.byref(p), ctypes.byref(out))
+    assert rc == -1
+    assert msg in lib.sdbg_last_error().decode()
+    assert not out
+
+
+def test_null_arguments_rejected():
+    _ensure_built()
+    lib = sdbg.load()
+    out = ctypes.POINTER(sdbg._Edges)()
+    assert lib.sdbg_count_solid(None, None, ctypes.byref(out)) == -1
+    g = ctypes.POINTER(sdbg._Graph)()
+    assert lib.sdbg_build(None, None, ctypes.byref(g)) == -1
+    # a pointer the library never returned is not an edge set
+    fake = sdbg._Edges()
+    assert lib.sdbg_build(ctypes.byref(fake), None, ctypes.byref(g)) == -1
+    lib.sdbg_free(None)  # no-op
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    monkeypatch.setattr(sdbg, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        sdbg.load(str(tmp_path / "nope.so"))
