@@ -8,7 +8,7 @@
 #include <string>
 #include <unordered_map>
 
-#include "../../include/sdbg.h"
+#include "sdbg.h"
 #include "engine.h"
 
 namespace {

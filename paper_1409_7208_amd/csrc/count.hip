@@ -20,6 +20,9 @@
 #include "kernels.h"
 #include "prims.h"
 
+#include <cstdio>
+#include <cstdlib>
+
 namespace sdbg {
 
 // ------------------------------------------------------------ packing
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_hist_prefix(ExArgs a, unsigne
 struct SegView {
   uint64_t* off;
   uint64_t* len;
-  uint8_t* bit;
+  uint16_t* bit;  // key bits below the segment's common prefix
   uint8_t* buf;
   uint8_t* D;  // digit width of this level's cut (0 = not cut)
   uint64_t n;
@@ -439,7 +442,7 @@ __global__ void k_seg_newwrite(SegView v, int tk, const uint64_t* __restrict__ t
     if (b > a) {
       nv.off[p] = v.off[s] + a;
       nv.len[p] = b - a;
-      nv.bit[p] = (uint8_t)(v.bit[s] - D);
+      nv.bit[p] = (uint16_t)(v.bit[s] - D);
       nv.buf[p] = (uint8_t)(v.buf[s] ^ 1);
       ++p;
     }
@@ -723,6 +726,23 @@ __global__ void k_merge_place(const uint64_t* __restrict__ akeys, const uint32_t
 namespace sdbg {
 namespace {
 
+// SDBG_VERBOSE=1 in the environment traces sizes of each stage to stderr.
+bool verbose() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("SDBG_VERBOSE");
+    v = (e && *e && *e != '0') ? 1 : 0;
+  }
+  return v == 1;
+}
+#define VLOG(...)                         \
+  do {                                    \
+    if (verbose()) {                      \
+      std::fprintf(stderr, "[sdbg] " __VA_ARGS__); \
+      std::fputc('\n', stderr);          \
+    }                                     \
+  } while (0)
+
 inline unsigned grid1(uint64_t n) {
   uint64_t g = ceil_div(n, SDBG_BLOCK);
   SDBG_CHECK(g < (1ull << 31), -1, "grid too large");
@@ -731,13 +751,14 @@ inline unsigned grid1(uint64_t n) {
 
 struct SegList {
   DBuf<uint64_t> off, len;
-  DBuf<uint8_t> bit, buf, D;
+  DBuf<uint16_t> bit;
+  DBuf<uint8_t> buf, D;
   uint64_t n = 0;
   void alloc(Ctx& c, uint64_t cnt) {
     n = cnt;
     off = c.buf<uint64_t>(cnt);
     len = c.buf<uint64_t>(cnt);
-    bit = c.buf<uint8_t>(cnt);
+    bit = c.buf<uint16_t>(cnt);
     buf = c.buf<uint8_t>(cnt);
     D = c.buf<uint8_t>(cnt);
   }
@@ -753,7 +774,7 @@ __global__ void k_seg_init(const uint32_t* __restrict__ tabscan, uint64_t ntiles
   uint64_t b = d + 1 < nbins ? tabscan[(uint64_t)(d + 1) * ntiles] : total;
   v.off[d] = a;
   v.len[d] = b - a;
-  v.bit[d] = (uint8_t)bit;
+  v.bit[d] = (uint16_t)bit;
   v.buf[d] = 0;
   v.D[d] = 0;
 }
@@ -783,6 +804,8 @@ struct Counter {
       c.d2h(hs, st.get(), 2);
       if (hs[0] == 0) return;
       const uint64_t avg = hs[1] / hs[0];
+      VLOG("refine level %d: %llu segments, %llu oversized holding %llu keys", level, (unsigned long long)L.n,
+           hs[0], hs[1]);
       int D = 1;
       while (D < 8 && (avg >> D) > (uint64_t)CAP / 2) ++D;
       DBuf<uint64_t> ntiles = c.buf<uint64_t>(L.n), tabsz = c.buf<uint64_t>(L.n);
@@ -874,7 +897,8 @@ struct Counter {
     SegList L;
     L.alloc(c, 1);
     uint64_t z = 0, nn = n;
-    uint8_t bit = (uint8_t)kb, b0 = 0;
+    uint16_t bit = (uint16_t)kb;
+    uint8_t b0 = 0;
     c.h2d(L.off.get(), &z, 1);
     c.h2d(L.len.get(), &nn, 1);
     c.h2d(L.bit.get(), &bit, 1);
@@ -1099,6 +1123,24 @@ struct Counter {
       }
       scan_excl<uint64_t, uint64_t>(mcount.get(), mpos.get(), R.n_reads, tot.get(), c);
       const uint64_t NC = c.d2h_one(tot.get());
+      VLOG("mercy: %llu solid edges, %llu candidate keys", (unsigned long long)nS, (unsigned long long)NC);
+      if (const char* dd = std::getenv("SDBG_DUMP_DIR")) {  // debugging aid: intermediate arrays
+        std::vector<uint8_t> h1(nS), h2(NW);
+        std::vector<uint64_t> h3(R.n_reads);
+        c.d2h(h1.data(), sfl.get(), nS);
+        c.d2h(h2.data(), wf.get(), NW);
+        c.d2h(h3.data(), mcount.get(), R.n_reads);
+        auto dump = [&](const char* name, const void* p, size_t bytes) {
+          std::string path = std::string(dd) + "/" + name;
+          if (FILE* f = std::fopen(path.c_str(), "wb")) {
+            std::fwrite(p, 1, bytes, f);
+            std::fclose(f);
+          }
+        };
+        dump("sfl.bin", h1.data(), nS);
+        dump("wf.bin", h2.data(), NW);
+        dump("mcount.bin", h3.data(), 8 * R.n_reads);
+      }
       if (NC) {
         DBuf<uint64_t> cand = c.buf<uint64_t>(NC * W);
         {
@@ -1108,6 +1150,7 @@ struct Counter {
         }
         wf.free();
         sort_unique(cand, NC, kb, M, &nM);
+        VLOG("mercy: %llu distinct mercy edges", (unsigned long long)nM);
         Mc = c.buf<uint32_t>(nM);
         if (P.d <= 2) {
           fill<uint32_t>(Mc.get(), nM, 1u, c);

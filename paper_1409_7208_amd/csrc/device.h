@@ -8,7 +8,8 @@
 #define SDBG_BLOCK 256
 #define SDBG_WAVES (SDBG_BLOCK / 64)
 
-#define DEV __device__ __forceinline__
+// Host-callable as well, so that the key arithmetic can be checked on the CPU.
+#define DEV __host__ __device__ __forceinline__
 
 // A key of W 64-bit words; w[0] is the most significant word, the same
 // order as in memory.  Indices into w[] are always compile-time constants

@@ -87,8 +87,13 @@ class DBuf {
     s_ = s;
     p_ = static_cast<T*>(Pool::get().alloc(sizeof(T) * (n ? n : 1), s));
   }
-  void free() {
-    if (p_) Pool::get().release(p_, s_, true);
+  void free() noexcept {
+    if (p_) {
+      try {
+        Pool::get().release(p_, s_, true);
+      } catch (...) {
+      }
+    }
     p_ = nullptr;
     n_ = 0;
   }
@@ -115,7 +120,10 @@ struct Ctx {
   explicit Ctx(void* stream) : s(static_cast<hipStream_t>(stream)) {}
   ~Ctx() {
     (void)hipStreamSynchronize(s);
-    Pool::get().untag(s);
+    try {
+      Pool::get().untag(s);
+    } catch (...) {
+    }
   }
   Ctx(const Ctx&) = delete;
   Ctx& operator=(const Ctx&) = delete;
