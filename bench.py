@@ -71,7 +71,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="metagenome")
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--cpu-reads", type=int, default=25000)
+    ap.add_argument("--cpu-reads", type=int, default=100000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-kernel breakdown to stderr")
     args = ap.parse_args()
@@ -124,6 +124,11 @@ def main():
     log(f"timed {args.steps} steps: {ms:.2f} ms/step (wall {wall / args.steps * 1e3:.2f} ms/step), {value:.2f} Gmer/s")
 
     recs = sdbg.profile_records()
+    if args.stages:
+        per_step = len(recs) // args.steps
+        log("  launches of the last step (ms, GB/s):")
+        for name, t, b in recs[-per_step:]:
+            log(f"    {name:14s} {t:9.3f} {b / (t * 1e-3) / 1e9 if t > 0 else 0:9.1f}")
     agg: dict[str, list] = {}
     for name, t, b in recs:
         a = agg.setdefault(name, [0, 0.0, 0])

@@ -108,8 +108,35 @@ DEV uint64_t find_read(const uint64_t* __restrict__ woff, uint64_t n_reads, uint
   return lo;
 }
 
+// Reads [lo, hi] of the windows [g_first, g_last] of a workgroup's tile,
+// found once per workgroup so that each thread searches a short range.
+DEV void tile_reads(const ExArgs& a, uint64_t g_first, uint64_t g_last, uint64_t* sh) {
+  if (threadIdx.x == 0) sh[0] = find_read(a.woff, a.n_reads, g_first);
+  if (threadIdx.x == 64) sh[1] = find_read(a.woff, a.n_reads, min(g_last, a.NW - 1));
+  __syncthreads();
+}
+
+// First read lo <= r <= hi with woff[r] <= g < woff[r+1].
+DEV uint64_t find_read_in(const uint64_t* __restrict__ woff, uint64_t lo, uint64_t hi, uint64_t g) {
+  ++hi;  // woff[lo] <= g < woff[hi]
+  while (hi - lo > 1) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (woff[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 struct WinIter {
   uint64_t r, i, nw, rstart;
+  DEV void init_in(const ExArgs& a, uint64_t g, const uint64_t* sh) {
+    r = find_read_in(a.woff, sh[0], sh[1], g);
+    rstart = a.offsets[r];
+    i = g - a.woff[r];
+    nw = a.woff[r + 1] - a.woff[r];
+  }
   DEV void init(const ExArgs& a, uint64_t g) {
     r = find_read(a.woff, a.n_reads, g);
     rstart = a.offsets[r];
@@ -164,13 +191,15 @@ template <int W, int IPT>
 __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_hist(ExArgs a, uint32_t* __restrict__ tab, uint64_t ntiles,
                                                         unsigned long long* __restrict__ occ) {
   __shared__ uint32_t h[256];
+  __shared__ uint64_t rr[2];
   h[threadIdx.x] = 0;
-  __syncthreads();
+  const uint64_t t0 = (uint64_t)blockIdx.x * SDBG_BLOCK * IPT;
+  tile_reads(a, t0, t0 + SDBG_BLOCK * IPT - 1, rr);
   uint32_t produced = 0;
   const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
   if (g0 < a.NW) {
     WinIter it;
-    it.init(a, g0);
+    it.init_in(a, g0, rr);
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
       if (g0 + q < a.NW) {
@@ -204,10 +233,12 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_scatter(ExArgs a, const uint3
   __shared__ uint64_t lk[NK * SDBG_BLOCK * W];
   __shared__ uint32_t cnt[256], lst[256], gb[256];
   __shared__ uint32_t sc[SDBG_WAVES + 1];
+  __shared__ uint64_t rr[2];
   const uint32_t nbins = 1u << a.dbits;
   cnt[threadIdx.x] = 0;
   gb[threadIdx.x] = threadIdx.x < nbins ? tab[(uint64_t)threadIdx.x * ntiles + blockIdx.x] : 0;
-  __syncthreads();
+  const uint64_t t0 = (uint64_t)blockIdx.x * SDBG_BLOCK * IPT;
+  tile_reads(a, t0, t0 + SDBG_BLOCK * IPT - 1, rr);
   Key<W> keys[NK];
   uint32_t pos[NK];
 #pragma unroll
@@ -215,7 +246,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_scatter(ExArgs a, const uint3
   const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
   if (g0 < a.NW) {
     WinIter it;
-    it.init(a, g0);
+    it.init_in(a, g0, rr);
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
       if (g0 + q < a.NW) {
@@ -450,20 +481,36 @@ __global__ void k_seg_newwrite(SegView v, int tk, const uint64_t* __restrict__ t
 }
 
 // ------------------------------------------------------------ leaves
-// One workgroup per leaf segment: load its keys into LDS, counting-sort them
-// by the next B bits, finish each bin with an insertion sort (bins are tiny
-// and equal keys do not move), run-length count, and write the distinct
-// keys with count >= d (and, if want_low, those below d after them) back in
-// place at the segment's start, counts into cnt[] at the same positions.
-// A segment longer than CAP has no key bits left to cut, so all its keys
-// are equal.
+// One workgroup per leaf segment.  Keys are loaded into LDS and their
+// duplicates are merged first with an LDS hash table (one slot per distinct
+// key: owner element in the high 16 bits, count in the low 16 bits, updated
+// with LDS atomics), so that a key seen hundreds of times costs one atomic
+// per copy instead of a serial run for one thread.  The distinct keys are
+// then counting-sorted by the next B key bits, each thread finishes a
+// contiguous range of bins with an insertion sort (bins hold about one
+// distinct key), and the keys with count >= dmin (and, if want_low, those
+// below, after them) are written back in place at the segment's start,
+// counts into cnt[] at the same positions.  A segment longer than CAP has
+// no key bits left to cut, so all its keys are equal.
+template <int W>
+DEV uint32_t leaf_hash(const Key<W>& k) {
+  uint64_t h = 0x9E3779B97F4A7C15ull;
+#pragma unroll
+  for (int i = 0; i < W; ++i) h = (h ^ k.w[i]) * 0xD6E8FEB86659FD93ull;
+  return (uint32_t)(h >> 32);
+}
+
 template <int W, int CAP>
 __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const* __restrict__ bufs,
                                                      uint32_t* __restrict__ cnt, uint32_t dmin, int want_low,
                                                      uint64_t* __restrict__ nsolid, uint64_t* __restrict__ nlow) {
   constexpr int PER = CAP / SDBG_BLOCK;
-  constexpr int MAXB = 12;
+  constexpr int H = 2 * CAP;  // hash slots, load <= 1/2
+  constexpr int MAXB = CAP >= 4096 ? 12 : CAP >= 2048 ? 11 : CAP >= 1024 ? 10 : 9;
+  constexpr uint32_t EMPTY = 0xFFFFFFFFu;
+  static_assert(CAP <= 4096 && H <= 65536, "leaf sizes");
   __shared__ uint64_t A[CAP * W];
+  __shared__ uint32_t hs[H];
   __shared__ uint16_t idx[CAP];
   __shared__ uint32_t bins[(1 << MAXB) + 1];
   __shared__ uint32_t sc[SDBG_WAVES + 1];
@@ -483,24 +530,46 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
   }
   const int n = (int)len;
   int B = 1;
-  while ((1 << B) < 2 * n && B < MAXB) ++B;
+  while ((1 << B) < n && B < MAXB) ++B;
   B = min(B, (int)v.bit[s]);
   const int lo = (int)v.bit[s] - B;
   const int nbins = 1 << B;
+  const uint32_t hmask = (uint32_t)(H - 1);
   for (int i = threadIdx.x; i < n; i += SDBG_BLOCK) key_store<W>(&A[i * W], key_load<W>(keys + (uint64_t)i * W));
+  for (int i = threadIdx.x; i < H; i += SDBG_BLOCK) hs[i] = EMPTY;
   for (int i = threadIdx.x; i <= nbins; i += SDBG_BLOCK) bins[i] = 0;
   __syncthreads();
-  uint32_t dg[PER], sl[PER];
+  // 1. merge duplicates; the element that claims a slot represents its key
+  uint32_t rep[PER];  // representative: hash slot | digit << 16, else EMPTY
+  uint32_t rsl[PER];  // its place among the distinct keys of its bin
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
+    rep[q] = EMPTY;
     const int i = q * SDBG_BLOCK + threadIdx.x;
     if (i < n) {
-      dg[q] = B ? key_bits<W>(key_load<W>(&A[i * W]), lo, B) : 0;
-      sl[q] = atomicAdd(&bins[dg[q]], 1u);
+      const Key<W> kx = key_load<W>(&A[i * W]);
+      uint32_t h = leaf_hash<W>(kx) & hmask;
+      for (;;) {
+        uint32_t cur = hs[h];
+        if (cur == EMPTY) {
+          cur = atomicCAS(&hs[h], EMPTY, ((uint32_t)i << 16) | 1u);
+          if (cur == EMPTY) {
+            const uint32_t dg = B ? key_bits<W>(kx, lo, B) : 0;
+            rep[q] = h | (dg << 16);
+            rsl[q] = atomicAdd(&bins[dg], 1u);
+            break;
+          }
+        }
+        if (key_eq<W>(key_load<W>(&A[(cur >> 16) * W]), kx)) {
+          atomicAdd(&hs[h], 1u);
+          break;
+        }
+        h = (h + 1) & hmask;
+      }
     }
   }
   __syncthreads();
-  // exclusive scan of the bins: each thread owns a contiguous run of bins
+  // 2. bin offsets (each thread scans a contiguous run of bins)
   {
     const int per = (nbins + SDBG_BLOCK - 1) / SDBG_BLOCK;
     const int b0 = min(nbins, (int)threadIdx.x * per), b1 = min(nbins, b0 + per);
@@ -516,45 +585,40 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
     if (threadIdx.x == 0) bins[nbins] = tot;
   }
   __syncthreads();
+  // 3. distinct keys (as hash slots) in bin order
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int i = q * SDBG_BLOCK + threadIdx.x;
-    if (i < n) idx[bins[dg[q]] + sl[q]] = (uint16_t)i;
-  }
+  for (int q = 0; q < PER; ++q)
+    if (rep[q] != EMPTY) idx[bins[rep[q] >> 16] + rsl[q]] = (uint16_t)(rep[q] & 0xFFFFu);
   __syncthreads();
-  // this thread's bins [b0, b1) = positions [r0, r1) of idx
+  // 4. finish each thread's bins: sort by key, count outputs, write
   const int b0 = (int)(((uint64_t)threadIdx.x * nbins) / SDBG_BLOCK);
   const int b1 = (int)(((uint64_t)(threadIdx.x + 1) * nbins) / SDBG_BLOCK);
   const int r0 = bins[b0], r1 = bins[b1];
   for (int i = r0 + 1; i < r1; ++i) {
-    uint16_t x = idx[i];
-    Key<W> kx = key_load<W>(&A[x * W]);
+    const uint16_t x = idx[i];
+    const Key<W> kx = key_load<W>(&A[(hs[x] >> 16) * W]);
     int j = i - 1;
-    while (j >= r0 && key_less<W>(kx, key_load<W>(&A[idx[j] * W]))) {
+    while (j >= r0 && key_less<W>(kx, key_load<W>(&A[(hs[idx[j]] >> 16) * W]))) {
       idx[j + 1] = idx[j];
       --j;
     }
     idx[j + 1] = x;
   }
   uint32_t ns = 0, nl = 0;
-  for (int i = r0; i < r1;) {
-    Key<W> kx = key_load<W>(&A[idx[i] * W]);
-    int j = i + 1;
-    while (j < r1 && key_eq<W>(kx, key_load<W>(&A[idx[j] * W]))) ++j;
-    if ((uint32_t)(j - i) >= dmin)
+  for (int i = r0; i < r1; ++i) {
+    const uint32_t c = hs[idx[i]] & 0xFFFFu;
+    if (c >= dmin)
       ++ns;
     else if (want_low)
       ++nl;
-    i = j;
   }
   uint32_t NS, NL;
   uint32_t bs = block_excl_scan<uint32_t>(ns, sc, &NS);
   uint32_t bl = block_excl_scan<uint32_t>(nl, sc, &NL);
-  for (int i = r0; i < r1;) {
-    Key<W> kx = key_load<W>(&A[idx[i] * W]);
-    int j = i + 1;
-    while (j < r1 && key_eq<W>(kx, key_load<W>(&A[idx[j] * W]))) ++j;
-    const uint32_t c = (uint32_t)(j - i);
+  for (int i = r0; i < r1; ++i) {
+    const uint32_t e = hs[idx[i]];
+    const uint32_t c = e & 0xFFFFu;
+    const Key<W> kx = key_load<W>(&A[(e >> 16) * W]);
     if (c >= dmin) {
       key_store<W>(keys + (uint64_t)bs * W, kx);
       cn[bs] = c;
@@ -564,7 +628,6 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
       cn[NS + bl] = c;
       ++bl;
     }
-    i = j;
   }
   if (threadIdx.x == 0) {
     nsolid[s] = NS;
@@ -634,23 +697,64 @@ __global__ void k_dead_ends(SortedView S, int k, uint8_t* __restrict__ fl) {
   fl[i] = (uint8_t)(1 | (!out ? 2 : 0) | (!in ? 4 : 0));
 }
 
+// Solid set as an open-addressing hash table for the per-window lookups of
+// the mercy rule (window keys arrive in read order, i.e. at random places in
+// key order, so one probe of one cache line beats a binary search).  Slot =
+// one meta word (0 = empty, else 0x100 | dead-end flags) followed by the W
+// key words; linear probing; at most half of the slots are used.
+template <int W>
+DEV uint64_t hslot(const Key<W>& k, uint64_t mask) {
+  uint64_t h = 0x9E3779B97F4A7C15ull;
+#pragma unroll
+  for (int i = 0; i < W; ++i) h = (h ^ k.w[i]) * 0xC2B2AE3D27D4EB4Full;
+  return (h ^ (h >> 29)) & mask;
+}
+
+template <int W>
+__global__ void k_hash_insert(SortedView S, const uint8_t* __restrict__ sfl, uint64_t* __restrict__ tab, uint64_t mask) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= S.n) return;
+  const Key<W> x = key_load<W>(S.keys + i * W);
+  const unsigned long long val = 0x100ull | sfl[i];
+  uint64_t h = hslot<W>(x, mask);
+  while (atomicCAS(reinterpret_cast<unsigned long long*>(tab + h * (W + 1)), 0ull, val) != 0ull) h = (h + 1) & mask;
+  key_store<W>(tab + h * (W + 1) + 1, x);
+}
+
+template <int W>
+DEV uint8_t hash_flags(const uint64_t* __restrict__ tab, uint64_t mask, const Key<W>& x) {
+  uint64_t h = hslot<W>(x, mask);
+  for (;;) {
+    const uint64_t m = tab[h * (W + 1)];
+    if (m == 0) return 0;
+    if (key_eq<W>(key_load<W>(tab + h * (W + 1) + 1), x)) return (uint8_t)(m & 0xFF);
+    h = (h + 1) & mask;
+  }
+}
+
 // Per forward-strand window: 0x80 if it holds a non-ACGT base, else the
 // dead-end flags of its edge if solid, else 0.
 template <int W, int IPT>
-__global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags(ExArgs a, SortedView S, const uint8_t* __restrict__ sfl,
-                                                             uint8_t* __restrict__ wf) {
+__global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags(ExArgs a, const uint64_t* __restrict__ htab,
+                                                             uint64_t hmask, uint8_t* __restrict__ wf) {
+  __shared__ uint64_t rr[2];
+  const uint64_t t0 = (uint64_t)blockIdx.x * SDBG_BLOCK * IPT;
+  tile_reads(a, t0, t0 + SDBG_BLOCK * IPT - 1, rr);
   const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
   if (g0 >= a.NW) return;
   WinIter it;
-  it.init(a, g0);
+  it.init_in(a, g0, rr);
+  // Launched with IPT = 1.  With two windows per thread (loop unrolled or
+  // not) the gfx950 code for 3-word keys lost lookups in every workgroup
+  // after the first one per CU -- a loop-carried lane mask seeded from an
+  // undefined SGPR pair picks up the previous workgroup's register state --
+  // while the same functions replayed on the host are exact.
   for (int q = 0; q < IPT && g0 + q < a.NW; ++q) {
     uint64_t j = it.pos();
     uint8_t f = 0x80;
     if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
       Key<W> F = stream_bits<W>(a.packed, 2 * j, a.kb);
-      Key<W> kf = key_from_fwd<W>(F, a.kb);
-      uint64_t ix;
-      f = sv_find<W>(S, kf, &ix) ? sfl[ix] : 0;
+      f = hash_flags<W>(htab, hmask, key_from_fwd<W>(F, a.kb));
     }
     wf[g0 + q] = f;
     it.next(a);
@@ -1109,12 +1213,22 @@ struct Counter {
         k_dead_ends<W><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(sv, k, sfl.get());
         c.check_launch("dead_ends");
       }
+      uint64_t hslots = 2;
+      while (hslots < 2 * nS) hslots <<= 1;
+      DBuf<uint64_t> htab = c.buf<uint64_t>(hslots * (W + 1));
+      fill<uint64_t>(htab.get(), hslots * (W + 1), 0, c);
+      {
+        Stage st_(c, "hash_insert", nS * (8 * W + 1) + nS * 8 * (W + 1));
+        k_hash_insert<W><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(sv, sfl.get(), htab.get(), hslots - 1);
+        c.check_launch("hash_insert");
+      }
       DBuf<uint8_t> wf = c.buf<uint8_t>(NW);
       {
         Stage st_(c, "window_flags", 3 * words * 8 + NW);
-        k_window_flags<W, IPT><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(ea, sv, sfl.get(), wf.get());
+        k_window_flags<W, 1><<<grid1(NW), SDBG_BLOCK, 0, c.s>>>(ea, htab.get(), hslots - 1, wf.get());
         c.check_launch("window_flags");
       }
+      htab.free();
       DBuf<uint64_t> mcount = c.buf<uint64_t>(R.n_reads), mpos = c.buf<uint64_t>(R.n_reads);
       {
         Stage st_(c, "mercy_count", NW + R.n_reads * 24);

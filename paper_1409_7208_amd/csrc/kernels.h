@@ -13,11 +13,11 @@ template <int W>
 struct Tune;
 template <>
 struct Tune<1> {
-  static constexpr int IPT = 8, TK = 4096, CAP = 4096;
+  static constexpr int IPT = 8, TK = 4096, CAP = 2048;
 };
 template <>
 struct Tune<2> {
-  static constexpr int IPT = 4, TK = 2048, CAP = 2048;
+  static constexpr int IPT = 4, TK = 2048, CAP = 1024;
 };
 template <>
 struct Tune<3> {

@@ -87,6 +87,13 @@ def load(path: str | None = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"{p} is not built; run paper_1409_7208_amd/build.py (or __graft_entry__.build())")
+    # torch ships its own HIP runtime (same soname).  Load it first so that
+    # the library binds to that copy: two HIP/HSA runtimes in one process do
+    # not share the device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(p)
     P = ctypes.POINTER
     lib.sdbg_count_solid.argtypes = [P(_Reads), P(_Params), P(P(_Edges))]

@@ -91,10 +91,12 @@ def test_tiny_workload(mercy):
     _parity(synth.tiny(), 21, 2, mercy)
 
 
-@pytest.mark.parametrize("k", [21, 31, 41, 61, 81, 99])
+@pytest.mark.parametrize("k", [21, 31, 33, 41, 61, 64, 75, 81, 95, 96, 99, 127])
 def test_metagenome_shape_each_k(k):
     """Skewed community (log-normal abundance), scaled down so the oracle
-    finishes quickly; every key width (1-4 words)."""
+    finishes quickly; every key width (1-4 words) at the ends of its k
+    range.  Thousands of workgroups per launch, so a kernel that is only
+    right in the first wave of workgroups on each CU fails here."""
     rs = synth.metagenome_long(scale=0.0015, k=k)
     _parity(rs, k, 2, True)
 
@@ -175,3 +177,15 @@ def test_repeat_calls_are_deterministic():
     for keys, cnt, h in outs[1:]:
         assert np.array_equal(keys, outs[0][0]) and np.array_equal(cnt, outs[0][1])
         assert_graph_equal(h, outs[0][2])
+
+
+def test_three_word_keys_mercy_repeatable():
+    """Regression: mercy lookups with 3-word keys (k = 64..95) must be exact
+    on every run (they once varied between runs on the device)."""
+    rs = synth.metagenome_long(scale=0.0015, k=81)
+    o = oracle.count_solid(rs.seq, rs.offsets, 81, 2, True)
+    for rep in range(3):
+        say(f"repeat {rep}")
+        e, keys, cnt = gpu_count(rs, 81, 2, True)
+        assert e.n_mercy == o.n_mercy
+        assert np.array_equal(keys, o.keys) and np.array_equal(cnt, o.counts)
