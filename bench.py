@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--cpu-reads", type=int, default=100000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-kernel breakdown to stderr")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (a reference kernel for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it", "n_gpus": args.gpus}))
@@ -92,6 +94,12 @@ def main():
     off = torch.from_numpy(rs.offsets.view(np.int64)).to("cuda:0")
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    if args.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.int64, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         e = sdbg.count_solid(seq, off, rs.k, rs.d, rs.mercy, stream=stream)

@@ -94,7 +94,19 @@ struct ExArgs {
   int pb;             // prefix bits used by the group filter
   uint32_t glo, ghi;  // keep keys whose top pb bits are in [glo, ghi)
   int dlo, dbits;     // partition digit = bits [dlo, dlo + dbits)
+  const uint64_t* tr; // tr[t] = read holding window t*TR_GRAIN (last entry: n_reads - 1)
 };
+
+// Granularity of the window -> read table.
+constexpr uint64_t TR_GRAIN = 256;
+
+// tr[t] = read containing window t * TR_GRAIN; one thread per read.
+__global__ void k_tile_reads(const uint64_t* __restrict__ woff, uint64_t n_reads, uint64_t* __restrict__ tr) {
+  uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (r >= n_reads) return;
+  const uint64_t a = woff[r], b = woff[r + 1];
+  for (uint64_t t = (a + TR_GRAIN - 1) / TR_GRAIN; t * TR_GRAIN < b; ++t) tr[t] = r;
+}
 
 DEV uint64_t find_read(const uint64_t* __restrict__ woff, uint64_t n_reads, uint64_t g) {
   uint64_t lo = 0, hi = n_reads;  // woff[lo] <= g < woff[hi]
@@ -106,14 +118,6 @@ DEV uint64_t find_read(const uint64_t* __restrict__ woff, uint64_t n_reads, uint
       hi = mid;
   }
   return lo;
-}
-
-// Reads [lo, hi] of the windows [g_first, g_last] of a workgroup's tile,
-// found once per workgroup so that each thread searches a short range.
-DEV void tile_reads(const ExArgs& a, uint64_t g_first, uint64_t g_last, uint64_t* sh) {
-  if (threadIdx.x == 0) sh[0] = find_read(a.woff, a.n_reads, g_first);
-  if (threadIdx.x == 64) sh[1] = find_read(a.woff, a.n_reads, min(g_last, a.NW - 1));
-  __syncthreads();
 }
 
 // First read lo <= r <= hi with woff[r] <= g < woff[r+1].
@@ -131,18 +135,16 @@ DEV uint64_t find_read_in(const uint64_t* __restrict__ woff, uint64_t lo, uint64
 
 struct WinIter {
   uint64_t r, i, nw, rstart;
-  DEV void init_in(const ExArgs& a, uint64_t g, const uint64_t* sh) {
-    r = find_read_in(a.woff, sh[0], sh[1], g);
-    rstart = a.offsets[r];
-    i = g - a.woff[r];
-    nw = a.woff[r + 1] - a.woff[r];
-  }
+  // The read of window g lies between the reads of the first windows of its
+  // granule and of the next granule.
   DEV void init(const ExArgs& a, uint64_t g) {
-    r = find_read(a.woff, a.n_reads, g);
+    const uint64_t t = g / TR_GRAIN;
+    r = find_read_in(a.woff, a.tr[t], a.tr[t + 1], g);
     rstart = a.offsets[r];
     i = g - a.woff[r];
     nw = a.woff[r + 1] - a.woff[r];
   }
+
   DEV uint64_t pos() const { return rstart + i; }
   DEV void next(const ExArgs& a) {
     ++i;
@@ -186,20 +188,19 @@ DEV bool ex_pass(const ExArgs& a, const Key<W>& key) {
 }
 
 // Histogram of the partition digit per tile of 256*IPT windows, written
-// digit-major: tab[d * ntiles + tile].  Also counts produced occurrences.
+// digit-major: tab[d * ntiles + tile].  If occ is given, also counts the
+// produced occurrences (one global atomic per wave; only for diagnostics).
 template <int W, int IPT>
 __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_hist(ExArgs a, uint32_t* __restrict__ tab, uint64_t ntiles,
                                                         unsigned long long* __restrict__ occ) {
   __shared__ uint32_t h[256];
-  __shared__ uint64_t rr[2];
   h[threadIdx.x] = 0;
-  const uint64_t t0 = (uint64_t)blockIdx.x * SDBG_BLOCK * IPT;
-  tile_reads(a, t0, t0 + SDBG_BLOCK * IPT - 1, rr);
+  __syncthreads();
   uint32_t produced = 0;
   const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
   if (g0 < a.NW) {
     WinIter it;
-    it.init_in(a, g0, rr);
+    it.init(a, g0);
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
       if (g0 + q < a.NW) {
@@ -233,12 +234,10 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_scatter(ExArgs a, const uint3
   __shared__ uint64_t lk[NK * SDBG_BLOCK * W];
   __shared__ uint32_t cnt[256], lst[256], gb[256];
   __shared__ uint32_t sc[SDBG_WAVES + 1];
-  __shared__ uint64_t rr[2];
   const uint32_t nbins = 1u << a.dbits;
   cnt[threadIdx.x] = 0;
   gb[threadIdx.x] = threadIdx.x < nbins ? tab[(uint64_t)threadIdx.x * ntiles + blockIdx.x] : 0;
-  const uint64_t t0 = (uint64_t)blockIdx.x * SDBG_BLOCK * IPT;
-  tile_reads(a, t0, t0 + SDBG_BLOCK * IPT - 1, rr);
+  __syncthreads();
   Key<W> keys[NK];
   uint32_t pos[NK];
 #pragma unroll
@@ -246,7 +245,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_scatter(ExArgs a, const uint3
   const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
   if (g0 < a.NW) {
     WinIter it;
-    it.init_in(a, g0, rr);
+    it.init(a, g0);
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
       if (g0 + q < a.NW) {
@@ -321,10 +320,16 @@ struct SegView {
 
 __global__ void k_seg_stats(SegView v, uint64_t cap, unsigned long long* st) {
   uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (s >= v.n) return;
-  if (v.len[s] > cap && v.bit[s] > 0) {
-    atomicAdd(&st[0], 1ull);
-    atomicAdd(&st[1], (unsigned long long)v.len[s]);
+  unsigned long long n = 0, sum = 0;
+  if (s < v.n && v.len[s] > cap && v.bit[s] > 0) {
+    n = 1;
+    sum = v.len[s];
+  }
+  n = wave_sum(n);
+  sum = wave_sum(sum);
+  if ((threadIdx.x & 63) == 0 && n) {
+    atomicAdd(&st[0], n);
+    atomicAdd(&st[1], sum);
   }
 }
 
@@ -494,16 +499,17 @@ __global__ void k_seg_newwrite(SegView v, int tk, const uint64_t* __restrict__ t
 // no key bits left to cut, so all its keys are equal.
 template <int W>
 DEV uint32_t leaf_hash(const Key<W>& k) {
-  uint64_t h = 0x9E3779B97F4A7C15ull;
+  uint32_t h = 0;
 #pragma unroll
-  for (int i = 0; i < W; ++i) h = (h ^ k.w[i]) * 0xD6E8FEB86659FD93ull;
-  return (uint32_t)(h >> 32);
+  for (int i = 0; i < W; ++i) h ^= (uint32_t)k.w[i] ^ (uint32_t)(k.w[i] >> 32) * 0x85EBCA6Bu;
+  return h * 0x9E3779B1u;
 }
 
 template <int W, int CAP>
 __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const* __restrict__ bufs,
                                                      uint32_t* __restrict__ cnt, uint32_t dmin, int want_low,
-                                                     uint64_t* __restrict__ nsolid, uint64_t* __restrict__ nlow) {
+                                                     uint64_t* __restrict__ nsolid, uint64_t* __restrict__ nlow,
+                                                     unsigned long long* __restrict__ work) {
   constexpr int PER = CAP / SDBG_BLOCK;
   constexpr int H = 2 * CAP;  // hash slots, load <= 1/2
   constexpr int MAXB = CAP >= 4096 ? 12 : CAP >= 2048 ? 11 : CAP >= 1024 ? 10 : 9;
@@ -514,7 +520,17 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
   __shared__ uint16_t idx[CAP];
   __shared__ uint32_t bins[(1 << MAXB) + 1];
   __shared__ uint32_t sc[SDBG_WAVES + 1];
-  const uint64_t s = blockIdx.x;
+  __shared__ uint64_t next_seg;
+  for (;;) {
+  // Persistent: workgroups take segments from a counter until none is left
+  // (the exit test is uniform across the workgroup).
+  __syncthreads();
+  if (threadIdx.x == 0) next_seg = atomicAdd(work, 1ull);
+  __syncthreads();
+  // uniform across the workgroup: keep it in scalar registers
+  const uint64_t s = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(next_seg >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)next_seg);
+  if (s >= v.n) break;
   const uint64_t len = v.len[s];
   uint64_t* keys = bufs[v.buf[s]] + v.off[s] * W;
   uint32_t* cn = cnt + v.off[s];
@@ -526,37 +542,29 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
       nsolid[s] = solid;
       nlow[s] = !solid && want_low;
     }
-    return;
+    continue;
   }
   const int n = (int)len;
-  int B = 1;
-  while ((1 << B) < n && B < MAXB) ++B;
-  B = min(B, (int)v.bit[s]);
-  const int lo = (int)v.bit[s] - B;
-  const int nbins = 1 << B;
-  const uint32_t hmask = (uint32_t)(H - 1);
+  const uint32_t hshift = 32 - (uint32_t)__builtin_ctz((uint32_t)H);
   for (int i = threadIdx.x; i < n; i += SDBG_BLOCK) key_store<W>(&A[i * W], key_load<W>(keys + (uint64_t)i * W));
   for (int i = threadIdx.x; i < H; i += SDBG_BLOCK) hs[i] = EMPTY;
-  for (int i = threadIdx.x; i <= nbins; i += SDBG_BLOCK) bins[i] = 0;
   __syncthreads();
   // 1. merge duplicates; the element that claims a slot represents its key
-  uint32_t rep[PER];  // representative: hash slot | digit << 16, else EMPTY
-  uint32_t rsl[PER];  // its place among the distinct keys of its bin
+  uint32_t rep[PER];  // representative's hash slot (| digit << 16 once binned), else EMPTY
+  uint32_t rsl[PER];  // its place among the output keys of its bin
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     rep[q] = EMPTY;
     const int i = q * SDBG_BLOCK + threadIdx.x;
     if (i < n) {
       const Key<W> kx = key_load<W>(&A[i * W]);
-      uint32_t h = leaf_hash<W>(kx) & hmask;
+      uint32_t h = leaf_hash<W>(kx) >> hshift;
       for (;;) {
         uint32_t cur = hs[h];
         if (cur == EMPTY) {
           cur = atomicCAS(&hs[h], EMPTY, ((uint32_t)i << 16) | 1u);
           if (cur == EMPTY) {
-            const uint32_t dg = B ? key_bits<W>(kx, lo, B) : 0;
-            rep[q] = h | (dg << 16);
-            rsl[q] = atomicAdd(&bins[dg], 1u);
+            rep[q] = h;
             break;
           }
         }
@@ -564,12 +572,37 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
           atomicAdd(&hs[h], 1u);
           break;
         }
-        h = (h + 1) & hmask;
+        h = (h + 1) & (uint32_t)(H - 1);
       }
     }
   }
   __syncthreads();
-  // 2. bin offsets (each thread scans a contiguous run of bins)
+  // 2. only keys that will be written are sorted: drop the others, count
+  uint32_t nout = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if (rep[q] != EMPTY && !want_low && (hs[rep[q]] & 0xFFFFu) < dmin) rep[q] = EMPTY;
+    nout += rep[q] != EMPTY;
+  }
+  uint32_t T;
+  (void)block_excl_scan<uint32_t>(nout, sc, &T);
+  int B = 0;
+  while ((1u << B) < T && B < MAXB) ++B;
+  B = min(B, (int)v.bit[s]);
+  const int lo = (int)v.bit[s] - B;
+  const int nbins = 1 << B;
+  for (int i = threadIdx.x; i <= nbins; i += SDBG_BLOCK) bins[i] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if (rep[q] != EMPTY) {
+      const uint32_t dg = B ? key_bits<W>(key_load<W>(&A[(hs[rep[q]] >> 16) * W]), lo, B) : 0;
+      rsl[q] = atomicAdd(&bins[dg], 1u);
+      rep[q] |= dg << 16;
+    }
+  }
+  __syncthreads();
+  // 3. bin offsets (each thread scans a contiguous run of bins)
   {
     const int per = (nbins + SDBG_BLOCK - 1) / SDBG_BLOCK;
     const int b0 = min(nbins, (int)threadIdx.x * per), b1 = min(nbins, b0 + per);
@@ -585,7 +618,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
     if (threadIdx.x == 0) bins[nbins] = tot;
   }
   __syncthreads();
-  // 3. distinct keys (as hash slots) in bin order
+  // output keys (as hash slots) in bin order
 #pragma unroll
   for (int q = 0; q < PER; ++q)
     if (rep[q] != EMPTY) idx[bins[rep[q] >> 16] + rsl[q]] = (uint16_t)(rep[q] & 0xFFFFu);
@@ -632,6 +665,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
   if (threadIdx.x == 0) {
     nsolid[s] = NS;
     nlow[s] = NL;
+  }
   }
 }
 
@@ -697,68 +731,107 @@ __global__ void k_dead_ends(SortedView S, int k, uint8_t* __restrict__ fl) {
   fl[i] = (uint8_t)(1 | (!out ? 2 : 0) | (!in ? 4 : 0));
 }
 
-// Solid set as an open-addressing hash table for the per-window lookups of
-// the mercy rule (window keys arrive in read order, i.e. at random places in
-// key order, so one probe of one cache line beats a binary search).  Slot =
-// one meta word (0 = empty, else 0x100 | dead-end flags) followed by the W
-// key words; linear probing; at most half of the slots are used.
+// Solid set as a static bucket table for the per-window lookups of the
+// mercy rule.  Window keys arrive in read order, i.e. at random places in
+// key order, so a lookup should touch one cache line.  Bucket b (the top bb
+// bits of the key) holds the solid keys of b -- a contiguous range of the
+// sorted solid set -- in up to SL slots; the four top bits of each slot's
+// word 0 carry a valid bit and the dead-end flags (those bits are either
+// above the key or part of the bucket number, so they are not needed to
+// compare keys of one bucket).  Buckets with more than SL keys are marked
+// in ovf[] and searched in the sorted set.  Built by one streaming pass
+// over the sorted set, without atomics.
 template <int W>
-DEV uint64_t hslot(const Key<W>& k, uint64_t mask) {
-  uint64_t h = 0x9E3779B97F4A7C15ull;
-#pragma unroll
-  for (int i = 0; i < W; ++i) h = (h ^ k.w[i]) * 0xC2B2AE3D27D4EB4Full;
-  return (h ^ (h >> 29)) & mask;
-}
+struct Bucket {
+  static constexpr int SL = W <= 2 ? 8 : 4;
+};
+
+constexpr uint64_t kLow60 = (1ull << 60) - 1;
 
 template <int W>
-__global__ void k_hash_insert(SortedView S, const uint8_t* __restrict__ sfl, uint64_t* __restrict__ tab, uint64_t mask) {
-  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (i >= S.n) return;
-  const Key<W> x = key_load<W>(S.keys + i * W);
-  const unsigned long long val = 0x100ull | sfl[i];
-  uint64_t h = hslot<W>(x, mask);
-  while (atomicCAS(reinterpret_cast<unsigned long long*>(tab + h * (W + 1)), 0ull, val) != 0ull) h = (h + 1) & mask;
-  key_store<W>(tab + h * (W + 1) + 1, x);
-}
-
-template <int W>
-DEV uint8_t hash_flags(const uint64_t* __restrict__ tab, uint64_t mask, const Key<W>& x) {
-  uint64_t h = hslot<W>(x, mask);
-  for (;;) {
-    const uint64_t m = tab[h * (W + 1)];
-    if (m == 0) return 0;
-    if (key_eq<W>(key_load<W>(tab + h * (W + 1) + 1), x)) return (uint8_t)(m & 0xFF);
-    h = (h + 1) & mask;
+__global__ void k_bucket_fill(SortedView S, const uint8_t* __restrict__ sfl, uint64_t* __restrict__ tab,
+                              uint8_t* __restrict__ ovf, uint64_t nb) {
+  constexpr int SL = Bucket<W>::SL;
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t b = t / SL;
+  const int j = (int)(t % SL);
+  if (b >= nb) return;
+  const uint64_t lo = S.dir[b], n = S.dir[b + 1] - lo;
+  Key<W> x = key_zero<W>();
+  if ((uint64_t)j < n) {
+    x = key_load<W>(S.keys + (lo + j) * W);
+    x.w[0] = (x.w[0] & kLow60) | ((uint64_t)(8u | sfl[lo + j]) << 60);
   }
+  key_store<W>(tab + t * W, x);
+  if (j == 0) ovf[b] = n > (uint64_t)SL;
+}
+
+template <int W>
+DEV uint8_t bucket_flags(const uint64_t* __restrict__ tab, const uint8_t* __restrict__ ovf, const SortedView& S,
+                         const uint8_t* __restrict__ sfl, const Key<W>& q) {
+  constexpr int SL = Bucket<W>::SL;
+  const uint64_t b = key_bits<W>(q, S.kbits - S.db, S.db);
+  const uint64_t* p = tab + b * SL * W;
+  const uint64_t q0 = q.w[0] & kLow60;
+  Key<W> slot[SL];
+#pragma unroll
+  for (int j = 0; j < SL; ++j) slot[j] = key_load<W>(p + j * W);
+  uint8_t f = 0;
+  bool full = true;
+#pragma unroll
+  for (int j = 0; j < SL; ++j) {
+    const bool valid = (slot[j].w[0] >> 63) != 0;
+    full = full && valid;
+    bool eq = valid && (slot[j].w[0] & kLow60) == q0;
+#pragma unroll
+    for (int i = 1; i < W; ++i) eq = eq && slot[j].w[i] == q.w[i];
+    if (eq) f = (uint8_t)((slot[j].w[0] >> 60) & 7);
+  }
+  if (!f && full && ovf[b]) {
+    uint64_t ix;
+    f = sv_find<W>(S, q, &ix) ? sfl[ix] : 0;
+  }
+  return f;
 }
 
 // Per forward-strand window: 0x80 if it holds a non-ACGT base, else the
-// dead-end flags of its edge if solid, else 0.
+// dead-end flags of its edge if solid, else 0.  Each thread takes IPT
+// consecutive windows: their keys are built first, then all bucket lookups
+// are issued together (independent loads in flight).  3-word keys are
+// launched with IPT = 1: with two or more windows per thread the gfx950 code
+// for that width lost lookups in every workgroup after the first one per CU
+// (a loop-carried lane mask seeded from an undefined SGPR pair picked up the
+// previous workgroup's register state), while the same functions replayed
+// on the host are exact.
 template <int W, int IPT>
-__global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags(ExArgs a, const uint64_t* __restrict__ htab,
-                                                             uint64_t hmask, uint8_t* __restrict__ wf) {
-  __shared__ uint64_t rr[2];
-  const uint64_t t0 = (uint64_t)blockIdx.x * SDBG_BLOCK * IPT;
-  tile_reads(a, t0, t0 + SDBG_BLOCK * IPT - 1, rr);
+__global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags(ExArgs a, const uint64_t* __restrict__ tab,
+                                                             const uint8_t* __restrict__ ovf, SortedView S,
+                                                             const uint8_t* __restrict__ sfl, uint8_t* __restrict__ wf) {
   const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
   if (g0 >= a.NW) return;
   WinIter it;
-  it.init_in(a, g0, rr);
-  // Launched with IPT = 1.  With two windows per thread (loop unrolled or
-  // not) the gfx950 code for 3-word keys lost lookups in every workgroup
-  // after the first one per CU -- a loop-carried lane mask seeded from an
-  // undefined SGPR pair picks up the previous workgroup's register state --
-  // while the same functions replayed on the host are exact.
-  for (int q = 0; q < IPT && g0 + q < a.NW; ++q) {
-    uint64_t j = it.pos();
-    uint8_t f = 0x80;
-    if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
-      Key<W> F = stream_bits<W>(a.packed, 2 * j, a.kb);
-      f = hash_flags<W>(htab, hmask, key_from_fwd<W>(F, a.kb));
+  it.init(a, g0);
+  Key<W> key[IPT];
+  bool ok[IPT];
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) {
+    ok[q] = false;
+    key[q] = key_zero<W>();
+    if (g0 + q < a.NW) {
+      const uint64_t j = it.pos();
+      if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
+        ok[q] = true;
+        key[q] = key_from_fwd<W>(stream_bits<W>(a.packed, 2 * j, a.kb), a.kb);
+      }
+      it.next(a);
     }
-    wf[g0 + q] = f;
-    it.next(a);
   }
+  uint8_t f[IPT];
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) f[q] = ok[q] ? bucket_flags<W>(tab, ovf, S, sfl, key[q]) : (uint8_t)0x80;
+#pragma unroll
+  for (int q = 0; q < IPT; ++q)
+    if (g0 + q < a.NW) wf[g0 + q] = f[q];
 }
 
 // Mercy rule along each read (forward strand): consecutive solid windows
@@ -962,8 +1035,12 @@ struct Counter {
     DBuf<uint64_t> spos = c.buf<uint64_t>(L.n), lpos = c.buf<uint64_t>(L.n), tot = c.buf<uint64_t>(2);
     if (L.n) {
       Stage st_(c, "leaf", nkeys * 8 * W);
-      k_leaf<W, CAP><<<(unsigned)L.n, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, cnt, dmin, want_low ? 1 : 0,
-                                                              nsolid.get(), nlow.get());
+      DBuf<uint64_t> work = c.buf<uint64_t>(1);
+      fill<uint64_t>(work.get(), 1, 0, c);
+      const unsigned lgrid = (unsigned)std::min<uint64_t>(L.n, 256 * 16);
+      k_leaf<W, CAP><<<lgrid, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, cnt, dmin, want_low ? 1 : 0,
+                                                              nsolid.get(), nlow.get(),
+                                                       reinterpret_cast<unsigned long long*>(work.get()));
       c.check_launch("leaf");
     }
     scan_excl<uint64_t, uint64_t>(nsolid.get(), spos.get(), L.n, tot.get(), c);
@@ -1020,6 +1097,10 @@ struct Counter {
   SortedView make_view(const uint64_t* keys, uint64_t n, int kbits, DBuf<uint64_t>& dir) {
     int db = 1;
     while (db < 24 && db < kbits && (n >> (db + 3)) > 0) ++db;
+    return make_view_db(keys, n, kbits, db, dir);
+  }
+
+  SortedView make_view_db(const uint64_t* keys, uint64_t n, int kbits, int db, DBuf<uint64_t>& dir) {
     dir = c.buf<uint64_t>((1ull << db) + 1);
     k_dir<W><<<grid1(n + 1), SDBG_BLOCK, 0, c.s>>>(keys, n, kbits, db, dir.get());
     c.check_launch("dir");
@@ -1071,22 +1152,30 @@ struct Counter {
     ea.ghi = 1u << ea.pb;
     ea.dbits = std::min(8, kb);
     ea.dlo = kb - ea.dbits;
+    const uint64_t ntr = ceil_div(NW, TR_GRAIN) + 1;
+    DBuf<uint64_t> trd = c.buf<uint64_t>(ntr);
+    fill<uint64_t>(trd.get() + ntr - 1, 1, R.n_reads - 1, c);
+    k_tile_reads<<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(woff.get(), R.n_reads, trd.get());
+    c.check_launch("tile_reads");
+    ea.tr = trd.get();
     const uint32_t nbins = 1u << ea.dbits;
     const uint64_t win_per_tile = (uint64_t)SDBG_BLOCK * IPT;
     const uint64_t ntiles = ceil_div(NW, win_per_tile);
     SDBG_CHECK(ntiles < (1ull << 31), -3, "too many reads for one launch");
 
     // ---- first-digit histogram over all keys
+    // Every key passes the unfiltered histogram, so the scan total is the
+    // number of occurrences N; for a single group the scanned table is
+    // also the scatter's offset table.
     DBuf<uint32_t> tab = c.buf<uint32_t>(ntiles * nbins);
-    DBuf<unsigned long long> occ = c.buf<unsigned long long>(1);
     DBuf<uint64_t> tot = c.buf<uint64_t>(1);
-    fill<uint64_t>(reinterpret_cast<uint64_t*>(occ.get()), 1, 0, c);
     {
       Stage st_(c, "ex_hist", 3 * words * 8 + ntiles * nbins * 4);
-      k_ex_hist<W, IPT><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(ea, tab.get(), ntiles, occ.get());
+      k_ex_hist<W, IPT><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(ea, tab.get(), ntiles, nullptr);
       c.check_launch("ex_hist");
     }
-    const uint64_t N = c.d2h_one(reinterpret_cast<uint64_t*>(occ.get()));
+    scan_excl<uint32_t, uint32_t>(tab.get(), tab.get(), ntiles * nbins, tot.get(), c);
+    const uint64_t N = c.d2h_one(tot.get());
     out->n_occ = N;
 
     // ---- groups of consecutive prefix blocks within the memory budget
@@ -1146,8 +1235,8 @@ struct Counter {
         if (groups.size() > 1) {
           k_ex_hist<W, IPT><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(ga, tab.get(), ntiles, nullptr);
           c.check_launch("ex_hist(group)");
+          scan_excl<uint32_t, uint32_t>(tab.get(), tab.get(), ntiles * nbins, tot.get(), c);
         }
-        scan_excl<uint32_t, uint32_t>(tab.get(), tab.get(), ntiles * nbins, tot.get(), c);
         const uint64_t NG = c.d2h_one(tot.get());
         SDBG_CHECK(NG <= cap_keys, -4, "group larger than planned");
         if (NG == 0) continue;
@@ -1213,22 +1302,30 @@ struct Counter {
         k_dead_ends<W><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(sv, k, sfl.get());
         c.check_launch("dead_ends");
       }
-      uint64_t hslots = 2;
-      while (hslots < 2 * nS) hslots <<= 1;
-      DBuf<uint64_t> htab = c.buf<uint64_t>(hslots * (W + 1));
-      fill<uint64_t>(htab.get(), hslots * (W + 1), 0, c);
+      // bucket table: about SL/2 solid keys per bucket
+      constexpr int SL = Bucket<W>::SL;
+      int bb = 4;
+      while (bb < 30 && bb < kb && ((uint64_t)SL << bb) < 2 * nS) ++bb;
+      const uint64_t nb = 1ull << bb;
+      DBuf<uint64_t> bdir;
+      SortedView bv = make_view_db(S.get(), nS, kb, bb, bdir);
+      DBuf<uint64_t> btab = c.buf<uint64_t>(nb * SL * W);
+      DBuf<uint8_t> ovf = c.buf<uint8_t>(nb);
       {
-        Stage st_(c, "hash_insert", nS * (8 * W + 1) + nS * 8 * (W + 1));
-        k_hash_insert<W><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(sv, sfl.get(), htab.get(), hslots - 1);
-        c.check_launch("hash_insert");
+        Stage st_(c, "bucket_fill", nS * (8 * W + 1) + nb * (SL * 8 * W + 1 + 8));
+        k_bucket_fill<W><<<grid1(nb * SL), SDBG_BLOCK, 0, c.s>>>(bv, sfl.get(), btab.get(), ovf.get(), nb);
+        c.check_launch("bucket_fill");
       }
       DBuf<uint8_t> wf = c.buf<uint8_t>(NW);
       {
         Stage st_(c, "window_flags", 3 * words * 8 + NW);
-        k_window_flags<W, 1><<<grid1(NW), SDBG_BLOCK, 0, c.s>>>(ea, htab.get(), hslots - 1, wf.get());
+        constexpr int WIPT = W == 1 ? 8 : W == 2 ? 4 : W == 4 ? 2 : 1;
+        k_window_flags<W, WIPT><<<grid1(ceil_div(NW, WIPT)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), ovf.get(), bv,
+                                                                                   sfl.get(), wf.get());
         c.check_launch("window_flags");
       }
-      htab.free();
+      btab.free();
+      ovf.free();
       DBuf<uint64_t> mcount = c.buf<uint64_t>(R.n_reads), mpos = c.buf<uint64_t>(R.n_reads);
       {
         Stage st_(c, "mercy_count", NW + R.n_reads * 24);
