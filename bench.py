@@ -64,6 +64,141 @@ def cpu_baseline(rs, n_reads: int):
             "sample": f"first {sub.n_reads} reads of the workload ({e.n_occ} (k+1)-mer occurrences), count+build, {dt:.1f} s"}
 
 
+def bench_batch(args):
+    """Batched form against one plain call per set, on the same device-resident
+    sets; both build the SdBG of every set."""
+    import torch
+
+    from paper_1409_7208_amd import sdbg, synth
+
+    sdbg.load()
+    torch.cuda.set_device(0)
+    scale = 0.01 if args.read_scale is None else args.read_scale
+    t0 = time.perf_counter()
+    sets = [synth.batch_set(i, read_scale=scale) for i in range(args.sets)]
+    log(f"generated {len(sets)} sets, {sum(r.n_reads for r in sets)} reads in {time.perf_counter() - t0:.1f} s")
+    dev = [(torch.from_numpy(r.seq).to("cuda:0"), torch.from_numpy(r.offsets.view(np.int64)).to("cuda:0"))
+           for r in sets]
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def batched():
+        res = sdbg.batch_run(dev, 31, 2, False, stream=stream)
+        occ = sum(e.n_occ for e, _ in res)
+        for e, g in res:
+            e.close()
+            g.close()
+        return occ
+
+    def sequential():
+        occ = 0
+        for seq, off in dev:
+            e = sdbg.count_solid(seq, off, 31, 2, False, stream=stream)
+            g = sdbg.build(e, stream=stream)
+            occ += e.n_occ
+            g.close()
+            e.close()
+        return occ
+
+    out = {}
+    for name, fn in (("batched", batched), ("sequential", sequential)):
+        fn()  # warm-up (device memory pool)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(max(1, args.steps)):
+            w0 = time.perf_counter()
+            occ = fn()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - w0)
+        t = float(np.median(times))
+        out[name] = {"seconds": round(t, 4), "gmer_s": round(occ / t / 1e9, 3)}
+        log(f"{name}: {t * 1e3:.1f} ms, {occ / t / 1e9:.3f} Gmer/s over {len(sets)} sets")
+    line = {"metric": "Gmer/s batched form vs one call per set", "form": "batch", "value": out["batched"]["gmer_s"],
+            "unit": "Gmer/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"first {len(sets)} sets of 4096: genome 20-500 kb, log-uniform 1k-1M reads "
+                                   f"x {scale} of 100 bp, 1% err, k=31, d=2, mercy off", "n_occ": int(occ)},
+            "batched": out["batched"], "sequential": out["sequential"],
+            "speedup": round(out["sequential"]["seconds"] / out["batched"]["seconds"], 3)}
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """Poisson request stream through the request loop (4 jobs at once)
+    against the same trace run one job at a time; latency = submit to
+    completion of the job's SdBG arrays."""
+    import threading
+
+    import torch
+
+    from paper_1409_7208_amd import sdbg, synth
+
+    sdbg.load()
+    torch.cuda.set_device(0)
+    scale = 0.1 if args.read_scale is None else args.read_scale
+    t0 = time.perf_counter()
+    pool = [j.reads for j in synth.serving_trace(1.0, args.pool, read_scale=scale, genome_scale=0.1)]
+    log(f"generated {len(pool)} jobs, {sum(r.n_reads for r in pool)} reads in {time.perf_counter() - t0:.1f} s")
+
+    def replay(max_jobs, arrivals, jobs):
+        res = [None] * len(jobs)
+        with sdbg.Server(max_jobs=max_jobs) as srv:
+            ids = [None] * len(jobs)
+            ready = threading.Event()
+
+            def submitter():
+                base = time.perf_counter()
+                for i, (a, rs) in enumerate(zip(arrivals, jobs)):
+                    dt = base + a - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                    ids[i] = srv.submit(rs.seq, rs.offsets, rs.k, 2, True)
+                    ready.set()
+
+            th = threading.Thread(target=submitter)
+            th.start()
+            for i in range(len(jobs)):
+                while ids[i] is None:
+                    ready.wait(0.01)
+                    ready.clear()
+                r = srv.poll(ids[i])
+                assert r.status == 0, r.error
+                res[i] = (r.submit_s, r.start_s, r.end_s, r.n_occ)
+                r.edges.close()
+                r.graph.close()
+            th.join()
+        lat = np.array([e - s for s, _, e, _ in res])
+        span = max(e for _, _, e, _ in res) - min(s for s, _, _, _ in res)
+        occ = sum(o for *_, o in res)
+        return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                "gmer_s": round(occ / span / 1e9, 3), "jobs": len(jobs), "n_occ": int(occ)}
+
+    # warm the device memory pool on the largest job
+    big = max(pool, key=lambda r: r.n_reads)
+    replay(1, [0.0], [big])
+    rng = np.random.default_rng(0x14097208)
+    rows = []
+    for lam in [float(x) for x in args.rates.split(",")]:
+        n = int(min(len(pool), max(8, 4 * lam)))
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n))
+        arrivals -= arrivals[0]
+        jobs = [pool[i % len(pool)] for i in range(n)]
+        cb = replay(4, arrivals, jobs)
+        fifo = replay(1, arrivals, jobs)
+        rows.append({"rate": lam, "served": cb, "one_at_a_time": fifo})
+        log(f"rate {lam:5.1f}/s: served p50 {cb['p50_ms']} ms p99 {cb['p99_ms']} ms {cb['gmer_s']} Gmer/s | "
+            f"one-at-a-time p50 {fifo['p50_ms']} ms p99 {fifo['p99_ms']} ms {fifo['gmer_s']} Gmer/s")
+    top = rows[-1]
+    line = {"metric": "p99 job latency and aggregate Gmer/s, request loop vs one job at a time", "form": "serve",
+            "value": top["served"]["gmer_s"], "unit": "Gmer/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"Poisson jobs: 1-50 genomes of 0.01-0.5 Mb, log-uniform 10k-20M reads x {scale}, "
+                                   "L 100-150, 0.5% err, k in {21,41,61}, d=2, mercy", "pool": len(pool),
+                       "max_jobs": 4},
+            "rates": rows}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,10 +211,21 @@ def main():
     ap.add_argument("--stages", action="store_true", help="print per-kernel breakdown to stderr")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (a reference kernel for hardware byte counters)")
+    ap.add_argument("--form", default="plain", choices=["plain", "batch", "serve"],
+                    help="plain: one job (the headline); batch: many read sets per call vs one call per set; "
+                         "serve: Poisson request stream through the request loop vs one job at a time")
+    ap.add_argument("--sets", type=int, default=4096, help="batch: first N sets of the 4096-set recipe")
+    ap.add_argument("--read-scale", type=float, default=None, help="batch/serve: scale of the read counts")
+    ap.add_argument("--rates", default="1,2,5,10,20,50", help="serve: arrival rates (jobs/s)")
+    ap.add_argument("--pool", type=int, default=32, help="serve: distinct jobs in the pool")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.form == "batch":
+        return bench_batch(args)
+    if args.form == "serve":
+        return bench_serve(args)
 
     import torch
 

@@ -75,8 +75,8 @@ extern "C" {
 #define SDBG_E_NOMEM (-2)        /* host allocation failed */
 #define SDBG_E_NOMEM_DEVICE (-3) /* device memory or mem_budget cannot hold one block */
 #define SDBG_E_HIP (-4)          /* HIP runtime error; message copied */
-#define SDBG_E_BUSY (-5)         /* reserved */
-#define SDBG_E_CANCELLED (-6)    /* reserved */
+#define SDBG_E_BUSY (-5)         /* request queue full, or job already running */
+#define SDBG_E_CANCELLED (-6)    /* job cancelled before it ran */
 
 /* Reads: seq[offsets[i] .. offsets[i+1]) is read i; offsets[0] = 0 and the
  * offsets are non-decreasing.  on_device = 1: both pointers are device
@@ -134,6 +134,76 @@ int sdbg_count_solid(const sdbg_reads *reads, const sdbg_params *params, sdbg_ed
 /* SdBG arrays of an edge set (Section 2, first and second paragraphs).
  * Uses params->stream only; the other fields are ignored. */
 int sdbg_build(const sdbg_edges *edges, const sdbg_params *params, sdbg_graph **out);
+
+/* Batched form: count (and, if graphs_out is not NULL, build) n_sets
+ * independent read sets.  Results are identical to sdbg_count_solid and
+ * sdbg_build on each set alone: edges_out[s] (and graphs_out[s]) receive
+ * set s's objects, owned by the caller.  Consecutive sets whose keys fit
+ * params->mem_budget (0 = 80% of free device memory) share every launch of
+ * the partition, sort and count -- the paper sorts consecutive partitions
+ * together in the same way (Section 2, second paragraph) -- so the number of
+ * launches does not grow with the number of sets; a set larger than one
+ * pass, and every set when mercy is on with d >= 2, runs on the single-set
+ * path.  Sets may mix host and device reads.  On error no output is left
+ * allocated and all entries are NULL. */
+int sdbg_batch_run(const sdbg_reads *sets, uint64_t n_sets, const sdbg_params *params, sdbg_edges **edges_out,
+                   sdbg_graph **graphs_out);
+
+/* Served form: a request loop on the current device.  Jobs (a read set and
+ * its parameters) are copied into pinned host memory at submit and queue in
+ * FIFO order; max_jobs workers, each with its own stream, start the head of
+ * the queue as soon as its device-memory footprint fits mem_budget next to
+ * the running jobs, so jobs that arrive while others run join them on the
+ * device (a job larger than the whole budget runs alone).  Each job runs
+ * the single-call path (sdbg_count_solid, then sdbg_build if cfg->build),
+ * so its results are identical to running it alone.  The device buffers of
+ * finished jobs stay cached for the next ones (the memory-adaptive
+ * construction of Section 2, third paragraph, under a shared budget). */
+typedef struct sdbg_server_cfg {
+  uint32_t max_jobs;   /* jobs running at once, at most 64; 0 = 4 */
+  uint32_t queue_cap;  /* waiting jobs before submit returns SDBG_E_BUSY; 0 = 4096 */
+  uint64_t mem_budget; /* device bytes shared by running jobs; 0 = 80% of free */
+  uint32_t build;      /* 1: each job also builds the SdBG arrays */
+  uint32_t reserved;
+} sdbg_server_cfg;
+
+/* Per-job record.  status: 1 waiting, 2 running, then SDBG_OK or the job's
+ * error code; times in seconds since the server started; footprint = device
+ * bytes reserved for the job at admission. */
+typedef struct sdbg_job_stats {
+  int32_t status;
+  uint32_t reserved;
+  double submit_s, start_s, end_s;
+  uint64_t n_occ;
+  uint64_t footprint;
+} sdbg_job_stats;
+
+typedef struct sdbg_server sdbg_server;
+
+/* Starts the workers (cfg may be NULL for defaults). */
+int sdbg_server_start(const sdbg_server_cfg *cfg, sdbg_server **out);
+
+/* Queues a job; reads must be host memory and are copied before the call
+ * returns; params->stream is ignored.  SDBG_E_BUSY if the queue is full. */
+int sdbg_server_submit(sdbg_server *srv, const sdbg_reads *reads, const sdbg_params *params, uint64_t *job_id);
+
+/* Result of a job.  wait = 1 blocks until it has finished.  Returns 1 or 2
+ * (waiting or running; only when wait = 0), else the job's final code:
+ * SDBG_OK hands its edges (and graph, if built) to the caller -- NULL
+ * pointers decline them and they are freed -- and forgets the job; an error
+ * code also forgets it.  stats (may be NULL) receives its record.
+ * SDBG_E_INVAL for an unknown id. */
+int sdbg_server_poll(sdbg_server *srv, uint64_t job_id, int wait, sdbg_edges **edges, sdbg_graph **graph,
+                     sdbg_job_stats *stats);
+
+/* Cancels a waiting job (it finishes with SDBG_E_CANCELLED); SDBG_E_BUSY
+ * if it is already running or finished. */
+int sdbg_server_cancel(sdbg_server *srv, uint64_t job_id);
+
+/* Cancels waiting jobs, waits for running ones, frees results nobody
+ * polled, and releases the server.  No other call on srv may be in
+ * progress or follow. */
+int sdbg_server_stop(sdbg_server *srv);
 
 /* Wraps host arrays (n*w key words ascending and unique, n counts) into a
  * library-owned device edge set, e.g. to build a graph from edges computed

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsdbg.so")
-SOURCES = ["runtime.cpp", "api.cpp", "prims.hip", "count.hip", "build.hip"]
+SOURCES = ["runtime.cpp", "api.cpp", "server.cpp", "prims.hip", "count.hip", "build.hip"]
 ARCH = os.environ.get("SDBG_OFFLOAD_ARCH", "gfx950")
 
 
@@ -61,7 +61,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(one, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

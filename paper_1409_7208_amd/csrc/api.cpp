@@ -7,11 +7,11 @@
 #include <new>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
-#include "sdbg.h"
-#include "engine.h"
+#include "abi_common.h"
 
-namespace {
+namespace sdbg_abi {
 
 thread_local std::string t_err;
 
@@ -49,27 +49,85 @@ void pool_free(void* p) {
   if (p) sdbg::Pool::get().release(p, nullptr, false);
 }
 
-template <typename F>
-int guarded(F&& f) {
-  try {
-    t_err.clear();
-    return f();
-  } catch (const sdbg::Error& e) {
-    sdbg::prof_flush();
-    t_err = e.what();
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    t_err = "host allocation failed";
-    return SDBG_E_NOMEM;
-  } catch (const std::exception& e) {
-    t_err = e.what();
-    return SDBG_E_HIP;
-  }
-}
-
 void check_k(uint32_t k) { SDBG_CHECK(k >= 2 && k <= 127, SDBG_E_INVAL, "k must be in [2, 127]"); }
 
-}  // namespace
+void check_params(const sdbg_params* p) {
+  check_k(p->k);
+  SDBG_CHECK(p->d >= 1, SDBG_E_INVAL, "d must be >= 1");
+  SDBG_CHECK(p->prefix_len <= 8, SDBG_E_INVAL, "prefix_len must be in [0, 8]");
+}
+
+sdbg_edges* wrap_edges(const sdbg::EdgesOut& eo, uint32_t k) {
+  sdbg_edges* e = new sdbg_edges();
+  e->k = k;
+  e->w = (uint32_t)sdbg::key_words((int)k);
+  e->n = eo.n;
+  e->n_mercy = eo.n_mercy;
+  e->n_occ = eo.n_occ;
+  e->keys = eo.keys;
+  e->count = eo.count;
+  reg_add(e, kEdges);
+  return e;
+}
+
+sdbg_graph* wrap_graph(const sdbg::GraphOut& go, uint32_t k) {
+  sdbg_graph* g = new sdbg_graph();
+  g->k = k;
+  g->w = (uint32_t)sdbg::key_words((int)k);
+  g->m = go.m;
+  g->t = go.t;
+  g->W = go.W;
+  g->last = go.last;
+  g->valid = go.valid;
+  g->tip = go.tip;
+  g->mult = go.mult;
+  std::memcpy(g->F, go.F, sizeof(g->F));
+  g->tip_seq = go.tip_seq;
+  g->tip_words = go.tip_words;
+  reg_add(g, kGraph);
+  return g;
+}
+
+// Host copy of a read set's offsets (validated); device offsets are copied.
+std::vector<uint64_t> host_offsets(sdbg::Ctx& c, const sdbg_reads* r) {
+  std::vector<uint64_t> o(r->n_reads + 1, 0);
+  if (r->n_reads == 0) return o;
+  SDBG_CHECK(r->offsets, SDBG_E_INVAL, "null offsets");
+  if (r->on_device)
+    c.d2h(o.data(), r->offsets, r->n_reads + 1);
+  else
+    std::memcpy(o.data(), r->offsets, sizeof(uint64_t) * (r->n_reads + 1));
+  SDBG_CHECK(o[0] == 0, SDBG_E_INVAL, "offsets[0] must be 0");
+  for (uint64_t i = 0; i < r->n_reads; ++i) SDBG_CHECK(o[i + 1] >= o[i], SDBG_E_INVAL, "offsets must be non-decreasing");
+  SDBG_CHECK(o[r->n_reads] == 0 || r->seq, SDBG_E_INVAL, "null seq");
+  return o;
+}
+
+// (k+1)-mer occurrences of a read set if no byte splits a read (an upper
+// bound otherwise): 2 * sum over reads of max(0, len - k).
+uint64_t occ_bound(const std::vector<uint64_t>& o, uint32_t k) {
+  uint64_t n = 0;
+  for (size_t i = 0; i + 1 < o.size(); ++i) {
+    const uint64_t len = o[i + 1] - o[i];
+    if (len > k) n += 2 * (len - k);
+  }
+  return n;
+}
+
+// Device bytes per key of a batched pass: two key buffers, counts, solid
+// output and its per-set copy, plus the reads' share.
+uint64_t batch_bytes_per_key(uint32_t w) { return 32ull * w + 16; }
+
+uint64_t device_budget(const sdbg_params* p) {
+  if (p->mem_budget) return p->mem_budget;
+  size_t fr = 0, tot = 0;
+  SDBG_HIP(hipMemGetInfo(&fr, &tot));
+  return (uint64_t)(0.8 * (double)(fr + sdbg::Pool::get().cached_bytes()));
+}
+
+}  // namespace sdbg_abi
+
+using namespace sdbg_abi;
 
 extern "C" {
 
@@ -188,6 +246,125 @@ int sdbg_build(const sdbg_edges* edges, const sdbg_params* params, sdbg_graph** 
     *out = g;
     return SDBG_OK;
   });
+}
+
+int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* params, sdbg_edges** edges_out,
+                   sdbg_graph** graphs_out) {
+  std::vector<void*> made;
+  int rc = guarded([&]() -> int {
+    SDBG_CHECK(params && edges_out && (sets || n_sets == 0), SDBG_E_INVAL, "null argument");
+    for (uint64_t s = 0; s < n_sets; ++s) {
+      edges_out[s] = nullptr;
+      if (graphs_out) graphs_out[s] = nullptr;
+    }
+    check_params(params);
+    const uint32_t k = params->k, w = (uint32_t)sdbg::key_words((int)k);
+    sdbg::Ctx c(params->stream);
+    std::vector<std::vector<uint64_t>> off(n_sets);
+    std::vector<uint64_t> occ(n_sets);
+    for (uint64_t s = 0; s < n_sets; ++s) {
+      off[s] = host_offsets(c, &sets[s]);
+      occ[s] = occ_bound(off[s], k);
+    }
+    const uint64_t max_keys = std::min<uint64_t>(device_budget(params) / batch_bytes_per_key(w), 0xFFFFFFFFull);
+    const bool shared = !(params->mercy && params->d >= 2);
+    sdbg::CountParams P{(int)k, params->d, params->mercy != 0, (int)params->prefix_len, params->mem_budget};
+    uint64_t s0 = 0;
+    while (s0 < n_sets) {
+      if (!shared || occ[s0] > max_keys) {
+        // one set alone on the single-set path (mercy, or larger than a pass)
+        sdbg::EdgesOut eo;
+        {
+          sdbg::DevReads R{};
+          R.n_reads = sets[s0].n_reads;
+          R.n_bases = off[s0].back();
+          sdbg::DBuf<uint8_t> seq_d = c.buf<uint8_t>(R.n_bases + 16);
+          sdbg::DBuf<uint64_t> off_d = c.buf<uint64_t>(R.n_reads + 1);
+          if (R.n_bases) {
+            if (sets[s0].on_device)
+              c.d2d(seq_d.get(), sets[s0].seq, R.n_bases);
+            else
+              c.h2d(seq_d.get(), sets[s0].seq, R.n_bases);
+          }
+          c.h2d(off_d.get(), off[s0].data(), R.n_reads + 1);
+          R.seq = seq_d.get();
+          R.offsets = off_d.get();
+          sdbg::count_solid(R, P, c, &eo);
+          c.sync();
+        }
+        edges_out[s0] = wrap_edges(eo, k);
+        made.push_back(edges_out[s0]);
+        ++s0;
+        continue;
+      }
+      // a wave: consecutive sets whose keys fit one pass
+      uint64_t s1 = s0, keys = 0, bases = 0, reads = 0;
+      while (s1 < n_sets && occ[s1] <= max_keys && keys + occ[s1] <= max_keys) {
+        keys += occ[s1];
+        bases += off[s1].back();
+        reads += sets[s1].n_reads;
+        ++s1;
+      }
+      std::vector<sdbg::EdgesOut> outs;
+      {
+        sdbg::DBuf<uint8_t> seq_d = c.buf<uint8_t>(bases + 16);
+        std::vector<uint64_t> ho(reads + 1), rb(s1 - s0 + 1);
+        uint64_t rp = 0, bp = 0;
+        for (uint64_t s = s0; s < s1; ++s) {
+          rb[s - s0] = rp;
+          const uint64_t nb = off[s].back();
+          for (uint64_t i = 0; i < sets[s].n_reads; ++i) ho[rp + i] = bp + off[s][i];
+          if (nb) {
+            if (sets[s].on_device)
+              c.d2d(seq_d.get() + bp, sets[s].seq, nb);
+            else
+              c.h2d(seq_d.get() + bp, sets[s].seq, nb);
+          }
+          rp += sets[s].n_reads;
+          bp += nb;
+        }
+        ho[reads] = bp;
+        rb[s1 - s0] = rp;
+        sdbg::DBuf<uint64_t> off_d = c.buf<uint64_t>(reads + 1);
+        c.h2d(off_d.get(), ho.data(), reads + 1);
+        sdbg::DevReads R{seq_d.get(), off_d.get(), reads, bases};
+        try {
+          sdbg::count_solid_sets(R, rb, P, c, &outs);
+        } catch (...) {
+          for (auto& o : outs) {
+            pool_free(o.keys);
+            pool_free(o.count);
+          }
+          throw;
+        }
+        c.sync();
+      }
+      for (uint64_t s = s0; s < s1; ++s) {
+        edges_out[s] = wrap_edges(outs[s - s0], k);
+        made.push_back(edges_out[s]);
+      }
+      s0 = s1;
+    }
+    if (graphs_out) {
+      for (uint64_t s = 0; s < n_sets; ++s) {
+        sdbg::GraphOut go;
+        sdbg::build_graph(edges_out[s]->keys, edges_out[s]->count, edges_out[s]->n, (int)k, c, &go);
+        c.sync();
+        graphs_out[s] = wrap_graph(go, k);
+        made.push_back(graphs_out[s]);
+      }
+    }
+    sdbg::prof_flush();
+    return SDBG_OK;
+  });
+  if (rc != SDBG_OK) {
+    for (void* p : made) sdbg_free(p);
+    for (uint64_t s = 0; edges_out && s < n_sets; ++s) {
+      edges_out[s] = nullptr;
+      if (graphs_out) graphs_out[s] = nullptr;
+    }
+  }
+  return rc;
 }
 
 int sdbg_edges_from_host(const uint64_t* keys, const uint32_t* count, uint64_t n, uint32_t k, sdbg_edges** out) {

@@ -95,7 +95,41 @@ struct ExArgs {
   uint32_t glo, ghi;  // keep keys whose top pb bits are in [glo, ghi)
   int dlo, dbits;     // partition digit = bits [dlo, dlo + dbits)
   const uint64_t* tr; // tr[t] = read holding window t*TR_GRAIN (last entry: n_reads - 1)
+  // Several read sets in one launch (null for a single set): the windows of
+  // set s are [sw[s], sw[s+1]), its tiles [st[s], st[s+1]) (at least one),
+  // tset[t] = set of tile t.  Tiles never straddle sets, and the histogram
+  // table is set-major: set s owns columns [st[s]*2^dbits, st[s+1]*2^dbits),
+  // digit-major within, so one scan orders keys by (set, digit, tile).
+  const uint32_t* tset;
+  const uint64_t* sw;
+  const uint64_t* st;
 };
+
+// Windows and histogram-table column of one extraction tile.
+struct TileGeo {
+  uint64_t g0, gend;    // first window of the tile, end of its set's windows
+  uint64_t col, stride; // table entry of digit d: col + d * stride
+};
+
+template <int IPT>
+DEV TileGeo tile_geo(const ExArgs& a, uint64_t t, uint64_t ntiles) {
+  constexpr uint64_t WPT = (uint64_t)SDBG_BLOCK * IPT;
+  TileGeo g;
+  if (!a.tset) {
+    g.g0 = t * WPT;
+    g.gend = a.NW;
+    g.col = t;
+    g.stride = ntiles;
+  } else {
+    const uint32_t s = a.tset[t];
+    const uint64_t t0 = a.st[s];
+    g.g0 = a.sw[s] + (t - t0) * WPT;
+    g.gend = a.sw[s + 1];
+    g.col = (t0 << a.dbits) + (t - t0);
+    g.stride = a.st[s + 1] - t0;
+  }
+  return g;
+}
 
 // Granularity of the window -> read table.
 constexpr uint64_t TR_GRAIN = 256;
@@ -197,13 +231,14 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_hist(ExArgs a, uint32_t* __re
   h[threadIdx.x] = 0;
   __syncthreads();
   uint32_t produced = 0;
-  const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
-  if (g0 < a.NW) {
+  const TileGeo tg = tile_geo<IPT>(a, blockIdx.x, ntiles);
+  const uint64_t g0 = tg.g0 + (uint64_t)threadIdx.x * IPT;
+  if (g0 < tg.gend) {
     WinIter it;
     it.init(a, g0);
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-      if (g0 + q < a.NW) {
+      if (g0 + q < tg.gend) {
         uint64_t j = it.pos();
         if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
           Key<W> kf, kr;
@@ -217,7 +252,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_hist(ExArgs a, uint32_t* __re
     }
   }
   __syncthreads();
-  if (threadIdx.x < (1u << a.dbits)) tab[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+  if (threadIdx.x < (1u << a.dbits)) tab[tg.col + (uint64_t)threadIdx.x * tg.stride] = h[threadIdx.x];
   if (occ) {
     uint32_t s = wave_sum(produced);
     if ((threadIdx.x & 63) == 0 && s) atomicAdd(occ, (unsigned long long)s);
@@ -235,20 +270,21 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_scatter(ExArgs a, const uint3
   __shared__ uint32_t cnt[256], lst[256], gb[256];
   __shared__ uint32_t sc[SDBG_WAVES + 1];
   const uint32_t nbins = 1u << a.dbits;
+  const TileGeo tg = tile_geo<IPT>(a, blockIdx.x, ntiles);
   cnt[threadIdx.x] = 0;
-  gb[threadIdx.x] = threadIdx.x < nbins ? tab[(uint64_t)threadIdx.x * ntiles + blockIdx.x] : 0;
+  gb[threadIdx.x] = threadIdx.x < nbins ? tab[tg.col + (uint64_t)threadIdx.x * tg.stride] : 0;
   __syncthreads();
   Key<W> keys[NK];
   uint32_t pos[NK];
 #pragma unroll
   for (int q = 0; q < NK; ++q) pos[q] = 0xFFFFFFFFu;
-  const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
-  if (g0 < a.NW) {
+  const uint64_t g0 = tg.g0 + (uint64_t)threadIdx.x * IPT;
+  if (g0 < tg.gend) {
     WinIter it;
     it.init(a, g0);
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-      if (g0 + q < a.NW) {
+      if (g0 + q < tg.gend) {
         uint64_t j = it.pos();
         if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
           window_keys<W>(a, j, &keys[2 * q], &keys[2 * q + 1]);
@@ -956,6 +992,54 @@ __global__ void k_seg_init(const uint32_t* __restrict__ tabscan, uint64_t ntiles
   v.D[d] = 0;
 }
 
+// Initial segments of several read sets: segment s * nbins + d is digit d
+// of set s (st = first tile of each set, at least one tile per set).
+__global__ void k_seg_init_sets(const uint32_t* __restrict__ tabscan, const uint64_t* __restrict__ st, uint64_t nsets,
+                                int dbits, uint64_t total, int bit, SegView v) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint32_t nbins = 1u << dbits;
+  if (i >= nsets * nbins) return;
+  const uint64_t s = i >> dbits;
+  const uint32_t d = (uint32_t)(i & (nbins - 1));
+  const uint64_t t0 = st[s], nt = st[s + 1] - t0, base = t0 << dbits;
+  const uint64_t a = tabscan[base + d * nt];
+  const uint64_t b = d + 1 < nbins ? tabscan[base + (d + 1) * nt] : (s + 1 < nsets ? tabscan[st[s + 1] << dbits] : total);
+  v.off[i] = a;
+  v.len[i] = b - a;
+  v.bit[i] = (uint16_t)bit;
+  v.buf[i] = 0;
+  v.D[i] = 0;
+}
+
+__global__ void k_gather_idx(const uint64_t* __restrict__ src, const uint64_t* __restrict__ idx, uint64_t n,
+                             uint64_t* __restrict__ dst) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
+// Per set s (and s = nsets for the end): its first key position and its
+// first output edge.  Leaf segments are in key order, so the set's output
+// starts at the scanned output count of its first segment (the first one
+// at or after the set's first key).
+__global__ void k_set_bounds(const uint64_t* __restrict__ seg_off, uint64_t nseg, const uint64_t* __restrict__ spos,
+                             const uint32_t* __restrict__ tabscan, const uint64_t* __restrict__ st, int dbits,
+                             uint64_t nsets, uint64_t total, uint64_t* __restrict__ key_base,
+                             uint64_t* __restrict__ out_base) {
+  const uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (s > nsets) return;
+  const uint64_t kb = s < nsets ? tabscan[st[s] << dbits] : total;
+  uint64_t lo = 0, hi = nseg;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (seg_off[mid] < kb)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  key_base[s] = kb;
+  out_base[s] = spos[lo];
+}
+
 __global__ void k_gather_strided(const uint32_t* __restrict__ src, uint64_t stride, uint32_t n, uint64_t* dst) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[(uint64_t)i * stride];
@@ -1028,11 +1112,13 @@ struct Counter {
 
   // Leaves -> dense sorted (key, count) arrays of the distinct keys with
   // count >= dmin, and (if want_low) of those below.
+  // spos_keep (optional) receives each segment's first output position,
+  // with the total at index L.n.
   void leaves(SegList& L, uint64_t nkeys, uint64_t* const* d_bufs, uint32_t* cnt, uint32_t dmin, bool want_low,
               DBuf<uint64_t>& skeys, DBuf<uint32_t>& scnt, uint64_t* ns_out, DBuf<uint64_t>& lkeys,
-              DBuf<uint32_t>& lcnt, uint64_t* nl_out) {
+              DBuf<uint32_t>& lcnt, uint64_t* nl_out, DBuf<uint64_t>* spos_keep = nullptr) {
     DBuf<uint64_t> nsolid = c.buf<uint64_t>(L.n), nlow = c.buf<uint64_t>(L.n);
-    DBuf<uint64_t> spos = c.buf<uint64_t>(L.n), lpos = c.buf<uint64_t>(L.n), tot = c.buf<uint64_t>(2);
+    DBuf<uint64_t> spos = c.buf<uint64_t>(L.n + 1), lpos = c.buf<uint64_t>(L.n), tot = c.buf<uint64_t>(2);
     if (L.n) {
       Stage st_(c, "leaf", nkeys * 8 * W);
       DBuf<uint64_t> work = c.buf<uint64_t>(1);
@@ -1043,8 +1129,9 @@ struct Counter {
                                                        reinterpret_cast<unsigned long long*>(work.get()));
       c.check_launch("leaf");
     }
-    scan_excl<uint64_t, uint64_t>(nsolid.get(), spos.get(), L.n, tot.get(), c);
+    scan_excl<uint64_t, uint64_t>(nsolid.get(), spos.get(), L.n, spos.get() + L.n, c);
     scan_excl<uint64_t, uint64_t>(nlow.get(), lpos.get(), L.n, tot.get() + 1, c);
+    c.d2d(tot.get(), spos.get() + L.n, 1);
     uint64_t ht[2];
     c.d2h(ht, tot.get(), 2);
     *ns_out = ht[0];
@@ -1065,6 +1152,7 @@ struct Counter {
                                                             want_low ? lcnt.get() : nullptr);
       c.check_launch("compact");
     }
+    if (spos_keep) *spos_keep = std::move(spos);
   }
 
   // Sorted distinct keys of an arbitrary key array (consumed).
@@ -1107,12 +1195,24 @@ struct Counter {
     return SortedView{keys, dir.get(), n, kbits, db};
   }
 
-  void run(const DevReads& R, const CountParams& P, EdgesOut* out) {
-    const int k = P.k, kb = 2 * (k + 1);
+  // Packed reads, window offsets and the window -> read table.
+  struct Prep {
+    DBuf<uint64_t> packed, bad, woff, trd;
+    uint64_t words = 0, NW = 0;
+    uint32_t any_bad = 0;
+    ExArgs ea{};
+  };
+
+  void prepare(const DevReads& R, int k, Prep& pr) {
+    const int kb = 2 * (k + 1);
     const uint64_t nb = R.n_bases;
     // ---- pack
     const uint64_t words = ceil_div(nb, 64);
-    DBuf<uint64_t> packed = c.buf<uint64_t>(2 * words + W + 8), bad = c.buf<uint64_t>(words + 8);
+    pr.words = words;
+    DBuf<uint64_t>& packed = pr.packed;
+    DBuf<uint64_t>& bad = pr.bad;
+    packed = c.buf<uint64_t>(2 * words + W + 8);
+    bad = c.buf<uint64_t>(words + 8);
     DBuf<uint32_t> anyb = c.buf<uint32_t>(1);
     fill<uint64_t>(packed.get() + 2 * words, W + 8, 0, c);
     fill<uint64_t>(bad.get() + words, 8, 0, c);
@@ -1123,7 +1223,8 @@ struct Counter {
       c.check_launch("pack");
     }
     // ---- windows per read
-    DBuf<uint64_t> woff = c.buf<uint64_t>(R.n_reads + 1);
+    DBuf<uint64_t>& woff = pr.woff;
+    woff = c.buf<uint64_t>(R.n_reads + 1);
     {
       DBuf<uint64_t> nwin = c.buf<uint64_t>(R.n_reads);
       if (R.n_reads) {
@@ -1134,10 +1235,11 @@ struct Counter {
     }
     const uint64_t NW = c.d2h_one(woff.get() + R.n_reads);
     const uint32_t any_bad = c.d2h_one(anyb.get());
-    *out = EdgesOut{};
+    pr.NW = NW;
+    pr.any_bad = any_bad;
     if (NW == 0) return;
 
-    ExArgs ea{};
+    ExArgs& ea = pr.ea;
     ea.packed = packed.get();
     ea.bad = bad.get();
     ea.woff = woff.get();
@@ -1153,11 +1255,22 @@ struct Counter {
     ea.dbits = std::min(8, kb);
     ea.dlo = kb - ea.dbits;
     const uint64_t ntr = ceil_div(NW, TR_GRAIN) + 1;
-    DBuf<uint64_t> trd = c.buf<uint64_t>(ntr);
+    DBuf<uint64_t>& trd = pr.trd;
+    trd = c.buf<uint64_t>(ntr);
     fill<uint64_t>(trd.get() + ntr - 1, 1, R.n_reads - 1, c);
     k_tile_reads<<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(woff.get(), R.n_reads, trd.get());
     c.check_launch("tile_reads");
     ea.tr = trd.get();
+  }
+
+  void run(const DevReads& R, const CountParams& P, EdgesOut* out) {
+    const int k = P.k, kb = 2 * (k + 1);
+    Prep pr;
+    prepare(R, k, pr);
+    *out = EdgesOut{};
+    if (pr.NW == 0) return;
+    const uint64_t NW = pr.NW, words = pr.words;
+    ExArgs ea = pr.ea;
     const uint32_t nbins = 1u << ea.dbits;
     const uint64_t win_per_tile = (uint64_t)SDBG_BLOCK * IPT;
     const uint64_t ntiles = ceil_div(NW, win_per_tile);
@@ -1397,9 +1510,113 @@ struct Counter {
     }
     c.sync();
   }
+
+  // Several read sets in one pass, without mercy: R holds the sets' reads
+  // back to back, set s owns reads [rb[s], rb[s+1]).  The first cut is
+  // taken per set (tiles never straddle sets and the histogram table is
+  // set-major), so every later segment lies inside one set, and the
+  // refinement, leaf and compaction launches serve all sets at once.
+  // Output: one edge set per read set, each equal to a single-set run.
+  void run_sets(const DevReads& R, const std::vector<uint64_t>& rb, const CountParams& P, std::vector<EdgesOut>* outs) {
+    const int k = P.k, kb = 2 * (k + 1);
+    const uint64_t S = rb.size() - 1;
+    outs->assign(S, EdgesOut{});
+    Prep pr;
+    prepare(R, k, pr);
+    if (pr.NW == 0) return;
+    ExArgs ea = pr.ea;
+    // windows of each set
+    DBuf<uint64_t> rbd = c.buf<uint64_t>(S + 1), swd = c.buf<uint64_t>(S + 1);
+    c.h2d(rbd.get(), rb.data(), S + 1);
+    k_gather_idx<<<grid1(S + 1), SDBG_BLOCK, 0, c.s>>>(pr.woff.get(), rbd.get(), S + 1, swd.get());
+    c.check_launch("gather_idx");
+    std::vector<uint64_t> sw(S + 1);
+    c.d2h(sw.data(), swd.get(), S + 1);
+    // tiles per set (at least one, so that every set has table columns)
+    const uint64_t WPT = (uint64_t)SDBG_BLOCK * IPT;
+    std::vector<uint64_t> st(S + 1);
+    std::vector<uint32_t> tset;
+    uint64_t NT = 0;
+    for (uint64_t s = 0; s < S; ++s) {
+      const uint64_t nt = std::max<uint64_t>(1, ceil_div(sw[s + 1] - sw[s], WPT));
+      st[s] = NT;
+      NT += nt;
+      tset.insert(tset.end(), nt, (uint32_t)s);
+    }
+    st[S] = NT;
+    SDBG_CHECK(NT < (1ull << 31), -3, "too many reads for one launch");
+    DBuf<uint64_t> std_ = c.buf<uint64_t>(S + 1);
+    DBuf<uint32_t> tsd = c.buf<uint32_t>(NT);
+    c.h2d(std_.get(), st.data(), S + 1);
+    c.h2d(tsd.get(), tset.data(), NT);
+    ea.tset = tsd.get();
+    ea.sw = swd.get();
+    ea.st = std_.get();
+    const uint32_t nbins = 1u << ea.dbits;
+    DBuf<uint32_t> tab = c.buf<uint32_t>(NT * nbins);
+    DBuf<uint64_t> tot = c.buf<uint64_t>(1);
+    {
+      Stage st_(c, "ex_hist", 3 * pr.words * 8 + NT * nbins * 4);
+      k_ex_hist<W, IPT><<<(unsigned)NT, SDBG_BLOCK, 0, c.s>>>(ea, tab.get(), NT, nullptr);
+      c.check_launch("ex_hist");
+    }
+    scan_excl<uint32_t, uint32_t>(tab.get(), tab.get(), NT * nbins, tot.get(), c);
+    const uint64_t N = c.d2h_one(tot.get());
+    SDBG_CHECK(N <= 0xFFFFFFFFull, -3, "read sets too large for one pass");
+    DBuf<uint64_t> bufA = c.buf<uint64_t>(N * W), bufB = c.buf<uint64_t>(N * W);
+    DBuf<uint32_t> cnt = c.buf<uint32_t>(N);
+    uint64_t* hb[2] = {bufA.get(), bufB.get()};
+    DBuf<uint64_t*> db = c.buf<uint64_t*>(2);
+    c.h2d(db.get(), hb, 2);
+    if (N) {
+      Stage st_(c, "ex_scatter", 3 * pr.words * 8 + NT * nbins * 4 + N * 8 * W);
+      k_ex_scatter<W, IPT><<<(unsigned)NT, SDBG_BLOCK, 0, c.s>>>(ea, tab.get(), NT, bufA.get());
+      c.check_launch("ex_scatter");
+    }
+    SegList L;
+    L.alloc(c, S * nbins);
+    k_seg_init_sets<<<grid1(S * nbins), SDBG_BLOCK, 0, c.s>>>(tab.get(), std_.get(), S, ea.dbits, N, kb - ea.dbits,
+                                                              L.view());
+    c.check_launch("seg_init_sets");
+    refine(L, db.get());
+    DBuf<uint64_t> Sk, Lk, spos;
+    DBuf<uint32_t> Sc, Lc;
+    uint64_t nS = 0, nL = 0;
+    leaves(L, N, db.get(), cnt.get(), P.d, false, Sk, Sc, &nS, Lk, Lc, &nL, &spos);
+    DBuf<uint64_t> kbase = c.buf<uint64_t>(S + 1), obase = c.buf<uint64_t>(S + 1);
+    k_set_bounds<<<grid1(S + 1), SDBG_BLOCK, 0, c.s>>>(L.off.get(), L.n, spos.get(), tab.get(), std_.get(), ea.dbits,
+                                                       S, N, kbase.get(), obase.get());
+    c.check_launch("set_bounds");
+    std::vector<uint64_t> hk(S + 1), ho(S + 1);
+    c.d2h(hk.data(), kbase.get(), S + 1);
+    c.d2h(ho.data(), obase.get(), S + 1);
+    for (uint64_t s = 0; s < S; ++s) {
+      EdgesOut& o = (*outs)[s];
+      o.n_occ = hk[s + 1] - hk[s];
+      o.n = ho[s + 1] - ho[s];
+      DBuf<uint64_t> ok = c.buf<uint64_t>(o.n * W);
+      DBuf<uint32_t> oc = c.buf<uint32_t>(o.n);
+      c.d2d(ok.get(), Sk.get() + ho[s] * W, o.n * W);
+      c.d2d(oc.get(), Sc.get() + ho[s], o.n);
+      o.keys = ok.release_ownership();
+      o.count = oc.release_ownership();
+    }
+    c.sync();
+  }
 };
 
 }  // namespace
+
+void count_solid_sets(const DevReads& r, const std::vector<uint64_t>& rb, const CountParams& p, Ctx& c,
+                      std::vector<EdgesOut>* outs) {
+  switch (key_words(p.k)) {
+    case 1: Counter<1>(c).run_sets(r, rb, p, outs); break;
+    case 2: Counter<2>(c).run_sets(r, rb, p, outs); break;
+    case 3: Counter<3>(c).run_sets(r, rb, p, outs); break;
+    case 4: Counter<4>(c).run_sets(r, rb, p, outs); break;
+    default: throw Error(-1, "k out of range");
+  }
+}
 
 void count_solid(const DevReads& r, const CountParams& p, Ctx& c, EdgesOut* out) {
   switch (key_words(p.k)) {

@@ -100,6 +100,8 @@ def load(path: str | None = None):
     lib.sdbg_count_solid.restype = ctypes.c_int
     lib.sdbg_build.argtypes = [P(_Edges), P(_Params), P(P(_Graph))]
     lib.sdbg_build.restype = ctypes.c_int
+    lib.sdbg_batch_run.argtypes = [P(_Reads), ctypes.c_uint64, P(_Params), P(P(_Edges)), P(P(_Graph))]
+    lib.sdbg_batch_run.restype = ctypes.c_int
     lib.sdbg_edges_from_host.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, P(P(_Edges))]
     lib.sdbg_edges_from_host.restype = ctypes.c_int
     lib.sdbg_edges_to_host.argtypes = [P(_Edges), ctypes.c_void_p, ctypes.c_void_p]
@@ -269,6 +271,26 @@ def build(edges: Edges, stream=None) -> Graph:
     return Graph(out)
 
 
+def batch_run(sets, k: int, d: int = 2, mercy: bool = False, build: bool = True, prefix_len: int = 8,
+              mem_budget: int = 0, stream=None) -> list[tuple[Edges, Graph | None]]:
+    """Batched form: sets is a sequence of (seq, offsets) pairs (device
+    tensors or host arrays).  Returns one (Edges, Graph or None) per set."""
+    lib = load()
+    n = len(sets)
+    arr = (_Reads * max(n, 1))()
+    keep = []
+    for i, (seq, off) in enumerate(sets):
+        r, kp = _reads_struct(seq, off)
+        arr[i] = r
+        keep += kp
+    p = _Params(k, d, 1 if mercy else 0, prefix_len, mem_budget, _stream_ptr(stream))
+    eo = (ctypes.POINTER(_Edges) * max(n, 1))()
+    go = (ctypes.POINTER(_Graph) * max(n, 1))()
+    _check(lib.sdbg_batch_run(arr, n, ctypes.byref(p), eo, go if build else None))
+    del keep
+    return [(Edges(eo[i]), Graph(go[i]) if build else None) for i in range(n)]
+
+
 def edges_from_host(keys: np.ndarray, counts: np.ndarray, k: int) -> Edges:
     lib = load()
     w = key_words(k)
@@ -303,3 +325,114 @@ def profile_records() -> list[tuple[str, float, int]]:
         _check(lib.sdbg_profile_get(i, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(b)))
         out.append((name.value.decode(), ms.value, b.value))
     return out
+
+
+class _ServerCfg(ctypes.Structure):
+    _fields_ = [
+        ("max_jobs", ctypes.c_uint32),
+        ("queue_cap", ctypes.c_uint32),
+        ("mem_budget", ctypes.c_uint64),
+        ("build", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class _JobStats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_uint32),
+        ("submit_s", ctypes.c_double),
+        ("start_s", ctypes.c_double),
+        ("end_s", ctypes.c_double),
+        ("n_occ", ctypes.c_uint64),
+        ("footprint", ctypes.c_uint64),
+    ]
+
+
+@dataclasses.dataclass
+class JobResult:
+    status: int  # 0 done, 1 waiting, 2 running, < 0 error code
+    edges: Edges | None
+    graph: Graph | None
+    submit_s: float
+    start_s: float
+    end_s: float
+    n_occ: int
+    footprint: int
+    error: str = ""
+
+
+def _server_api(lib):
+    if getattr(lib, "_server_api", False):
+        return
+    P = ctypes.POINTER
+    lib.sdbg_server_start.argtypes = [P(_ServerCfg), ctypes.c_void_p]
+    lib.sdbg_server_start.restype = ctypes.c_int
+    lib.sdbg_server_submit.argtypes = [ctypes.c_void_p, P(_Reads), P(_Params), P(ctypes.c_uint64)]
+    lib.sdbg_server_submit.restype = ctypes.c_int
+    lib.sdbg_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, P(P(_Edges)), P(P(_Graph)),
+                                     P(_JobStats)]
+    lib.sdbg_server_poll.restype = ctypes.c_int
+    lib.sdbg_server_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    lib.sdbg_server_cancel.restype = ctypes.c_int
+    lib.sdbg_server_stop.argtypes = [ctypes.c_void_p]
+    lib.sdbg_server_stop.restype = ctypes.c_int
+    lib._server_api = True
+
+
+class Server:
+    """Served form (sdbg_server_*): a request loop on the current device."""
+
+    def __init__(self, max_jobs: int = 4, queue_cap: int = 0, mem_budget: int = 0, build: bool = True):
+        lib = load()
+        _server_api(lib)
+        cfg = _ServerCfg(max_jobs, queue_cap, mem_budget, 1 if build else 0, 0)
+        h = ctypes.c_void_p()
+        _check(lib.sdbg_server_start(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, seq, offsets, k: int, d: int = 2, mercy: bool = False, prefix_len: int = 8,
+               mem_budget: int = 0) -> int:
+        """Queues a job on host reads; raises SdbgError (code -5) if the queue is full."""
+        lib = load()
+        r, keep = _reads_struct(seq, offsets)
+        p = _Params(k, d, 1 if mercy else 0, prefix_len, mem_budget, None)
+        jid = ctypes.c_uint64()
+        _check(lib.sdbg_server_submit(self._h, ctypes.byref(r), ctypes.byref(p), ctypes.byref(jid)))
+        del keep
+        return jid.value
+
+    def poll(self, job_id: int, wait: bool = True) -> JobResult:
+        lib = load()
+        e = ctypes.POINTER(_Edges)()
+        g = ctypes.POINTER(_Graph)()
+        st = _JobStats()
+        rc = lib.sdbg_server_poll(self._h, job_id, 1 if wait else 0, ctypes.byref(e), ctypes.byref(g),
+                                  ctypes.byref(st))
+        err = "" if rc >= 0 else lib.sdbg_last_error().decode(errors="replace")
+        if rc == SDBG_OK:
+            return JobResult(0, Edges(e), Graph(g) if g else None, st.submit_s, st.start_s, st.end_s, st.n_occ,
+                             st.footprint)
+        if rc < 0 and st.status != rc:
+            raise SdbgError(rc, err)  # not a job's own result (e.g. unknown id)
+        return JobResult(rc, None, None, st.submit_s, st.start_s, st.end_s, st.n_occ, st.footprint, err)
+
+    def cancel(self, job_id: int) -> int:
+        return load().sdbg_server_cancel(self._h, job_id)
+
+    def stop(self):
+        if self._h:
+            _check(load().sdbg_server_stop(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

@@ -232,7 +232,7 @@ def batch_sets(n_sets: int = 4096, first: int = 0, read_scale: float = 1.0) -> l
         comm = make_community(1, int(glen[i]), int(glen[i]), 0.0, rng, log_uniform=False)
         n = max(1, int(round(nreads[i] * read_scale)))
         seq, off = sample_reads(comm, n, 100, 0.01, rng)
-        out.append(ReadSet(seq, off, k=31, d=2, mercy=True, name=f"batch[{i}]"))
+        out.append(ReadSet(seq, off, k=31, d=2, mercy=False, name=f"batch[{i}]"))
     return out
 
 
@@ -244,7 +244,7 @@ def batch_set(i: int, n_sets: int = 4096, read_scale: float = 1.0) -> ReadSet:
     comm = make_community(1, int(glen[i]), int(glen[i]), 0.0, rng, log_uniform=False)
     n = max(1, int(round(nreads[i] * read_scale)))
     seq, off = sample_reads(comm, n, 100, 0.01, rng)
-    return ReadSet(seq, off, k=31, d=2, mercy=True, name=f"batch[{i}]")
+    return ReadSet(seq, off, k=31, d=2, mercy=False, name=f"batch[{i}]")
 
 
 @dataclasses.dataclass
