@@ -100,6 +100,13 @@ def bench_batch(args):
             e.close()
         return occ
 
+    tuned = None
+    if args.autotune:
+        # tune on every 16th set (a sample of the size mix), then time all
+        sample = dev[::16]
+        t0 = time.perf_counter()
+        tuned = sdbg.autotune(sample, 31, reps=1)
+        log(f"autotune on {len(sample)} sets picked {tuned} in {time.perf_counter() - t0:.1f} s")
     out = {}
     for name, fn in (("batched", batched), ("sequential", sequential)):
         fn()  # warm-up (device memory pool)
@@ -117,7 +124,7 @@ def bench_batch(args):
             "unit": "Gmer/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u64", "data": "synthetic",
             "config": {"workload": f"first {len(sets)} sets of 4096: genome 20-500 kb, log-uniform 1k-1M reads "
                                    f"x {scale} of 100 bp, 1% err, k=31, d=2, mercy off", "n_occ": int(occ)},
-            "batched": out["batched"], "sequential": out["sequential"],
+            "batched": out["batched"], "sequential": out["sequential"], "tune": tuned or sdbg.tune_get(),
             "speedup": round(out["sequential"]["seconds"] / out["batched"]["seconds"], 3)}
     print(json.dumps(line), flush=True)
 
@@ -134,7 +141,7 @@ def bench_serve(args):
 
     sdbg.load()
     torch.cuda.set_device(0)
-    scale = 0.1 if args.read_scale is None else args.read_scale
+    scale = 0.5 if args.read_scale is None else args.read_scale
     t0 = time.perf_counter()
     pool = [j.reads for j in synth.serving_trace(1.0, args.pool, read_scale=scale, genome_scale=0.1)]
     log(f"generated {len(pool)} jobs, {sum(r.n_reads for r in pool)} reads in {time.perf_counter() - t0:.1f} s")
@@ -218,6 +225,7 @@ def main():
     ap.add_argument("--read-scale", type=float, default=None, help="batch/serve: scale of the read counts")
     ap.add_argument("--rates", default="1,2,5,10,20,50", help="serve: arrival rates (jobs/s)")
     ap.add_argument("--pool", type=int, default=32, help="serve: distinct jobs in the pool")
+    ap.add_argument("--autotune", action="store_true", help="batch: pick launch parameters on a sample first")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it", "n_gpus": args.gpus}))

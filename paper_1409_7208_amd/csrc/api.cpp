@@ -1,8 +1,12 @@
 // C ABI of the SdBG library (declared in include/sdbg.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cstdlib>
 #include <cstring>
+#include <thread>
 #include <mutex>
 #include <new>
 #include <string>
@@ -117,6 +121,9 @@ uint64_t occ_bound(const std::vector<uint64_t>& o, uint32_t k) {
 // Device bytes per key of a batched pass: two key buffers, counts, solid
 // output and its per-set copy, plus the reads' share.
 uint64_t batch_bytes_per_key(uint32_t w) { return 32ull * w + 16; }
+
+// Host threads (and streams) building the graphs of a batch.
+constexpr unsigned kBuildThreads = 4;
 
 uint64_t device_budget(const sdbg_params* p) {
   if (p->mem_budget) return p->mem_budget;
@@ -346,13 +353,52 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
       s0 = s1;
     }
     if (graphs_out) {
-      for (uint64_t s = 0; s < n_sets; ++s) {
-        sdbg::GraphOut go;
-        sdbg::build_graph(edges_out[s]->keys, edges_out[s]->count, edges_out[s]->n, (int)k, c, &go);
-        c.sync();
-        graphs_out[s] = wrap_graph(go, k);
-        made.push_back(graphs_out[s]);
+      // The sets' graphs are built by a few host threads, each on a stream
+      // of its own, so that one set's size read-backs overlap with the
+      // kernels of the others.
+      c.sync();
+      const unsigned nth = (unsigned)std::min<uint64_t>(kBuildThreads, n_sets);
+      int dev = 0;
+      SDBG_HIP(hipGetDevice(&dev));
+      std::atomic<uint64_t> next{0};
+      std::atomic<bool> failed{false};
+      std::vector<int> rcs(nth, SDBG_OK);
+      std::vector<std::string> errs(nth);
+      std::vector<std::thread> th;
+      for (unsigned t = 0; t < nth; ++t) {
+        th.emplace_back([&, t] {
+          rcs[t] = guarded([&]() -> int {
+            SDBG_HIP(hipSetDevice(dev));
+            hipStream_t st = nullptr;
+            SDBG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            try {
+              sdbg::Ctx c2(st);
+              for (;;) {
+                const uint64_t i = next.fetch_add(1);
+                if (i >= n_sets || failed.load()) break;
+                sdbg::GraphOut go;
+                sdbg::build_graph(edges_out[i]->keys, edges_out[i]->count, edges_out[i]->n, (int)k, c2, &go);
+                c2.sync();
+                graphs_out[i] = wrap_graph(go, k);
+              }
+            } catch (...) {
+              (void)hipStreamDestroy(st);
+              throw;
+            }
+            (void)hipStreamDestroy(st);
+            return SDBG_OK;
+          });
+          if (rcs[t] != SDBG_OK) {
+            errs[t] = t_err;
+            failed.store(true);
+          }
+        });
       }
+      for (auto& x : th) x.join();
+      for (uint64_t s = 0; s < n_sets; ++s)
+        if (graphs_out[s]) made.push_back(graphs_out[s]);
+      for (unsigned t = 0; t < nth; ++t)
+        if (rcs[t] != SDBG_OK) throw sdbg::Error(rcs[t], errs[t]);
     }
     sdbg::prof_flush();
     return SDBG_OK;
@@ -365,6 +411,89 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
     }
   }
   return rc;
+}
+
+int sdbg_tune_get(sdbg_tune* t) {
+  return guarded([&]() -> int {
+    SDBG_CHECK(t, SDBG_E_INVAL, "null argument");
+    const sdbg::SortTune x = sdbg::sort_tune();
+    t->digit_bits = (uint32_t)x.digit_bits;
+    t->tile_shift = (uint32_t)x.tile_shift;
+    t->leaf_wg_per_cu = (uint32_t)x.leaf_wg_per_cu;
+    t->reserved = 0;
+    return SDBG_OK;
+  });
+}
+
+int sdbg_tune_set(const sdbg_tune* t) {
+  return guarded([&]() -> int {
+    sdbg::SortTune x;
+    if (t) {
+      x.digit_bits = (int)t->digit_bits;
+      x.tile_shift = (int)t->tile_shift;
+      x.leaf_wg_per_cu = (int)t->leaf_wg_per_cu;
+    }
+    sdbg::set_sort_tune(x);
+    return SDBG_OK;
+  });
+}
+
+int sdbg_autotune(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* params, uint32_t reps, sdbg_tune* best) {
+  return guarded([&]() -> int {
+    SDBG_CHECK(params && (sets || n_sets == 0), SDBG_E_INVAL, "null argument");
+    check_params(params);
+    if (!reps) reps = 3;
+    std::vector<sdbg_edges*> eo(n_sets ? n_sets : 1);
+    // Median wall time of reps batched counts of the sample (each call
+    // waits for its stream, so the host clock brackets the device work).
+    auto time_it = [&](const sdbg::SortTune& t) -> double {
+      sdbg::set_sort_tune(t);
+      std::vector<double> ts;
+      for (uint32_t r = 0; r <= reps; ++r) {  // the first run warms the memory pool
+        const auto a = std::chrono::steady_clock::now();
+        const int rc = sdbg_batch_run(sets, n_sets, params, eo.data(), nullptr);
+        const auto b = std::chrono::steady_clock::now();
+        if (rc != SDBG_OK) throw sdbg::Error(rc, t_err);
+        for (uint64_t s = 0; s < n_sets; ++s) sdbg_free(eo[s]);
+        if (r) ts.push_back(std::chrono::duration<double>(b - a).count());
+      }
+      std::sort(ts.begin(), ts.end());
+      return ts[ts.size() / 2];
+    };
+    const sdbg::SortTune start = sdbg::sort_tune();
+    sdbg::SortTune cur = start;
+    try {
+      double best_t = time_it(cur);
+      // coordinate descent over the three knobs
+      const int digit_vals[] = {6, 7, 8}, shift_vals[] = {0, 1}, wpc_vals[] = {4, 8, 16, 32};
+      for (int knob = 0; knob < 3; ++knob) {
+        const int* vals = knob == 0 ? digit_vals : knob == 1 ? shift_vals : wpc_vals;
+        const int nv = knob == 0 ? 3 : knob == 1 ? 2 : 4;
+        for (int i = 0; i < nv; ++i) {
+          sdbg::SortTune t = cur;
+          int& f = knob == 0 ? t.digit_bits : knob == 1 ? t.tile_shift : t.leaf_wg_per_cu;
+          if (f == vals[i]) continue;
+          f = vals[i];
+          const double x = time_it(t);
+          if (x < best_t) {
+            best_t = x;
+            cur = t;
+          }
+        }
+      }
+    } catch (...) {
+      sdbg::set_sort_tune(start);
+      throw;
+    }
+    sdbg::set_sort_tune(cur);
+    if (best) {
+      best->digit_bits = (uint32_t)cur.digit_bits;
+      best->tile_shift = (uint32_t)cur.tile_shift;
+      best->leaf_wg_per_cu = (uint32_t)cur.leaf_wg_per_cu;
+      best->reserved = 0;
+    }
+    return SDBG_OK;
+  });
 }
 
 int sdbg_edges_from_host(const uint64_t* keys, const uint32_t* count, uint64_t n, uint32_t k, sdbg_edges** out) {

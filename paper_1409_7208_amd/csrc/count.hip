@@ -962,6 +962,22 @@ inline unsigned grid1(uint64_t n) {
   return (unsigned)(g ? g : 1);
 }
 
+std::mutex g_tune_mu;
+SortTune g_tune;
+
+int cu_count() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      n = v;
+    else
+      n = 256;
+  }
+  return n;
+}
+
 struct SegList {
   DBuf<uint64_t> off, len;
   DBuf<uint16_t> bit;
@@ -1049,7 +1065,27 @@ template <int W>
 struct Counter {
   static constexpr int IPT = Tune<W>::IPT, TK = Tune<W>::TK, CAP = Tune<W>::CAP;
   Ctx& c;
-  explicit Counter(Ctx& c_) : c(c_) {}
+  SortTune tune;
+  explicit Counter(Ctx& c_) : c(c_), tune(sort_tune()) {}
+
+  // Histogram and scatter of one refinement level with tiles of TKX keys.
+  template <int TKX>
+  void seg_pass(SegList& L, uint64_t* const* d_bufs, uint64_t NT, uint64_t NTab, uint64_t moved, DBuf<uint32_t>& tile_seg,
+                DBuf<uint64_t>& tile_first, DBuf<uint64_t>& tab_base, DBuf<uint32_t>& tab) {
+    {
+      Stage st_(c, "seg_hist", moved * 8 * W + NTab * 4);
+      k_seg_hist<W, TKX><<<(unsigned)NT, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, tile_seg.get(), tile_first.get(),
+                                                                 tab_base.get(), tab.get());
+      c.check_launch("seg_hist");
+    }
+    scan_excl<uint32_t, uint32_t>(tab.get(), tab.get(), NTab, nullptr, c);
+    {
+      Stage st_(c, "seg_scatter", moved * 16 * W + NTab * 4);
+      k_seg_scatter<W, TKX><<<(unsigned)NT, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, tile_seg.get(), tile_first.get(),
+                                                                    tab_base.get(), tab.get());
+      c.check_launch("seg_scatter");
+    }
+  }
 
   // Cut every segment longer than CAP (while it has key bits left) until
   // all fit a leaf; data ping-pongs between bufs[0] and bufs[1] at equal
@@ -1068,11 +1104,12 @@ struct Counter {
       VLOG("refine level %d: %llu segments, %llu oversized holding %llu keys", level, (unsigned long long)L.n,
            hs[0], hs[1]);
       int D = 1;
-      while (D < 8 && (avg >> D) > (uint64_t)CAP / 2) ++D;
+      while (D < tune.digit_bits && (avg >> D) > (uint64_t)CAP / 2) ++D;
+      const int tk = TK >> tune.tile_shift;
       DBuf<uint64_t> ntiles = c.buf<uint64_t>(L.n), tabsz = c.buf<uint64_t>(L.n);
       DBuf<uint64_t> tile_first = c.buf<uint64_t>(L.n), tab_base = c.buf<uint64_t>(L.n);
       DBuf<uint64_t> tot = c.buf<uint64_t>(2);
-      k_seg_mark<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), CAP, D, TK, ntiles.get(), tabsz.get());
+      k_seg_mark<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), CAP, D, tk, ntiles.get(), tabsz.get());
       c.check_launch("seg_mark");
       scan_excl<uint64_t, uint64_t>(ntiles.get(), tile_first.get(), L.n, tot.get(), c);
       scan_excl<uint64_t, uint64_t>(tabsz.get(), tab_base.get(), L.n, tot.get() + 1, c);
@@ -1083,27 +1120,18 @@ struct Counter {
       DBuf<uint32_t> tile_seg = c.buf<uint32_t>(NT), tab = c.buf<uint32_t>(NTab);
       k_seg_tiles<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), tile_first.get(), ntiles.get(), tile_seg.get());
       c.check_launch("seg_tiles");
-      {
-        Stage st_(c, "seg_hist", hs[1] * 8 * W + NTab * 4);
-        k_seg_hist<W, TK><<<(unsigned)NT, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, tile_seg.get(), tile_first.get(),
-                                                                  tab_base.get(), tab.get());
-        c.check_launch("seg_hist");
-      }
-      scan_excl<uint32_t, uint32_t>(tab.get(), tab.get(), NTab, nullptr, c);
-      {
-        Stage st_(c, "seg_scatter", hs[1] * 16 * W + NTab * 4);
-        k_seg_scatter<W, TK><<<(unsigned)NT, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, tile_seg.get(), tile_first.get(),
-                                                                     tab_base.get(), tab.get());
-        c.check_launch("seg_scatter");
-      }
+      if (tk == TK)
+        seg_pass<TK>(L, d_bufs, NT, NTab, hs[1], tile_seg, tile_first, tab_base, tab);
+      else
+        seg_pass<TK / 2>(L, d_bufs, NT, NTab, hs[1], tile_seg, tile_first, tab_base, tab);
       DBuf<uint64_t> ncnt = c.buf<uint64_t>(L.n), npos = c.buf<uint64_t>(L.n);
-      k_seg_newcount<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), TK, tab_base.get(), tab.get(), ncnt.get());
+      k_seg_newcount<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), tk, tab_base.get(), tab.get(), ncnt.get());
       c.check_launch("seg_newcount");
       scan_excl<uint64_t, uint64_t>(ncnt.get(), npos.get(), L.n, tot.get(), c);
       const uint64_t nn = c.d2h_one(tot.get());
       SegList N;
       N.alloc(c, nn);
-      k_seg_newwrite<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), TK, tab_base.get(), tab.get(), npos.get(), N.view());
+      k_seg_newwrite<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), tk, tab_base.get(), tab.get(), npos.get(), N.view());
       c.check_launch("seg_newwrite");
       L = std::move(N);
     }
@@ -1123,7 +1151,7 @@ struct Counter {
       Stage st_(c, "leaf", nkeys * 8 * W);
       DBuf<uint64_t> work = c.buf<uint64_t>(1);
       fill<uint64_t>(work.get(), 1, 0, c);
-      const unsigned lgrid = (unsigned)std::min<uint64_t>(L.n, 256 * 16);
+      const unsigned lgrid = (unsigned)std::min<uint64_t>(L.n, (uint64_t)cu_count() * tune.leaf_wg_per_cu);
       k_leaf<W, CAP><<<lgrid, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, cnt, dmin, want_low ? 1 : 0,
                                                               nsolid.get(), nlow.get(),
                                                        reinterpret_cast<unsigned long long*>(work.get()));
@@ -1606,6 +1634,19 @@ struct Counter {
 };
 
 }  // namespace
+
+SortTune sort_tune() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tune;
+}
+
+void set_sort_tune(const SortTune& t) {
+  SDBG_CHECK(t.digit_bits >= 4 && t.digit_bits <= 8, -1, "digit_bits must be in [4, 8]");
+  SDBG_CHECK(t.tile_shift == 0 || t.tile_shift == 1, -1, "tile_shift must be 0 or 1");
+  SDBG_CHECK(t.leaf_wg_per_cu >= 1 && t.leaf_wg_per_cu <= 32, -1, "leaf_wg_per_cu must be in [1, 32]");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune = t;
+}
 
 void count_solid_sets(const DevReads& r, const std::vector<uint64_t>& rb, const CountParams& p, Ctx& c,
                       std::vector<EdgesOut>* outs) {

@@ -74,6 +74,16 @@ class Stage {
   hipEvent_t a_ = nullptr;
 };
 
+// Launch parameters of the partition/sort engine.  Results never depend on
+// them; they only move work between passes and workgroups.
+struct SortTune {
+  int digit_bits = 8;       // most key bits one refinement pass cuts (4..8)
+  int tile_shift = 0;       // refinement tile = the width's default tile >> tile_shift (0 or 1)
+  int leaf_wg_per_cu = 16;  // persistent leaf workgroups per compute unit (1..32)
+};
+SortTune sort_tune();
+void set_sort_tune(const SortTune& t);
+
 void count_solid(const DevReads& r, const CountParams& p, Ctx& c, EdgesOut* out);
 // Several read sets (reads [rb[s], rb[s+1]) of r) counted together, mercy
 // off; outs[s] equals count_solid of set s alone.

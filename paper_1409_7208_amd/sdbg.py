@@ -291,6 +291,65 @@ def batch_run(sets, k: int, d: int = 2, mercy: bool = False, build: bool = True,
     return [(Edges(eo[i]), Graph(go[i]) if build else None) for i in range(n)]
 
 
+class _Tune(ctypes.Structure):
+    _fields_ = [
+        ("digit_bits", ctypes.c_uint32),
+        ("tile_shift", ctypes.c_uint32),
+        ("leaf_wg_per_cu", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+def _tune_api(lib):
+    if getattr(lib, "_tune_api", False):
+        return
+    P = ctypes.POINTER
+    lib.sdbg_tune_get.argtypes = [P(_Tune)]
+    lib.sdbg_tune_get.restype = ctypes.c_int
+    lib.sdbg_tune_set.argtypes = [P(_Tune)]
+    lib.sdbg_tune_set.restype = ctypes.c_int
+    lib.sdbg_autotune.argtypes = [P(_Reads), ctypes.c_uint64, P(_Params), ctypes.c_uint32, P(_Tune)]
+    lib.sdbg_autotune.restype = ctypes.c_int
+    lib._tune_api = True
+
+
+def tune_get() -> dict:
+    lib = load()
+    _tune_api(lib)
+    t = _Tune()
+    _check(lib.sdbg_tune_get(ctypes.byref(t)))
+    return {"digit_bits": t.digit_bits, "tile_shift": t.tile_shift, "leaf_wg_per_cu": t.leaf_wg_per_cu}
+
+
+def tune_set(t: dict | None = None):
+    """Sets the engine's launch parameters (None restores the defaults)."""
+    lib = load()
+    _tune_api(lib)
+    if t is None:
+        _check(lib.sdbg_tune_set(None))
+    else:
+        _check(lib.sdbg_tune_set(ctypes.byref(_Tune(t["digit_bits"], t["tile_shift"], t["leaf_wg_per_cu"], 0))))
+
+
+def autotune(sets, k: int, d: int = 2, mercy: bool = False, reps: int = 3) -> dict:
+    """Picks the fastest launch parameters on a sample of read sets (the
+    batched count) and leaves them in effect."""
+    lib = load()
+    _tune_api(lib)
+    n = len(sets)
+    arr = (_Reads * max(n, 1))()
+    keep = []
+    for i, (seq, off) in enumerate(sets):
+        r, kp = _reads_struct(seq, off)
+        arr[i] = r
+        keep += kp
+    p = _Params(k, d, 1 if mercy else 0, 8, 0, None)
+    t = _Tune()
+    _check(lib.sdbg_autotune(arr, n, ctypes.byref(p), reps, ctypes.byref(t)))
+    del keep
+    return {"digit_bits": t.digit_bits, "tile_shift": t.tile_shift, "leaf_wg_per_cu": t.leaf_wg_per_cu}
+
+
 def edges_from_host(keys: np.ndarray, counts: np.ndarray, k: int) -> Edges:
     lib = load()
     w = key_words(k)

@@ -77,3 +77,26 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(sdbg, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         sdbg.load(str(tmp_path / "nope.so"))
+
+
+def test_tune_parameters_validated_on_host():
+    """The launch-parameter setter is host-only: range checks and round trip."""
+    _ensure_built()
+    sdbg.load()
+    sdbg.tune_set(None)
+    default = sdbg.tune_get()
+    assert default == {"digit_bits": 8, "tile_shift": 0, "leaf_wg_per_cu": 16}
+    for bad in ({"digit_bits": 3, "tile_shift": 0, "leaf_wg_per_cu": 16},
+                {"digit_bits": 9, "tile_shift": 0, "leaf_wg_per_cu": 16},
+                {"digit_bits": 8, "tile_shift": 2, "leaf_wg_per_cu": 16},
+                {"digit_bits": 8, "tile_shift": 0, "leaf_wg_per_cu": 0},
+                {"digit_bits": 8, "tile_shift": 0, "leaf_wg_per_cu": 33}):
+        with pytest.raises(sdbg.SdbgError) as ei:
+            sdbg.tune_set(bad)
+        assert ei.value.code == -1
+        assert sdbg.tune_get() == default
+    t = {"digit_bits": 6, "tile_shift": 1, "leaf_wg_per_cu": 8}
+    sdbg.tune_set(t)
+    assert sdbg.tune_get() == t
+    sdbg.tune_set(None)
+    assert sdbg.tune_get() == default

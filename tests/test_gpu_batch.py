@@ -131,3 +131,64 @@ def test_batch_edges_only_and_empty():
     for e, g in res:
         assert g is None and e.n == 0 and e.n_occ == 0
         e.close()
+
+
+TUNES = [
+    {"digit_bits": 4, "tile_shift": 1, "leaf_wg_per_cu": 1},
+    {"digit_bits": 6, "tile_shift": 0, "leaf_wg_per_cu": 4},
+    {"digit_bits": 7, "tile_shift": 1, "leaf_wg_per_cu": 32},
+]
+
+
+@pytest.mark.parametrize("k", [31, 41, 99])
+def test_launch_parameters_do_not_change_results(k):
+    """Every autotuner candidate gives the same bytes (batched and plain)."""
+    sets = _sets(300 + k, 12, k)
+    big = synth.metagenome_long(scale=0.001, k=k)
+    dev = [to_device(rs) for rs in sets]
+    bseq, boff = to_device(big)
+    sdbg.tune_set(None)
+    ref = sdbg.batch_run(dev, k, 2, False)
+    ref_keys = [e.to_host() for e, _ in ref]
+    e0 = sdbg.count_solid(bseq, boff, k, 2, True)
+    big_ref = e0.to_host()
+    try:
+        for t in TUNES:
+            say(f"tune {t} k={k}")
+            sdbg.tune_set(t)
+            assert sdbg.tune_get() == t
+            res = sdbg.batch_run(dev, k, 2, False)
+            for (e, g), (rk, rc), (_, rg) in zip(res, ref_keys, ref):
+                kk, cc = e.to_host()
+                assert np.array_equal(kk, rk) and np.array_equal(cc, rc)
+                assert_graph_equal(g.to_host(), rg.to_host())
+            _close(res)
+            e1 = sdbg.count_solid(bseq, boff, k, 2, True)
+            kk, cc = e1.to_host()
+            assert np.array_equal(kk, big_ref[0]) and np.array_equal(cc, big_ref[1])
+            e1.close()
+    finally:
+        sdbg.tune_set(None)
+    e0.close()
+    _close(ref)
+
+
+def test_autotune_keeps_results():
+    sets = [synth.batch_set(i, read_scale=0.003) for i in range(64)]
+    dev = [to_device(rs) for rs in sets]
+    sdbg.tune_set(None)
+    ref = sdbg.batch_run(dev, 31, 2, False, build=False)
+    try:
+        best = sdbg.autotune(dev, 31, reps=1)
+        say(f"autotune picked {best}")
+        assert best == sdbg.tune_get()
+        assert best["digit_bits"] in (6, 7, 8) and best["tile_shift"] in (0, 1)
+        assert best["leaf_wg_per_cu"] in (4, 8, 16, 32)
+        res = sdbg.batch_run(dev, 31, 2, False, build=False)
+        for (e, _), (r, _) in zip(res, ref):
+            a, b = e.to_host(), r.to_host()
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        _close(res)
+    finally:
+        sdbg.tune_set(None)
+    _close(ref)
