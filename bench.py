@@ -206,6 +206,15 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def parse_tune(spec: str) -> dict:
+    t = {}
+    for part in spec.split(","):
+        if part.strip():
+            k, v = part.split("=")
+            t[k.strip()] = int(v)
+    return t
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +235,9 @@ def main():
     ap.add_argument("--rates", default="1,2,5,10,20,50", help="serve: arrival rates (jobs/s)")
     ap.add_argument("--pool", type=int, default=32, help="serve: distinct jobs in the pool")
     ap.add_argument("--autotune", action="store_true", help="batch: pick launch parameters on a sample first")
+    ap.add_argument("--tune", default="", help="launch parameters, e.g. leaf_cap_shift=1,leaf_wg_per_cu=8")
+    ap.add_argument("--sweep", default="",
+                    help="plain: also time these launch-parameter settings (';'-separated --tune strings), stderr only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it", "n_gpus": args.gpus}))
@@ -241,6 +253,8 @@ def main():
 
     sdbg.load()
     torch.cuda.set_device(0)
+    if args.tune:
+        sdbg.tune_set(parse_tune(args.tune))
     t0 = time.perf_counter()
     rs, desc = make_workload(args.workload, args.scale)
     log(f"generated {rs.n_reads} reads in {time.perf_counter() - t0:.1f} s")
@@ -284,6 +298,22 @@ def main():
     n_occ = r[0]
     value = n_occ / (ms / 1e3) / 1e9
     log(f"timed {args.steps} steps: {ms:.2f} ms/step (wall {wall / args.steps * 1e3:.2f} ms/step), {value:.2f} Gmer/s")
+
+    for spec in [x for x in args.sweep.split(";") if x.strip()]:
+        base = sdbg.tune_get()
+        sdbg.tune_set(parse_tune(spec))
+        step()
+        torch.cuda.synchronize()
+        ea = torch.cuda.Event(enable_timing=True)
+        eb = torch.cuda.Event(enable_timing=True)
+        ea.record(stream)
+        for _ in range(args.steps):
+            step()
+        eb.record(stream)
+        torch.cuda.synchronize()
+        sms = ea.elapsed_time(eb) / args.steps
+        log(f"sweep {spec}: {sms:.2f} ms/step, {n_occ / (sms / 1e3) / 1e9:.2f} Gmer/s")
+        sdbg.tune_set(base)
 
     recs = sdbg.profile_records()
     if args.stages:
@@ -334,6 +364,7 @@ def main():
                    "tips": int(r[4])},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "tune": sdbg.tune_get(),
     }
     print(json.dumps(out), flush=True)
 

@@ -151,17 +151,20 @@ int sdbg_batch_run(const sdbg_reads *sets, uint64_t n_sets, const sdbg_params *p
 
 /* Launch parameters of the partition and sort, process-wide.  Results do
  * not depend on them.
- *   digit_bits      most key bits one refinement pass cuts, 4..8 (8)
+ *   digit_bits      most key bits one refinement pass cuts, 4..8 (7)
  *   tile_shift      refinement pass tile = the key width's default tile
  *                   (4096, 2048, 1024, 1024 keys for w = 1..4) >> tile_shift,
  *                   0 or 1 (0)
  *   leaf_wg_per_cu  persistent workgroups per compute unit of the in-LDS
- *                   sort and count, 1..32 (16) */
+ *                   sort and count, 1..32 (16; fewer if fewer fit)
+ *   leaf_cap_shift  largest segment sorted in LDS = the key width's default
+ *                   (2048, 1024, 1024, 1024 keys for w = 1..4) >> leaf_cap_shift,
+ *                   0 or 1 (0) */
 typedef struct sdbg_tune {
   uint32_t digit_bits;
   uint32_t tile_shift;
   uint32_t leaf_wg_per_cu;
-  uint32_t reserved;
+  uint32_t leaf_cap_shift;
 } sdbg_tune;
 
 int sdbg_tune_get(sdbg_tune *t);
@@ -170,7 +173,8 @@ int sdbg_tune_set(const sdbg_tune *t);
 
 /* Autotuner: times reps (0 = 3) batched counts (sdbg_batch_run without
  * graphs) of the sample sets for each candidate value of one parameter at
- * a time (digit_bits 6..8, tile_shift 0..1, leaf_wg_per_cu 4..32), keeps
+ * a time (digit_bits 6..8, tile_shift 0..1, leaf_wg_per_cu 4..32,
+ * leaf_cap_shift 0..1), keeps
  * the fastest, and leaves the best setting in effect (also copied to *best
  * if not NULL).  On error the previous setting is restored. */
 int sdbg_autotune(const sdbg_reads *sets, uint64_t n_sets, const sdbg_params *params, uint32_t reps, sdbg_tune *best);

@@ -420,7 +420,7 @@ int sdbg_tune_get(sdbg_tune* t) {
     t->digit_bits = (uint32_t)x.digit_bits;
     t->tile_shift = (uint32_t)x.tile_shift;
     t->leaf_wg_per_cu = (uint32_t)x.leaf_wg_per_cu;
-    t->reserved = 0;
+    t->leaf_cap_shift = (uint32_t)x.leaf_cap_shift;
     return SDBG_OK;
   });
 }
@@ -432,6 +432,7 @@ int sdbg_tune_set(const sdbg_tune* t) {
       x.digit_bits = (int)t->digit_bits;
       x.tile_shift = (int)t->tile_shift;
       x.leaf_wg_per_cu = (int)t->leaf_wg_per_cu;
+      x.leaf_cap_shift = (int)t->leaf_cap_shift;
     }
     sdbg::set_sort_tune(x);
     return SDBG_OK;
@@ -466,12 +467,12 @@ int sdbg_autotune(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* pa
       double best_t = time_it(cur);
       // coordinate descent over the three knobs
       const int digit_vals[] = {6, 7, 8}, shift_vals[] = {0, 1}, wpc_vals[] = {4, 8, 16, 32};
-      for (int knob = 0; knob < 3; ++knob) {
-        const int* vals = knob == 0 ? digit_vals : knob == 1 ? shift_vals : wpc_vals;
-        const int nv = knob == 0 ? 3 : knob == 1 ? 2 : 4;
+      for (int knob = 0; knob < 4; ++knob) {
+        const int* vals = knob == 0 ? digit_vals : knob == 2 ? wpc_vals : shift_vals;
+        const int nv = knob == 0 ? 3 : knob == 2 ? 4 : 2;
         for (int i = 0; i < nv; ++i) {
           sdbg::SortTune t = cur;
-          int& f = knob == 0 ? t.digit_bits : knob == 1 ? t.tile_shift : t.leaf_wg_per_cu;
+          int& f = knob == 0 ? t.digit_bits : knob == 1 ? t.tile_shift : knob == 2 ? t.leaf_wg_per_cu : t.leaf_cap_shift;
           if (f == vals[i]) continue;
           f = vals[i];
           const double x = time_it(t);
@@ -490,7 +491,7 @@ int sdbg_autotune(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* pa
       best->digit_bits = (uint32_t)cur.digit_bits;
       best->tile_shift = (uint32_t)cur.tile_shift;
       best->leaf_wg_per_cu = (uint32_t)cur.leaf_wg_per_cu;
-      best->reserved = 0;
+      best->leaf_cap_shift = (uint32_t)cur.leaf_cap_shift;
     }
     return SDBG_OK;
   });

@@ -522,17 +522,21 @@ __global__ void k_seg_newwrite(SegView v, int tk, const uint64_t* __restrict__ t
 }
 
 // ------------------------------------------------------------ leaves
-// One workgroup per leaf segment.  Keys are loaded into LDS and their
-// duplicates are merged first with an LDS hash table (one slot per distinct
-// key: owner element in the high 16 bits, count in the low 16 bits, updated
-// with LDS atomics), so that a key seen hundreds of times costs one atomic
-// per copy instead of a serial run for one thread.  The distinct keys are
-// then counting-sorted by the next B key bits, each thread finishes a
-// contiguous range of bins with an insertion sort (bins hold about one
-// distinct key), and the keys with count >= dmin (and, if want_low, those
-// below, after them) are written back in place at the segment's start,
-// counts into cnt[] at the same positions.  A segment longer than CAP has
-// no key bits left to cut, so all its keys are equal.
+// Persistent workgroups walk the leaf segments with a fixed stride (grid
+// sized to the resident capacity), and each one loads the next segment's
+// descriptor and keys into registers while it sorts the current one, so
+// the global-memory latency of a segment overlaps the LDS work of the one
+// before.  Per segment: duplicates are merged first with an LDS hash table
+// (one slot per distinct key: owner element in the high 16 bits, count in
+// the low 16 bits, updated with LDS atomics), so that a key seen hundreds
+// of times costs one atomic per copy instead of a serial run for one
+// thread.  Only the distinct keys that will be written (count >= dmin, or
+// all when want_low) are then counting-sorted by their next B key bits;
+// each thread finishes a contiguous range of bins with an insertion sort,
+// and the keys with count >= dmin (then, if want_low, those below) are
+// written back in place at the segment's start, counts into cnt[] at the
+// same positions.  A segment longer than CAP has no key bits left to cut,
+// so all its keys are equal.
 template <int W>
 DEV uint32_t leaf_hash(const Key<W>& k) {
   uint32_t h = 0;
@@ -541,14 +545,18 @@ DEV uint32_t leaf_hash(const Key<W>& k) {
   return h * 0x9E3779B1u;
 }
 
+template <int CAP>
+struct LeafShape {
+  static constexpr int PER = CAP / SDBG_BLOCK;
+  static constexpr int H = 2 * CAP;  // hash slots, load <= 1/2
+  static constexpr int MAXB = CAP >= 1024 ? 9 : 8;  // bins <= 512: a few output keys per bin at most
+};
+
 template <int W, int CAP>
 __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const* __restrict__ bufs,
                                                      uint32_t* __restrict__ cnt, uint32_t dmin, int want_low,
-                                                     uint64_t* __restrict__ nsolid, uint64_t* __restrict__ nlow,
-                                                     unsigned long long* __restrict__ work) {
-  constexpr int PER = CAP / SDBG_BLOCK;
-  constexpr int H = 2 * CAP;  // hash slots, load <= 1/2
-  constexpr int MAXB = CAP >= 4096 ? 12 : CAP >= 2048 ? 11 : CAP >= 1024 ? 10 : 9;
+                                                     uint64_t* __restrict__ nsolid, uint64_t* __restrict__ nlow) {
+  constexpr int PER = LeafShape<CAP>::PER, H = LeafShape<CAP>::H, MAXB = LeafShape<CAP>::MAXB;
   constexpr uint32_t EMPTY = 0xFFFFFFFFu;
   static_assert(CAP <= 4096 && H <= 65536, "leaf sizes");
   __shared__ uint64_t A[CAP * W];
@@ -556,152 +564,181 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
   __shared__ uint16_t idx[CAP];
   __shared__ uint32_t bins[(1 << MAXB) + 1];
   __shared__ uint32_t sc[SDBG_WAVES + 1];
-  __shared__ uint64_t next_seg;
-  for (;;) {
-  // Persistent: workgroups take segments from a counter until none is left
-  // (the exit test is uniform across the workgroup).
-  __syncthreads();
-  if (threadIdx.x == 0) next_seg = atomicAdd(work, 1ull);
-  __syncthreads();
-  // uniform across the workgroup: keep it in scalar registers
-  const uint64_t s = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(next_seg >> 32)) << 32) |
-                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)next_seg);
-  if (s >= v.n) break;
-  const uint64_t len = v.len[s];
-  uint64_t* keys = bufs[v.buf[s]] + v.off[s] * W;
-  uint32_t* cn = cnt + v.off[s];
-  if (len > CAP) {
-    if (threadIdx.x == 0) {
-      const uint32_t c = len > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)len;
-      const bool solid = len >= dmin;
-      if (solid || want_low) cn[0] = c;
-      nsolid[s] = solid;
-      nlow[s] = !solid && want_low;
-    }
-    continue;
-  }
-  const int n = (int)len;
-  const uint32_t hshift = 32 - (uint32_t)__builtin_ctz((uint32_t)H);
-  for (int i = threadIdx.x; i < n; i += SDBG_BLOCK) key_store<W>(&A[i * W], key_load<W>(keys + (uint64_t)i * W));
-  for (int i = threadIdx.x; i < H; i += SDBG_BLOCK) hs[i] = EMPTY;
-  __syncthreads();
-  // 1. merge duplicates; the element that claims a slot represents its key
-  uint32_t rep[PER];  // representative's hash slot (| digit << 16 once binned), else EMPTY
-  uint32_t rsl[PER];  // its place among the output keys of its bin
+  uint64_t* const buf0 = bufs[0];
+  uint64_t* const buf1 = bufs[1];
+  const uint64_t G = gridDim.x;
+
+  // next segment, prefetched
+  uint64_t n_len = 0, n_off = 0;
+  int n_buf = 0, n_bit = 0;
+  Key<W> nk[PER];
+  auto fetch = [&](uint64_t t) {
+    if (t >= v.n) return;
+    n_len = v.len[t];
+    n_off = v.off[t];
+    n_buf = v.buf[t];
+    n_bit = v.bit[t];
+    if (n_len <= CAP) {
+      const uint64_t* src = (n_buf ? buf1 : buf0) + n_off * W;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    rep[q] = EMPTY;
-    const int i = q * SDBG_BLOCK + threadIdx.x;
-    if (i < n) {
-      const Key<W> kx = key_load<W>(&A[i * W]);
-      uint32_t h = leaf_hash<W>(kx) >> hshift;
-      for (;;) {
-        uint32_t cur = hs[h];
-        if (cur == EMPTY) {
-          cur = atomicCAS(&hs[h], EMPTY, ((uint32_t)i << 16) | 1u);
-          if (cur == EMPTY) {
-            rep[q] = h;
-            break;
-          }
-        }
-        if (key_eq<W>(key_load<W>(&A[(cur >> 16) * W]), kx)) {
-          atomicAdd(&hs[h], 1u);
-          break;
-        }
-        h = (h + 1) & (uint32_t)(H - 1);
+      for (int q = 0; q < PER; ++q) {
+        const int i = q * SDBG_BLOCK + threadIdx.x;
+        if (i < (int)n_len) nk[q] = key_load<W>(src + (uint64_t)i * W);
       }
     }
-  }
-  __syncthreads();
-  // 2. only keys that will be written are sorted: drop the others, count
-  uint32_t nout = 0;
+  };
+  fetch(blockIdx.x);
+  for (uint64_t s = blockIdx.x; s < v.n; s += G) {
+    const uint64_t len = n_len;
+    uint64_t* keys = (n_buf ? buf1 : buf0) + n_off * W;
+    uint32_t* cn = cnt + n_off;
+    const int bit = n_bit;
+    if (len > CAP) {
+      fetch(s + G);
+      if (threadIdx.x == 0) {
+        const uint32_t c = len > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)len;
+        const bool solid = len >= dmin;
+        if (solid || want_low) cn[0] = c;
+        nsolid[s] = solid;
+        nlow[s] = !solid && want_low;
+      }
+      continue;
+    }
+    const int n = (int)len;
+    // hash slots in use: a power of two >= 2n (load <= 1/2)
+    int hb = 6;
+    while ((1 << hb) < 2 * n) ++hb;
+    const int Hs = 1 << hb;
+    const uint32_t hshift = 32 - (uint32_t)hb;
+    // keys to LDS, then start loading the next segment
+    __syncthreads();  // the previous segment's LDS readers are done
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    if (rep[q] != EMPTY && !want_low && (hs[rep[q]] & 0xFFFFu) < dmin) rep[q] = EMPTY;
-    nout += rep[q] != EMPTY;
-  }
-  uint32_t T;
-  (void)block_excl_scan<uint32_t>(nout, sc, &T);
-  int B = 0;
-  while ((1u << B) < T && B < MAXB) ++B;
-  B = min(B, (int)v.bit[s]);
-  const int lo = (int)v.bit[s] - B;
-  const int nbins = 1 << B;
-  for (int i = threadIdx.x; i <= nbins; i += SDBG_BLOCK) bins[i] = 0;
-  __syncthreads();
+    for (int q = 0; q < PER; ++q) {
+      const int i = q * SDBG_BLOCK + threadIdx.x;
+      if (i < n) key_store<W>(&A[i * W], nk[q]);
+    }
+    for (int i = threadIdx.x; i < Hs; i += SDBG_BLOCK) hs[i] = EMPTY;
+    fetch(s + G);
+    __syncthreads();
+    // 1. merge duplicates; the element that claims a slot represents its key
+    uint32_t rep[PER];  // representative's hash slot (| digit << 16 once binned), else EMPTY
+    uint32_t rsl[PER];  // its place among the output keys of its bin
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    if (rep[q] != EMPTY) {
-      const uint32_t dg = B ? key_bits<W>(key_load<W>(&A[(hs[rep[q]] >> 16) * W]), lo, B) : 0;
-      rsl[q] = atomicAdd(&bins[dg], 1u);
-      rep[q] |= dg << 16;
+    for (int q = 0; q < PER; ++q) {
+      rep[q] = EMPTY;
+      const int i = q * SDBG_BLOCK + threadIdx.x;
+      if (i < n) {
+        const Key<W> kx = key_load<W>(&A[i * W]);
+        uint32_t h = leaf_hash<W>(kx) >> hshift;
+        for (;;) {
+          uint32_t cur = hs[h];
+          if (cur == EMPTY) {
+            cur = atomicCAS(&hs[h], EMPTY, ((uint32_t)i << 16) | 1u);
+            if (cur == EMPTY) {
+              rep[q] = h;
+              break;
+            }
+          }
+          if (key_eq<W>(key_load<W>(&A[(cur >> 16) * W]), kx)) {
+            atomicAdd(&hs[h], 1u);
+            break;
+          }
+          h = (h + 1) & (uint32_t)(Hs - 1);
+        }
+      }
     }
-  }
-  __syncthreads();
-  // 3. bin offsets (each thread scans a contiguous run of bins)
-  {
-    const int per = (nbins + SDBG_BLOCK - 1) / SDBG_BLOCK;
-    const int b0 = min(nbins, (int)threadIdx.x * per), b1 = min(nbins, b0 + per);
-    uint32_t run = 0;
-    for (int b = b0; b < b1; ++b) run += bins[b];
-    uint32_t tot;
-    uint32_t ex = block_excl_scan<uint32_t>(run, sc, &tot);
-    for (int b = b0; b < b1; ++b) {
-      uint32_t t = bins[b];
-      bins[b] = ex;
-      ex += t;
-    }
-    if (threadIdx.x == 0) bins[nbins] = tot;
-  }
-  __syncthreads();
-  // output keys (as hash slots) in bin order
+    __syncthreads();
+    // 2. only keys that will be written are sorted: drop the others, count
+    uint32_t nout = 0;
 #pragma unroll
-  for (int q = 0; q < PER; ++q)
-    if (rep[q] != EMPTY) idx[bins[rep[q] >> 16] + rsl[q]] = (uint16_t)(rep[q] & 0xFFFFu);
-  __syncthreads();
-  // 4. finish each thread's bins: sort by key, count outputs, write
-  const int b0 = (int)(((uint64_t)threadIdx.x * nbins) / SDBG_BLOCK);
-  const int b1 = (int)(((uint64_t)(threadIdx.x + 1) * nbins) / SDBG_BLOCK);
-  const int r0 = bins[b0], r1 = bins[b1];
-  for (int i = r0 + 1; i < r1; ++i) {
-    const uint16_t x = idx[i];
-    const Key<W> kx = key_load<W>(&A[(hs[x] >> 16) * W]);
-    int j = i - 1;
-    while (j >= r0 && key_less<W>(kx, key_load<W>(&A[(hs[idx[j]] >> 16) * W]))) {
-      idx[j + 1] = idx[j];
-      --j;
+    for (int q = 0; q < PER; ++q) {
+      if (rep[q] != EMPTY && !want_low && (hs[rep[q]] & 0xFFFFu) < dmin) rep[q] = EMPTY;
+      nout += rep[q] != EMPTY;
     }
-    idx[j + 1] = x;
-  }
-  uint32_t ns = 0, nl = 0;
-  for (int i = r0; i < r1; ++i) {
-    const uint32_t c = hs[idx[i]] & 0xFFFFu;
-    if (c >= dmin)
-      ++ns;
-    else if (want_low)
-      ++nl;
-  }
-  uint32_t NS, NL;
-  uint32_t bs = block_excl_scan<uint32_t>(ns, sc, &NS);
-  uint32_t bl = block_excl_scan<uint32_t>(nl, sc, &NL);
-  for (int i = r0; i < r1; ++i) {
-    const uint32_t e = hs[idx[i]];
-    const uint32_t c = e & 0xFFFFu;
-    const Key<W> kx = key_load<W>(&A[(e >> 16) * W]);
-    if (c >= dmin) {
-      key_store<W>(keys + (uint64_t)bs * W, kx);
-      cn[bs] = c;
-      ++bs;
-    } else if (want_low) {
-      key_store<W>(keys + (uint64_t)(NS + bl) * W, kx);
-      cn[NS + bl] = c;
-      ++bl;
+    uint32_t T;
+    (void)block_excl_scan<uint32_t>(nout, sc, &T);
+    int B = 0;
+    while ((1u << B) < T && B < MAXB) ++B;
+    B = min(B, bit);
+    const int lo = bit - B;
+    const int nbins = 1 << B;
+    for (int i = threadIdx.x; i <= nbins; i += SDBG_BLOCK) bins[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      if (rep[q] != EMPTY) {
+        const uint32_t dg = B ? key_bits<W>(key_load<W>(&A[(hs[rep[q]] >> 16) * W]), lo, B) : 0;
+        rsl[q] = atomicAdd(&bins[dg], 1u);
+        rep[q] |= dg << 16;
+      }
     }
-  }
-  if (threadIdx.x == 0) {
-    nsolid[s] = NS;
-    nlow[s] = NL;
-  }
+    __syncthreads();
+    // 3. bin offsets (each thread scans a contiguous run of bins)
+    {
+      const int per = (nbins + SDBG_BLOCK - 1) / SDBG_BLOCK;
+      const int b0 = min(nbins, (int)threadIdx.x * per), b1 = min(nbins, b0 + per);
+      uint32_t run = 0;
+      for (int b = b0; b < b1; ++b) run += bins[b];
+      uint32_t tot;
+      uint32_t ex = block_excl_scan<uint32_t>(run, sc, &tot);
+      for (int b = b0; b < b1; ++b) {
+        uint32_t t = bins[b];
+        bins[b] = ex;
+        ex += t;
+      }
+      if (threadIdx.x == 0) bins[nbins] = tot;
+    }
+    __syncthreads();
+    // output keys (as hash slots) in bin order
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+      if (rep[q] != EMPTY) idx[bins[rep[q] >> 16] + rsl[q]] = (uint16_t)(rep[q] & 0xFFFFu);
+    __syncthreads();
+    // 4. finish each thread's bins: sort by key, count outputs, write
+    const int b0 = (int)(((uint64_t)threadIdx.x * nbins) / SDBG_BLOCK);
+    const int b1 = (int)(((uint64_t)(threadIdx.x + 1) * nbins) / SDBG_BLOCK);
+    const int r0 = bins[b0], r1 = bins[b1];
+    for (int i = r0 + 1; i < r1; ++i) {
+      const uint16_t x = idx[i];
+      const Key<W> kx = key_load<W>(&A[(hs[x] >> 16) * W]);
+      int j = i - 1;
+      while (j >= r0 && key_less<W>(kx, key_load<W>(&A[(hs[idx[j]] >> 16) * W]))) {
+        idx[j + 1] = idx[j];
+        --j;
+      }
+      idx[j + 1] = x;
+    }
+    uint32_t ns = 0, nl = 0;
+    for (int i = r0; i < r1; ++i) {
+      const uint32_t c = hs[idx[i]] & 0xFFFFu;
+      if (c >= dmin)
+        ++ns;
+      else if (want_low)
+        ++nl;
+    }
+    // both counts in one scan (each fits 16 bits)
+    uint32_t tot2;
+    const uint32_t ex2 = block_excl_scan<uint32_t>(ns | (nl << 16), sc, &tot2);
+    const uint32_t NS = tot2 & 0xFFFFu, NL = tot2 >> 16;
+    uint32_t bs = ex2 & 0xFFFFu, bl = ex2 >> 16;
+    for (int i = r0; i < r1; ++i) {
+      const uint32_t e = hs[idx[i]];
+      const uint32_t c = e & 0xFFFFu;
+      const Key<W> kx = key_load<W>(&A[(e >> 16) * W]);
+      if (c >= dmin) {
+        key_store<W>(keys + (uint64_t)bs * W, kx);
+        cn[bs] = c;
+        ++bs;
+      } else if (want_low) {
+        key_store<W>(keys + (uint64_t)(NS + bl) * W, kx);
+        cn[NS + bl] = c;
+        ++bl;
+      }
+    }
+    if (threadIdx.x == 0) {
+      nsolid[s] = NS;
+      nlow[s] = NL;
+    }
   }
 }
 
@@ -828,6 +865,116 @@ DEV uint8_t bucket_flags(const uint64_t* __restrict__ tab, const uint8_t* __rest
     f = sv_find<W>(S, q, &ix) ? sfl[ix] : 0;
   }
   return f;
+}
+
+// One-word keys use a denser table: 32-byte buckets, so that a lookup reads
+// one 32-byte sector instead of a 64-byte line (random reads over a table of
+// several GB are bound by the bytes they move).  Slot j of a bucket holds
+// bits [j*sb, (j+1)*sb) of the 256-bit bucket: the key's low rbits bits
+// (its top bb bits are the bucket number) and 4 flag bits (valid | dead-end
+// flags); bit 255 marks a bucket with more keys than slots, whose keys are
+// then searched in the sorted set.
+struct Packed32 {
+  int bb, rbits, sb, slots;
+};
+
+inline Packed32 packed32_shape(int kb, uint64_t nS) {
+  Packed32 p{};
+  for (p.bb = std::max(1, kb - 59);; ++p.bb) {
+    p.rbits = std::max(0, kb - p.bb);
+    p.sb = p.rbits + 4;
+    p.slots = 255 / p.sb;
+    if (p.bb >= 30 || p.bb >= kb || ((uint64_t)p.slots << p.bb) >= 2 * nS) return p;
+  }
+}
+
+// One thread per bucket: its keys are a contiguous range of the sorted set
+// (S's directory is over the top bb bits).  Slots are shifted in from the
+// last to the first.
+__global__ void k_bucket32_fill(SortedView S, const uint8_t* __restrict__ sfl, uint64_t* __restrict__ tab,
+                                uint64_t nb, Packed32 p) {
+  const uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const uint64_t lo = S.dir[b], n = S.dir[b + 1] - lo;
+  const uint64_t m = n < (uint64_t)p.slots ? n : (uint64_t)p.slots;
+  const uint64_t rmask = p.rbits ? (~0ull >> (64 - p.rbits)) : 0;
+  const int sb = p.sb;
+  uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+  for (uint64_t j = m; j-- > 0;) {
+    const uint64_t slot = (S.keys[lo + j] & rmask) | ((uint64_t)(8u | sfl[lo + j]) << p.rbits);
+    w3 = (w3 << sb) | (w2 >> (64 - sb));
+    w2 = (w2 << sb) | (w1 >> (64 - sb));
+    w1 = (w1 << sb) | (w0 >> (64 - sb));
+    w0 = (w0 << sb) | slot;
+  }
+  if (n > (uint64_t)p.slots) w3 |= 1ull << 63;
+  uint64_t* out = tab + b * 4;
+  out[0] = w0;
+  out[1] = w1;
+  out[2] = w2;
+  out[3] = w3;
+}
+
+DEV uint8_t bucket32_flags(const uint64_t* __restrict__ tab, const SortedView& S, const uint8_t* __restrict__ sfl,
+                           uint64_t q, const Packed32& p) {
+  const uint64_t b = p.rbits ? q >> p.rbits : q;
+  const uint4* v = reinterpret_cast<const uint4*>(tab + b * 4);
+  const uint4 a = v[0], c = v[1];
+  uint64_t w0 = a.x | ((uint64_t)a.y << 32), w1 = a.z | ((uint64_t)a.w << 32);
+  uint64_t w2 = c.x | ((uint64_t)c.y << 32), w3 = c.z | ((uint64_t)c.w << 32);
+  const bool ovf = (w3 >> 63) != 0;
+  const uint64_t rmask = p.rbits ? (~0ull >> (64 - p.rbits)) : 0;
+  const uint64_t smask = ~0ull >> (64 - p.sb);
+  const uint64_t qr = q & rmask;
+  const int sb = p.sb;
+  uint8_t f = 0;
+  for (int j = 0; j < p.slots; ++j) {
+    const uint64_t x = w0 & smask;
+    const uint32_t fl = (uint32_t)(x >> p.rbits);
+    if ((fl & 8u) && (x & rmask) == qr) f = (uint8_t)(fl & 7u);
+    w0 = (w0 >> sb) | (w1 << (64 - sb));
+    w1 = (w1 >> sb) | (w2 << (64 - sb));
+    w2 = (w2 >> sb) | (w3 << (64 - sb));
+    w3 >>= sb;
+  }
+  if (!f && ovf) {
+    uint64_t ix;
+    Key<1> k1;
+    k1.w[0] = q;
+    f = sv_find<1>(S, k1, &ix) ? sfl[ix] : 0;
+  }
+  return f;
+}
+
+template <int IPT>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags32(ExArgs a, const uint64_t* __restrict__ tab, Packed32 p,
+                                                               SortedView S, const uint8_t* __restrict__ sfl,
+                                                               uint8_t* __restrict__ wf) {
+  const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
+  if (g0 >= a.NW) return;
+  WinIter it;
+  it.init(a, g0);
+  uint64_t key[IPT];
+  bool ok[IPT];
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) {
+    ok[q] = false;
+    key[q] = 0;
+    if (g0 + q < a.NW) {
+      const uint64_t j = it.pos();
+      if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
+        ok[q] = true;
+        key[q] = key_from_fwd<1>(stream_bits<1>(a.packed, 2 * j, a.kb), a.kb).w[0];
+      }
+      it.next(a);
+    }
+  }
+  uint8_t f[IPT];
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) f[q] = ok[q] ? bucket32_flags(tab, S, sfl, key[q], p) : (uint8_t)0x80;
+#pragma unroll
+  for (int q = 0; q < IPT; ++q)
+    if (g0 + q < a.NW) wf[g0 + q] = f[q];
 }
 
 // Per forward-strand window: 0x80 if it holds a non-ACGT base, else the
@@ -1068,6 +1215,27 @@ struct Counter {
   SortTune tune;
   explicit Counter(Ctx& c_) : c(c_), tune(sort_tune()) {}
 
+  // Largest segment a leaf sorts (the refinement cuts until segments fit).
+  uint64_t leaf_cap() const { return (uint64_t)CAP >> tune.leaf_cap_shift; }
+
+  // Persistent leaf launch: as many workgroups as can be resident (at most
+  // leaf_wg_per_cu per compute unit), so that none waits for another.
+  template <int CAPX>
+  void launch_leaf(SegList& L, uint64_t* const* d_bufs, uint32_t* cnt, uint32_t dmin, bool want_low, uint64_t* ns,
+                   uint64_t* nl) {
+    static int resident = 0;
+    if (!resident) {
+      int r = 0;
+      SDBG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, reinterpret_cast<const void*>(&k_leaf<W, CAPX>),
+                                                            SDBG_BLOCK, 0));
+      resident = std::max(1, r);
+    }
+    const int per_cu = std::max(1, std::min(resident, tune.leaf_wg_per_cu));
+    const unsigned lgrid = (unsigned)std::min<uint64_t>(L.n, (uint64_t)cu_count() * per_cu);
+    k_leaf<W, CAPX><<<lgrid, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, cnt, dmin, want_low ? 1 : 0, ns, nl);
+    c.check_launch("leaf");
+  }
+
   // Histogram and scatter of one refinement level with tiles of TKX keys.
   template <int TKX>
   void seg_pass(SegList& L, uint64_t* const* d_bufs, uint64_t NT, uint64_t NTab, uint64_t moved, DBuf<uint32_t>& tile_seg,
@@ -1095,7 +1263,7 @@ struct Counter {
     for (int level = 0; level < 64; ++level) {
       if (L.n == 0) return;
       fill<uint64_t>(reinterpret_cast<uint64_t*>(st.get()), 2, 0, c);
-      k_seg_stats<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), CAP, st.get());
+      k_seg_stats<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), leaf_cap(), st.get());
       c.check_launch("seg_stats");
       unsigned long long hs[2];
       c.d2h(hs, st.get(), 2);
@@ -1104,12 +1272,12 @@ struct Counter {
       VLOG("refine level %d: %llu segments, %llu oversized holding %llu keys", level, (unsigned long long)L.n,
            hs[0], hs[1]);
       int D = 1;
-      while (D < tune.digit_bits && (avg >> D) > (uint64_t)CAP / 2) ++D;
+      while (D < tune.digit_bits && (avg >> D) > leaf_cap() / 2) ++D;
       const int tk = TK >> tune.tile_shift;
       DBuf<uint64_t> ntiles = c.buf<uint64_t>(L.n), tabsz = c.buf<uint64_t>(L.n);
       DBuf<uint64_t> tile_first = c.buf<uint64_t>(L.n), tab_base = c.buf<uint64_t>(L.n);
       DBuf<uint64_t> tot = c.buf<uint64_t>(2);
-      k_seg_mark<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), CAP, D, tk, ntiles.get(), tabsz.get());
+      k_seg_mark<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), leaf_cap(), D, tk, ntiles.get(), tabsz.get());
       c.check_launch("seg_mark");
       scan_excl<uint64_t, uint64_t>(ntiles.get(), tile_first.get(), L.n, tot.get(), c);
       scan_excl<uint64_t, uint64_t>(tabsz.get(), tab_base.get(), L.n, tot.get() + 1, c);
@@ -1149,13 +1317,10 @@ struct Counter {
     DBuf<uint64_t> spos = c.buf<uint64_t>(L.n + 1), lpos = c.buf<uint64_t>(L.n), tot = c.buf<uint64_t>(2);
     if (L.n) {
       Stage st_(c, "leaf", nkeys * 8 * W);
-      DBuf<uint64_t> work = c.buf<uint64_t>(1);
-      fill<uint64_t>(work.get(), 1, 0, c);
-      const unsigned lgrid = (unsigned)std::min<uint64_t>(L.n, (uint64_t)cu_count() * tune.leaf_wg_per_cu);
-      k_leaf<W, CAP><<<lgrid, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, cnt, dmin, want_low ? 1 : 0,
-                                                              nsolid.get(), nlow.get(),
-                                                       reinterpret_cast<unsigned long long*>(work.get()));
-      c.check_launch("leaf");
+      if (tune.leaf_cap_shift == 0)
+        launch_leaf<CAP>(L, d_bufs, cnt, dmin, want_low, nsolid.get(), nlow.get());
+      else
+        launch_leaf<CAP / 2>(L, d_bufs, cnt, dmin, want_low, nsolid.get(), nlow.get());
     }
     scan_excl<uint64_t, uint64_t>(nsolid.get(), spos.get(), L.n, spos.get() + L.n, c);
     scan_excl<uint64_t, uint64_t>(nlow.get(), lpos.get(), L.n, tot.get() + 1, c);
@@ -1443,30 +1608,50 @@ struct Counter {
         k_dead_ends<W><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(sv, k, sfl.get());
         c.check_launch("dead_ends");
       }
-      // bucket table: about SL/2 solid keys per bucket
-      constexpr int SL = Bucket<W>::SL;
-      int bb = 4;
-      while (bb < 30 && bb < kb && ((uint64_t)SL << bb) < 2 * nS) ++bb;
-      const uint64_t nb = 1ull << bb;
-      DBuf<uint64_t> bdir;
-      SortedView bv = make_view_db(S.get(), nS, kb, bb, bdir);
-      DBuf<uint64_t> btab = c.buf<uint64_t>(nb * SL * W);
-      DBuf<uint8_t> ovf = c.buf<uint8_t>(nb);
-      {
-        Stage st_(c, "bucket_fill", nS * (8 * W + 1) + nb * (SL * 8 * W + 1 + 8));
-        k_bucket_fill<W><<<grid1(nb * SL), SDBG_BLOCK, 0, c.s>>>(bv, sfl.get(), btab.get(), ovf.get(), nb);
-        c.check_launch("bucket_fill");
-      }
       DBuf<uint8_t> wf = c.buf<uint8_t>(NW);
-      {
-        Stage st_(c, "window_flags", 3 * words * 8 + NW);
-        constexpr int WIPT = W == 1 ? 8 : W == 2 ? 4 : W == 4 ? 2 : 1;
-        k_window_flags<W, WIPT><<<grid1(ceil_div(NW, WIPT)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), ovf.get(), bv,
-                                                                                   sfl.get(), wf.get());
-        c.check_launch("window_flags");
+      if constexpr (W == 1) {
+        // packed 32-byte buckets, about slots/2 solid keys per bucket
+        const Packed32 pk = packed32_shape(kb, nS);
+        const uint64_t nb = 1ull << pk.bb;
+        DBuf<uint64_t> bdir;
+        SortedView bv = make_view_db(S.get(), nS, kb, pk.bb, bdir);
+        DBuf<uint64_t> btab = c.buf<uint64_t>(nb * 4);
+        {
+          Stage st_(c, "bucket_fill", nS * 9 + nb * (32 + 8));
+          k_bucket32_fill<<<grid1(nb), SDBG_BLOCK, 0, c.s>>>(bv, sfl.get(), btab.get(), nb, pk);
+          c.check_launch("bucket_fill");
+        }
+        {
+          // each probe reads its 32-byte bucket
+          Stage st_(c, "window_flags", 3 * words * 8 + NW + NW * 32);
+          k_window_flags32<8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), pk, bv, sfl.get(),
+                                                                               wf.get());
+          c.check_launch("window_flags");
+        }
+      } else {
+        // bucket table: about SL/2 solid keys per bucket
+        constexpr int SL = Bucket<W>::SL;
+        int bb = 4;
+        while (bb < 30 && bb < kb && ((uint64_t)SL << bb) < 2 * nS) ++bb;
+        const uint64_t nb = 1ull << bb;
+        DBuf<uint64_t> bdir;
+        SortedView bv = make_view_db(S.get(), nS, kb, bb, bdir);
+        DBuf<uint64_t> btab = c.buf<uint64_t>(nb * SL * W);
+        DBuf<uint8_t> ovf = c.buf<uint8_t>(nb);
+        {
+          Stage st_(c, "bucket_fill", nS * (8 * W + 1) + nb * (SL * 8 * W + 1 + 8));
+          k_bucket_fill<W><<<grid1(nb * SL), SDBG_BLOCK, 0, c.s>>>(bv, sfl.get(), btab.get(), ovf.get(), nb);
+          c.check_launch("bucket_fill");
+        }
+        {
+          // each probe reads its bucket of SL keys
+          Stage st_(c, "window_flags", 3 * words * 8 + NW + NW * SL * 8 * W);
+          constexpr int WIPT = W == 2 ? 4 : W == 4 ? 2 : 1;
+          k_window_flags<W, WIPT><<<grid1(ceil_div(NW, WIPT)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), ovf.get(), bv,
+                                                                                     sfl.get(), wf.get());
+          c.check_launch("window_flags");
+        }
       }
-      btab.free();
-      ovf.free();
       DBuf<uint64_t> mcount = c.buf<uint64_t>(R.n_reads), mpos = c.buf<uint64_t>(R.n_reads);
       {
         Stage st_(c, "mercy_count", NW + R.n_reads * 24);
@@ -1644,6 +1829,7 @@ void set_sort_tune(const SortTune& t) {
   SDBG_CHECK(t.digit_bits >= 4 && t.digit_bits <= 8, -1, "digit_bits must be in [4, 8]");
   SDBG_CHECK(t.tile_shift == 0 || t.tile_shift == 1, -1, "tile_shift must be 0 or 1");
   SDBG_CHECK(t.leaf_wg_per_cu >= 1 && t.leaf_wg_per_cu <= 32, -1, "leaf_wg_per_cu must be in [1, 32]");
+  SDBG_CHECK(t.leaf_cap_shift == 0 || t.leaf_cap_shift == 1, -1, "leaf_cap_shift must be 0 or 1");
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune = t;
 }

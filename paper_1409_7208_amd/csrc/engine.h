@@ -77,9 +77,10 @@ class Stage {
 // Launch parameters of the partition/sort engine.  Results never depend on
 // them; they only move work between passes and workgroups.
 struct SortTune {
-  int digit_bits = 8;       // most key bits one refinement pass cuts (4..8)
+  int digit_bits = 7;       // most key bits one refinement pass cuts (4..8)
   int tile_shift = 0;       // refinement tile = the width's default tile >> tile_shift (0 or 1)
   int leaf_wg_per_cu = 16;  // persistent leaf workgroups per compute unit (1..32)
+  int leaf_cap_shift = 0;   // largest leaf = the width's default >> leaf_cap_shift (0 or 1)
 };
 SortTune sort_tune();
 void set_sort_tune(const SortTune& t);

@@ -296,7 +296,7 @@ class _Tune(ctypes.Structure):
         ("digit_bits", ctypes.c_uint32),
         ("tile_shift", ctypes.c_uint32),
         ("leaf_wg_per_cu", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("leaf_cap_shift", ctypes.c_uint32),
     ]
 
 
@@ -318,7 +318,8 @@ def tune_get() -> dict:
     _tune_api(lib)
     t = _Tune()
     _check(lib.sdbg_tune_get(ctypes.byref(t)))
-    return {"digit_bits": t.digit_bits, "tile_shift": t.tile_shift, "leaf_wg_per_cu": t.leaf_wg_per_cu}
+    return {"digit_bits": t.digit_bits, "tile_shift": t.tile_shift, "leaf_wg_per_cu": t.leaf_wg_per_cu,
+            "leaf_cap_shift": t.leaf_cap_shift}
 
 
 def tune_set(t: dict | None = None):
@@ -328,7 +329,10 @@ def tune_set(t: dict | None = None):
     if t is None:
         _check(lib.sdbg_tune_set(None))
     else:
-        _check(lib.sdbg_tune_set(ctypes.byref(_Tune(t["digit_bits"], t["tile_shift"], t["leaf_wg_per_cu"], 0))))
+        full = tune_get()
+        full.update(t)
+        _check(lib.sdbg_tune_set(ctypes.byref(_Tune(full["digit_bits"], full["tile_shift"], full["leaf_wg_per_cu"],
+                                                     full["leaf_cap_shift"]))))
 
 
 def autotune(sets, k: int, d: int = 2, mercy: bool = False, reps: int = 3) -> dict:
@@ -347,7 +351,8 @@ def autotune(sets, k: int, d: int = 2, mercy: bool = False, reps: int = 3) -> di
     t = _Tune()
     _check(lib.sdbg_autotune(arr, n, ctypes.byref(p), reps, ctypes.byref(t)))
     del keep
-    return {"digit_bits": t.digit_bits, "tile_shift": t.tile_shift, "leaf_wg_per_cu": t.leaf_wg_per_cu}
+    return {"digit_bits": t.digit_bits, "tile_shift": t.tile_shift, "leaf_wg_per_cu": t.leaf_wg_per_cu,
+            "leaf_cap_shift": t.leaf_cap_shift}
 
 
 def edges_from_host(keys: np.ndarray, counts: np.ndarray, k: int) -> Edges:

@@ -134,9 +134,9 @@ def test_batch_edges_only_and_empty():
 
 
 TUNES = [
-    {"digit_bits": 4, "tile_shift": 1, "leaf_wg_per_cu": 1},
-    {"digit_bits": 6, "tile_shift": 0, "leaf_wg_per_cu": 4},
-    {"digit_bits": 7, "tile_shift": 1, "leaf_wg_per_cu": 32},
+    {"digit_bits": 4, "tile_shift": 1, "leaf_wg_per_cu": 1, "leaf_cap_shift": 1},
+    {"digit_bits": 6, "tile_shift": 0, "leaf_wg_per_cu": 4, "leaf_cap_shift": 0},
+    {"digit_bits": 7, "tile_shift": 1, "leaf_wg_per_cu": 32, "leaf_cap_shift": 1},
 ]
 
 
@@ -183,7 +183,7 @@ def test_autotune_keeps_results():
         say(f"autotune picked {best}")
         assert best == sdbg.tune_get()
         assert best["digit_bits"] in (6, 7, 8) and best["tile_shift"] in (0, 1)
-        assert best["leaf_wg_per_cu"] in (4, 8, 16, 32)
+        assert best["leaf_wg_per_cu"] in (4, 8, 16, 32) and best["leaf_cap_shift"] in (0, 1)
         res = sdbg.batch_run(dev, 31, 2, False, build=False)
         for (e, _), (r, _) in zip(res, ref):
             a, b = e.to_host(), r.to_host()
