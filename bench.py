@@ -236,6 +236,8 @@ def main():
     ap.add_argument("--pool", type=int, default=32, help="serve: distinct jobs in the pool")
     ap.add_argument("--autotune", action="store_true", help="batch: pick launch parameters on a sample first")
     ap.add_argument("--tune", default="", help="launch parameters, e.g. leaf_cap_shift=1,leaf_wg_per_cu=8")
+    ap.add_argument("--host-input", action="store_true",
+                    help="plain: also time a step that takes the reads from host memory (PCIe included), stderr only")
     ap.add_argument("--sweep", default="",
                     help="plain: also time these launch-parameter settings (';'-separated --tune strings), stderr only")
     args = ap.parse_args()
@@ -315,6 +317,23 @@ def main():
         log(f"sweep {spec}: {sms:.2f} ms/step, {n_occ / (sms / 1e3) / 1e9:.2f} Gmer/s")
         sdbg.tune_set(base)
 
+    host_rate = None
+    if args.host_input:
+        seq_h, off_h = rs.seq, rs.offsets
+        e = sdbg.count_solid(seq_h, off_h, rs.k, rs.d, rs.mercy, stream=stream)
+        sdbg.build(e, stream=stream).close()
+        e.close()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for _ in range(args.steps):
+            e = sdbg.count_solid(seq_h, off_h, rs.k, rs.d, rs.mercy, stream=stream)
+            sdbg.build(e, stream=stream).close()
+            e.close()
+        torch.cuda.synchronize()
+        hms = (time.perf_counter() - w0) / args.steps * 1e3
+        host_rate = n_occ / (hms / 1e3) / 1e9
+        log(f"host input (PCIe copy of reads included): {hms:.2f} ms/step, {host_rate:.2f} Gmer/s")
+
     recs = sdbg.profile_records()
     if args.stages:
         per_step = len(recs) // args.steps
@@ -340,6 +359,19 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dn,
                 "avg_launch_ms": round(dms / dcnt, 4), "bytes_per_launch": int(dbytes / dcnt)}
 
+    # Whole step against the HBM roofline: every profiled launch's algorithmic
+    # bytes over the step time, and the floor of a one-partition-pass
+    # schedule (32 w bytes per occurrence for extraction write, one
+    # partition pass and the leaf read, plus 8w+4 per output edge).
+    w = (2 * (rs.k + 1) + 63) // 64
+    step_bytes = sum(a[2] for a in agg.values()) / args.steps
+    floor_b = 32 * w + (int(r[1]) / n_occ) * (8 * w + 4)
+    step_roofline = {"bytes_per_occ": round(step_bytes / n_occ, 2),
+                     "achieved_gbs": round(step_bytes / (ms * 1e-3) / 1e9, 1),
+                     "frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "floor_bytes_per_occ": round(floor_b, 2),
+                     "floor_frac": round(value * floor_b / HBM_PEAK_GBS, 4)}
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
@@ -364,8 +396,11 @@ def main():
                    "tips": int(r[4])},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "step_roofline": step_roofline,
         "tune": sdbg.tune_get(),
     }
+    if host_rate is not None:
+        out["host_input_gmer_s"] = round(host_rate, 3)
     print(json.dumps(out), flush=True)
 
 
