@@ -159,12 +159,17 @@ int sdbg_batch_run(const sdbg_reads *sets, uint64_t n_sets, const sdbg_params *p
  *                   sort and count, 1..32 (16; fewer if fewer fit)
  *   leaf_cap_shift  largest segment sorted in LDS = the key width's default
  *                   (2048, 1024, 1024, 1024 keys for w = 1..4) >> leaf_cap_shift,
- *                   0 or 1 (0) */
+ *                   0 or 1 (0)
+ *   first_bits      key bits of the first cut, which is taken straight from
+ *                   the packed reads, 4..8 (6)
+ * (The autotuner varies the first four.) */
 typedef struct sdbg_tune {
   uint32_t digit_bits;
   uint32_t tile_shift;
   uint32_t leaf_wg_per_cu;
   uint32_t leaf_cap_shift;
+  uint32_t first_bits;
+  uint32_t reserved[3];
 } sdbg_tune;
 
 int sdbg_tune_get(sdbg_tune *t);

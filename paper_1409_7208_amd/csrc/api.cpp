@@ -421,6 +421,8 @@ int sdbg_tune_get(sdbg_tune* t) {
     t->tile_shift = (uint32_t)x.tile_shift;
     t->leaf_wg_per_cu = (uint32_t)x.leaf_wg_per_cu;
     t->leaf_cap_shift = (uint32_t)x.leaf_cap_shift;
+    t->first_bits = (uint32_t)x.first_bits;
+    t->reserved[0] = t->reserved[1] = t->reserved[2] = 0;
     return SDBG_OK;
   });
 }
@@ -433,6 +435,7 @@ int sdbg_tune_set(const sdbg_tune* t) {
       x.tile_shift = (int)t->tile_shift;
       x.leaf_wg_per_cu = (int)t->leaf_wg_per_cu;
       x.leaf_cap_shift = (int)t->leaf_cap_shift;
+      x.first_bits = (int)t->first_bits;
     }
     sdbg::set_sort_tune(x);
     return SDBG_OK;
@@ -492,6 +495,8 @@ int sdbg_autotune(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* pa
       best->tile_shift = (uint32_t)cur.tile_shift;
       best->leaf_wg_per_cu = (uint32_t)cur.leaf_wg_per_cu;
       best->leaf_cap_shift = (uint32_t)cur.leaf_cap_shift;
+      best->first_bits = (uint32_t)cur.first_bits;
+      best->reserved[0] = best->reserved[1] = best->reserved[2] = 0;
     }
     return SDBG_OK;
   });

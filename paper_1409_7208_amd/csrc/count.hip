@@ -407,7 +407,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_seg_hist(SegView v, uint64_t* co
   h[threadIdx.x] = 0;
   __syncthreads();
   for (uint32_t p = threadIdx.x; p < n; p += SDBG_BLOCK)
-    atomicAdd(&h[key_bits<W>(key_load<W>(src + (uint64_t)p * W), lo, D)], 1u);
+    atomicAdd(&h[key_bits<W>(key_load_g<W>(src + (uint64_t)p * W), lo, D)], 1u);
   __syncthreads();
   if (threadIdx.x < (1u << D)) tab[tab_base[s] + (uint64_t)threadIdx.x * nt + i] = h[threadIdx.x];
 }
@@ -444,7 +444,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_seg_scatter(SegView v, uint64_t*
     uint32_t p = q * SDBG_BLOCK + threadIdx.x;
     pos[q] = 0xFFFFFFFFu;
     if (p < n) {
-      keys[q] = key_load<W>(src + (uint64_t)p * W);
+      keys[q] = key_load_g<W>(src + (uint64_t)p * W);
       uint32_t d = key_bits<W>(keys[q], lo, D);
       pos[q] = (d << 16) | atomicAdd(&cnt[d], 1u);
     }
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_seg_scatter(SegView v, uint64_t*
   for (uint32_t p = threadIdx.x; p < total; p += SDBG_BLOCK) {
     Key<W> key = key_load<W>(&lk[p * W]);
     uint32_t d = key_bits<W>(key, lo, D);
-    key_store<W>(dst + ((uint64_t)gb[d] + (p - lst[d])) * W, key);
+    key_store_g<W>(dst + ((uint64_t)gb[d] + (p - lst[d])) * W, key);
   }
 }
 
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int i = q * SDBG_BLOCK + threadIdx.x;
-        if (i < (int)n_len) nk[q] = key_load<W>(src + (uint64_t)i * W);
+        if (i < (int)n_len) nk[q] = key_load_g<W>(src + (uint64_t)i * W);
       }
     }
   };
@@ -611,7 +611,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
     const int Hs = 1 << hb;
     const uint32_t hshift = 32 - (uint32_t)hb;
     // keys to LDS, then start loading the next segment
-    __syncthreads();  // the previous segment's LDS readers are done
+    lds_barrier();  // the previous segment's LDS readers are done
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int i = q * SDBG_BLOCK + threadIdx.x;
@@ -619,7 +619,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
     }
     for (int i = threadIdx.x; i < Hs; i += SDBG_BLOCK) hs[i] = EMPTY;
     fetch(s + G);
-    __syncthreads();
+    lds_barrier();
     // 1. merge duplicates; the element that claims a slot represents its key
     uint32_t rep[PER];  // representative's hash slot (| digit << 16 once binned), else EMPTY
     uint32_t rsl[PER];  // its place among the output keys of its bin
@@ -647,7 +647,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     // 2. only keys that will be written are sorted: drop the others, count
     uint32_t nout = 0;
 #pragma unroll
@@ -663,7 +663,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
     const int lo = bit - B;
     const int nbins = 1 << B;
     for (int i = threadIdx.x; i <= nbins; i += SDBG_BLOCK) bins[i] = 0;
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       if (rep[q] != EMPTY) {
@@ -672,7 +672,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
         rep[q] |= dg << 16;
       }
     }
-    __syncthreads();
+    lds_barrier();
     // 3. bin offsets (each thread scans a contiguous run of bins)
     {
       const int per = (nbins + SDBG_BLOCK - 1) / SDBG_BLOCK;
@@ -688,12 +688,12 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
       }
       if (threadIdx.x == 0) bins[nbins] = tot;
     }
-    __syncthreads();
+    lds_barrier();
     // output keys (as hash slots) in bin order
 #pragma unroll
     for (int q = 0; q < PER; ++q)
       if (rep[q] != EMPTY) idx[bins[rep[q] >> 16] + rsl[q]] = (uint16_t)(rep[q] & 0xFFFFu);
-    __syncthreads();
+    lds_barrier();
     // 4. finish each thread's bins: sort by key, count outputs, write
     const int b0 = (int)(((uint64_t)threadIdx.x * nbins) / SDBG_BLOCK);
     const int b1 = (int)(((uint64_t)(threadIdx.x + 1) * nbins) / SDBG_BLOCK);
@@ -726,11 +726,11 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const*
       const uint32_t c = e & 0xFFFFu;
       const Key<W> kx = key_load<W>(&A[(e >> 16) * W]);
       if (c >= dmin) {
-        key_store<W>(keys + (uint64_t)bs * W, kx);
+        key_store_g<W>(keys + (uint64_t)bs * W, kx);
         cn[bs] = c;
         ++bs;
       } else if (want_low) {
-        key_store<W>(keys + (uint64_t)(NS + bl) * W, kx);
+        key_store_g<W>(keys + (uint64_t)(NS + bl) * W, kx);
         cn[NS + bl] = c;
         ++bl;
       }
@@ -758,13 +758,13 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_compact(SegView v, uint64_t* con
   const uint64_t a = nsolid[s], b = nlow ? nlow[s] : 0;
   const uint64_t ps = spos[s];
   for (uint64_t i = threadIdx.x; i < a; i += SDBG_BLOCK) {
-    key_store<W>(skeys + (ps + i) * W, key_load<W>(src + i * W));
+    key_store<W>(skeys + (ps + i) * W, key_load_g<W>(src + i * W));
     scnt[ps + i] = cnt[off + i];
   }
   if (b) {
     const uint64_t pl = lpos[s];
     for (uint64_t i = threadIdx.x; i < b; i += SDBG_BLOCK) {
-      key_store<W>(lkeys + (pl + i) * W, key_load<W>(src + (a + i) * W));
+      key_store<W>(lkeys + (pl + i) * W, key_load_g<W>(src + (a + i) * W));
       lcnt[pl + i] = cnt[off + a + i];
     }
   }
@@ -1068,16 +1068,77 @@ __global__ void k_lookup_counts(const uint64_t* __restrict__ keys, uint64_t n, S
   out[i] = sv_find<W>(L, key_load<W>(keys + i * W), &ix) ? lcnt[ix] : 0;
 }
 
-// Merge of two disjoint sorted sets: element i of A goes to i + #(B < a_i).
+// Merge of two disjoint sorted key sets (with their counts) along the merge
+// path: output tile t covers positions [t*T, (t+1)*T); the split of each
+// tile boundary between A and B is found by one binary search on the
+// cross diagonal, then a workgroup stages its A and B runs in LDS, ranks each
+// element in the other run there and writes it to its place in the tile.
 template <int W>
-__global__ void k_merge_place(const uint64_t* __restrict__ akeys, const uint32_t* __restrict__ acnt, uint64_t na,
-                              SortedView B, uint64_t* __restrict__ okeys, uint32_t* __restrict__ ocnt) {
-  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (i >= na) return;
-  Key<W> x = key_load<W>(akeys + i * W);
-  uint64_t p = i + sv_lower<W>(B, x);
-  key_store<W>(okeys + p * W, x);
-  ocnt[p] = acnt[i];
+struct MergeTile {
+  static constexpr int T = W == 1 ? 2048 : W == 2 ? 1024 : 512;
+};
+
+template <int W>
+__global__ void k_merge_split(const uint64_t* __restrict__ A, uint64_t na, const uint64_t* __restrict__ B, uint64_t nb,
+                              uint64_t ntiles, uint64_t* __restrict__ split) {
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (t > ntiles) return;
+  const uint64_t d = min(t * (uint64_t)MergeTile<W>::T, na + nb);
+  // smallest i in [max(0, d - nb), min(d, na)] with A[i] > B[d - i - 1]
+  uint64_t lo = d > nb ? d - nb : 0, hi = min(d, na);
+  while (lo < hi) {
+    const uint64_t i = (lo + hi) >> 1;
+    if (key_less<W>(key_load<W>(A + i * W), key_load<W>(B + (d - i - 1) * W)))
+      lo = i + 1;
+    else
+      hi = i;
+  }
+  split[t] = lo;
+}
+
+template <int W>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_merge_tile(const uint64_t* __restrict__ A, const uint32_t* __restrict__ Ac,
+                                                           uint64_t na, const uint64_t* __restrict__ B,
+                                                           const uint32_t* __restrict__ Bc, uint64_t nb,
+                                                           const uint64_t* __restrict__ split, uint64_t* __restrict__ E,
+                                                           uint32_t* __restrict__ Ec) {
+  constexpr int T = MergeTile<W>::T;
+  __shared__ uint64_t la[T * W], lb[T * W];
+  const uint64_t t = blockIdx.x;
+  const uint64_t d0 = t * (uint64_t)T, d1 = min(d0 + T, na + nb);
+  const uint64_t a0 = split[t], a1 = split[t + 1];
+  const uint64_t b0 = d0 - a0, b1 = d1 - a1;
+  const int nA = (int)(a1 - a0), nB = (int)(b1 - b0);
+  for (int i = threadIdx.x; i < nA; i += SDBG_BLOCK) key_store<W>(&la[i * W], key_load<W>(A + (a0 + i) * W));
+  for (int i = threadIdx.x; i < nB; i += SDBG_BLOCK) key_store<W>(&lb[i * W], key_load<W>(B + (b0 + i) * W));
+  lds_barrier();
+  // rank of each element in the other run (the sets are disjoint)
+  for (int i = threadIdx.x; i < nA; i += SDBG_BLOCK) {
+    const Key<W> x = key_load<W>(&la[i * W]);
+    int lo = 0, hi = nB;
+    while (lo < hi) {
+      const int m = (lo + hi) >> 1;
+      if (key_less<W>(key_load<W>(&lb[m * W]), x))
+        lo = m + 1;
+      else
+        hi = m;
+    }
+    key_store<W>(E + (d0 + i + lo) * W, x);
+    Ec[d0 + i + lo] = Ac[a0 + i];
+  }
+  for (int i = threadIdx.x; i < nB; i += SDBG_BLOCK) {
+    const Key<W> x = key_load<W>(&lb[i * W]);
+    int lo = 0, hi = nA;
+    while (lo < hi) {
+      const int m = (lo + hi) >> 1;
+      if (key_less<W>(key_load<W>(&la[m * W]), x))
+        lo = m + 1;
+      else
+        hi = m;
+    }
+    key_store<W>(E + (d0 + i + lo) * W, x);
+    Ec[d0 + i + lo] = Bc[b0 + i];
+  }
 }
 
 }  // namespace sdbg
@@ -1445,7 +1506,7 @@ struct Counter {
     ea.pb = std::min(16, kb);
     ea.glo = 0;
     ea.ghi = 1u << ea.pb;
-    ea.dbits = std::min(8, kb);
+    ea.dbits = std::min(tune.first_bits, kb);
     ea.dlo = kb - ea.dbits;
     const uint64_t ntr = ceil_div(NW, TR_GRAIN) + 1;
     DBuf<uint64_t>& trd = pr.trd;
@@ -1707,16 +1768,19 @@ struct Counter {
       out->keys = S.release_ownership();
       out->count = Sc.release_ownership();
     } else {
-      Stage st_(c, "merge", 2 * (nS + nM) * (8 * W + 4));
       DBuf<uint64_t> E = c.buf<uint64_t>((nS + nM) * W);
       DBuf<uint32_t> Ec = c.buf<uint32_t>(nS + nM);
-      DBuf<uint64_t> sdir, mdir;
-      SortedView sv = make_view(S.get(), nS, kb, sdir);
-      SortedView mv = make_view(M.get(), nM, kb, mdir);
-      k_merge_place<W><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(S.get(), Sc.get(), nS, mv, E.get(), Ec.get());
-      c.check_launch("merge_s");
-      k_merge_place<W><<<grid1(nM), SDBG_BLOCK, 0, c.s>>>(M.get(), Mc.get(), nM, sv, E.get(), Ec.get());
-      c.check_launch("merge_m");
+      const uint64_t mt = ceil_div(nS + nM, MergeTile<W>::T);
+      DBuf<uint64_t> split = c.buf<uint64_t>(mt + 1);
+      k_merge_split<W><<<grid1(mt + 1), SDBG_BLOCK, 0, c.s>>>(S.get(), nS, M.get(), nM, mt, split.get());
+      c.check_launch("merge_split");
+      {
+        Stage st_(c, "merge", 2 * (nS + nM) * (8 * W + 4));
+        SDBG_CHECK(mt < (1ull << 31), -3, "merge too large");
+        k_merge_tile<W><<<(unsigned)mt, SDBG_BLOCK, 0, c.s>>>(S.get(), Sc.get(), nS, M.get(), Mc.get(), nM, split.get(),
+                                                               E.get(), Ec.get());
+        c.check_launch("merge");
+      }
       c.sync();
       out->keys = E.release_ownership();
       out->count = Ec.release_ownership();
@@ -1830,6 +1894,7 @@ void set_sort_tune(const SortTune& t) {
   SDBG_CHECK(t.tile_shift == 0 || t.tile_shift == 1, -1, "tile_shift must be 0 or 1");
   SDBG_CHECK(t.leaf_wg_per_cu >= 1 && t.leaf_wg_per_cu <= 32, -1, "leaf_wg_per_cu must be in [1, 32]");
   SDBG_CHECK(t.leaf_cap_shift == 0 || t.leaf_cap_shift == 1, -1, "leaf_cap_shift must be 0 or 1");
+  SDBG_CHECK(t.first_bits >= 4 && t.first_bits <= 8, -1, "first_bits must be in [4, 8]");
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune = t;
 }

@@ -33,6 +33,28 @@ DEV void key_store(uint64_t* p, const Key<W>& k) {
   for (int i = 0; i < W; ++i) p[i] = k.w[i];
 }
 
+// Key access through a pointer the compiler cannot place in global memory
+// (one read from a table of buffers): as generic pointers these become flat
+// accesses, which also count against the LDS wait counter, so a wait for LDS
+// (a barrier) would wait for them too.  These access global memory.
+typedef __attribute__((address_space(1))) uint64_t global_u64;
+
+template <int W>
+__device__ __forceinline__ Key<W> key_load_g(const uint64_t* p) {
+  const global_u64* q = (const global_u64*)p;
+  Key<W> k;
+#pragma unroll
+  for (int i = 0; i < W; ++i) k.w[i] = q[i];
+  return k;
+}
+
+template <int W>
+__device__ __forceinline__ void key_store_g(uint64_t* p, const Key<W>& k) {
+  global_u64* q = (global_u64*)p;
+#pragma unroll
+  for (int i = 0; i < W; ++i) q[i] = k.w[i];
+}
+
 template <int W>
 DEV bool key_less(const Key<W>& a, const Key<W>& b) {
 #pragma unroll
@@ -196,29 +218,32 @@ DEV T wave_sum(T v) {
   return v;
 }
 
+// Workgroup barrier for communication through LDS only: waits for this
+// wave's LDS operations but not for its global loads and stores (the fence
+// of __syncthreads would), so global traffic in flight keeps overlapping
+// with the work after the barrier.  The memory clobber keeps the compiler
+// from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Exclusive scan over the SDBG_BLOCK threads of a workgroup; *total gets the
-// sum.  `scratch` holds SDBG_WAVES + 1 elements of LDS.
+// sum.  `scratch` holds SDBG_WAVES elements of LDS; the scan ends with a
+// barrier, so the caller may reuse scratch at once.
 template <typename T>
-DEV T block_excl_scan(T v, T* scratch, T* total) {
+__device__ __forceinline__ T block_excl_scan(T v, T* scratch, T* total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   T inc = wave_incl_scan(v);
   if (lane == 63) scratch[wid] = inc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    T run = 0;
+  lds_barrier();
+  T base = 0, all = 0;
 #pragma unroll
-    for (int i = 0; i < SDBG_WAVES; ++i) {
-      T t = scratch[i];
-      scratch[i] = run;
-      run += t;
-    }
-    scratch[SDBG_WAVES] = run;
+  for (int i = 0; i < SDBG_WAVES; ++i) {
+    const T t = scratch[i];
+    base += i < wid ? t : T(0);
+    all += t;
   }
-  __syncthreads();
-  T res = scratch[wid] + inc - v;
-  *total = scratch[SDBG_WAVES];
-  __syncthreads();
-  return res;
+  *total = all;
+  lds_barrier();  // scratch may be reused at once
+  return base + inc - v;
 }
 
 // 2-bit code of an ASCII base; *ok = false for anything but A/C/G/T (any case).

@@ -297,6 +297,8 @@ class _Tune(ctypes.Structure):
         ("tile_shift", ctypes.c_uint32),
         ("leaf_wg_per_cu", ctypes.c_uint32),
         ("leaf_cap_shift", ctypes.c_uint32),
+        ("first_bits", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 3),
     ]
 
 
@@ -318,8 +320,12 @@ def tune_get() -> dict:
     _tune_api(lib)
     t = _Tune()
     _check(lib.sdbg_tune_get(ctypes.byref(t)))
+    return _tune_dict(t)
+
+
+def _tune_dict(t) -> dict:
     return {"digit_bits": t.digit_bits, "tile_shift": t.tile_shift, "leaf_wg_per_cu": t.leaf_wg_per_cu,
-            "leaf_cap_shift": t.leaf_cap_shift}
+            "leaf_cap_shift": t.leaf_cap_shift, "first_bits": t.first_bits}
 
 
 def tune_set(t: dict | None = None):
@@ -331,8 +337,10 @@ def tune_set(t: dict | None = None):
     else:
         full = tune_get()
         full.update(t)
-        _check(lib.sdbg_tune_set(ctypes.byref(_Tune(full["digit_bits"], full["tile_shift"], full["leaf_wg_per_cu"],
-                                                     full["leaf_cap_shift"]))))
+        x = _Tune()
+        for key, val in full.items():
+            setattr(x, key, int(val))
+        _check(lib.sdbg_tune_set(ctypes.byref(x)))
 
 
 def autotune(sets, k: int, d: int = 2, mercy: bool = False, reps: int = 3) -> dict:
@@ -351,8 +359,7 @@ def autotune(sets, k: int, d: int = 2, mercy: bool = False, reps: int = 3) -> di
     t = _Tune()
     _check(lib.sdbg_autotune(arr, n, ctypes.byref(p), reps, ctypes.byref(t)))
     del keep
-    return {"digit_bits": t.digit_bits, "tile_shift": t.tile_shift, "leaf_wg_per_cu": t.leaf_wg_per_cu,
-            "leaf_cap_shift": t.leaf_cap_shift}
+    return _tune_dict(t)
 
 
 def edges_from_host(keys: np.ndarray, counts: np.ndarray, k: int) -> Edges:
