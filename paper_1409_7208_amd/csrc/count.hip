@@ -806,61 +806,96 @@ __global__ void k_dead_ends(SortedView S, int k, uint8_t* __restrict__ fl) {
 
 // Solid set as a static bucket table for the per-window lookups of the
 // mercy rule.  Window keys arrive in read order, i.e. at random places in
-// key order, so a lookup should touch one cache line.  Bucket b (the top bb
-// bits of the key) holds the solid keys of b -- a contiguous range of the
-// sorted solid set -- in up to SL slots; the four top bits of each slot's
-// word 0 carry a valid bit and the dead-end flags (those bits are either
-// above the key or part of the bucket number, so they are not needed to
-// compare keys of one bucket).  Buckets with more than SL keys are marked
-// in ovf[] and searched in the sorted set.  Built by one streaming pass
-// over the sorted set, without atomics.
-template <int W>
-struct Bucket {
-  static constexpr int SL = W <= 2 ? 8 : 4;
+// key order, so a lookup should touch one short stretch of memory: random
+// reads from a table of several GB are bound by the number of load
+// requests and lines they make, so buckets are small and slots carry only
+// what the bucket number does not.  Bucket b holds the solid keys whose top
+// bb bits are b -- a contiguous range of the sorted solid set -- and is
+// built from it by one pass without atomics.  Keys whose bucket holds more
+// keys than slots are searched in the sorted set.
+//
+// Wider keys (two or more words): 4 slots of SWD words each.  A slot is the
+// little-endian integer (key's low rbits bits) | (valid | dead-end flags) <<
+// rbits; bit 64*SWD - 1 of slot 0 marks an overfull bucket.
+constexpr int WS_SLOTS = 4;
+
+struct WordSlots {
+  int bb, rbits, swd;
 };
 
-constexpr uint64_t kLow60 = (1ull << 60) - 1;
-
-template <int W>
-__global__ void k_bucket_fill(SortedView S, const uint8_t* __restrict__ sfl, uint64_t* __restrict__ tab,
-                              uint8_t* __restrict__ ovf, uint64_t nb) {
-  constexpr int SL = Bucket<W>::SL;
-  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  const uint64_t b = t / SL;
-  const int j = (int)(t % SL);
-  if (b >= nb) return;
-  const uint64_t lo = S.dir[b], n = S.dir[b + 1] - lo;
-  Key<W> x = key_zero<W>();
-  if ((uint64_t)j < n) {
-    x = key_load<W>(S.keys + (lo + j) * W);
-    x.w[0] = (x.w[0] & kLow60) | ((uint64_t)(8u | sfl[lo + j]) << 60);
-  }
-  key_store<W>(tab + t * W, x);
-  if (j == 0) ovf[b] = n > (uint64_t)SL;
+inline WordSlots word_slots_shape(int kb, int W, uint64_t nS) {
+  WordSlots p{};
+  p.bb = std::max(1, kb + 5 - 64 * W);  // the slot must fit W words
+  while (p.bb < 30 && p.bb < kb && ((uint64_t)WS_SLOTS << p.bb) < 2 * nS) ++p.bb;
+  p.rbits = kb - p.bb;
+  p.swd = (p.rbits + 5 + 63) / 64;
+  return p;
 }
 
-template <int W>
-DEV uint8_t bucket_flags(const uint64_t* __restrict__ tab, const uint8_t* __restrict__ ovf, const SortedView& S,
-                         const uint8_t* __restrict__ sfl, const Key<W>& q) {
-  constexpr int SL = Bucket<W>::SL;
-  const uint64_t b = key_bits<W>(q, S.kbits - S.db, S.db);
-  const uint64_t* p = tab + b * SL * W;
-  const uint64_t q0 = q.w[0] & kLow60;
-  Key<W> slot[SL];
+// Remainder bits of little-endian word i of a slot (0..64).
+DEV int ws_bits(int rbits, int i) { return rbits - 64 * i >= 64 ? 64 : (rbits - 64 * i > 0 ? rbits - 64 * i : 0); }
+
+DEV uint64_t ws_mask(int nbits) { return nbits >= 64 ? ~0ull : (nbits ? (~0ull >> (64 - nbits)) : 0ull); }
+
+template <int W, int SWD>
+__global__ void k_wslot_fill(SortedView S, const uint8_t* __restrict__ sfl, uint64_t* __restrict__ tab, uint64_t nb,
+                             int rbits) {
+  const uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const uint64_t lo = S.dir[b], n = S.dir[b + 1] - lo;
+  const int fw = rbits >> 6, fs = rbits & 63;
+  uint64_t* out = tab + b * (WS_SLOTS * SWD);
 #pragma unroll
-  for (int j = 0; j < SL; ++j) slot[j] = key_load<W>(p + j * W);
-  uint8_t f = 0;
-  bool full = true;
+  for (int j = 0; j < WS_SLOTS; ++j) {
+    uint64_t w[SWD];
 #pragma unroll
-  for (int j = 0; j < SL; ++j) {
-    const bool valid = (slot[j].w[0] >> 63) != 0;
-    full = full && valid;
-    bool eq = valid && (slot[j].w[0] & kLow60) == q0;
+    for (int i = 0; i < SWD; ++i) w[i] = 0;
+    if ((uint64_t)j < n) {
+      const Key<W> x = key_load<W>(S.keys + (lo + j) * W);
 #pragma unroll
-    for (int i = 1; i < W; ++i) eq = eq && slot[j].w[i] == q.w[i];
-    if (eq) f = (uint8_t)((slot[j].w[0] >> 60) & 7);
+      for (int i = 0; i < SWD; ++i) w[i] = x.w[W - 1 - i] & ws_mask(ws_bits(rbits, i));
+      const uint64_t fl = 8u | sfl[lo + j];
+#pragma unroll
+      for (int i = 0; i < SWD; ++i) {
+        if (i == fw) w[i] |= fl << fs;
+        if (i == fw + 1 && fs > 60) w[i] |= fl >> (64 - fs);
+      }
+    }
+    if (j == 0 && n > (uint64_t)WS_SLOTS) w[SWD - 1] |= 1ull << 63;
+#pragma unroll
+    for (int i = 0; i < SWD; ++i) out[j * SWD + i] = w[i];
   }
-  if (!f && full && ovf[b]) {
+}
+
+template <int W, int SWD>
+DEV uint8_t wslot_flags(const uint64_t* __restrict__ tab, const SortedView& S, const uint8_t* __restrict__ sfl,
+                        const Key<W>& q, int bb, int rbits) {
+  const uint64_t b = key_bits<W>(q, rbits, bb);
+  const uint4* v = reinterpret_cast<const uint4*>(tab + b * (WS_SLOTS * SWD));
+  uint64_t w[WS_SLOTS * SWD];
+#pragma unroll
+  for (int i = 0; i < WS_SLOTS * SWD / 2; ++i) {
+    const uint4 x = v[i];
+    w[2 * i] = x.x | ((uint64_t)x.y << 32);
+    w[2 * i + 1] = x.z | ((uint64_t)x.w << 32);
+  }
+  const bool ovf = (w[SWD - 1] >> 63) != 0;
+  const int fw = rbits >> 6, fs = rbits & 63;
+  uint8_t f = 0;
+#pragma unroll
+  for (int j = 0; j < WS_SLOTS; ++j) {
+    bool eq = true;
+    uint64_t fl = 0;
+#pragma unroll
+    for (int i = 0; i < SWD; ++i) {
+      const uint64_t m = ws_mask(ws_bits(rbits, i));
+      eq = eq && ((w[j * SWD + i] ^ q.w[W - 1 - i]) & m) == 0;
+      if (i == fw) fl |= w[j * SWD + i] >> fs;
+      if (i == fw + 1 && fs > 60) fl |= w[j * SWD + i] << (64 - fs);
+    }
+    if (eq && (fl & 8)) f = (uint8_t)(fl & 7);
+  }
+  if (!f && ovf) {
     uint64_t ix;
     f = sv_find<W>(S, q, &ix) ? sfl[ix] : 0;
   }
@@ -986,10 +1021,10 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags32(ExArgs a, const u
 // (a loop-carried lane mask seeded from an undefined SGPR pair picked up the
 // previous workgroup's register state), while the same functions replayed
 // on the host are exact.
-template <int W, int IPT>
-__global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags(ExArgs a, const uint64_t* __restrict__ tab,
-                                                             const uint8_t* __restrict__ ovf, SortedView S,
-                                                             const uint8_t* __restrict__ sfl, uint8_t* __restrict__ wf) {
+template <int W, int SWD, int IPT>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags(ExArgs a, const uint64_t* __restrict__ tab, int bb,
+                                                             int rbits, SortedView S, const uint8_t* __restrict__ sfl,
+                                                             uint8_t* __restrict__ wf) {
   const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
   if (g0 >= a.NW) return;
   WinIter it;
@@ -1011,7 +1046,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags(ExArgs a, const uin
   }
   uint8_t f[IPT];
 #pragma unroll
-  for (int q = 0; q < IPT; ++q) f[q] = ok[q] ? bucket_flags<W>(tab, ovf, S, sfl, key[q]) : (uint8_t)0x80;
+  for (int q = 0; q < IPT; ++q) f[q] = ok[q] ? wslot_flags<W, SWD>(tab, S, sfl, key[q], bb, rbits) : (uint8_t)0x80;
 #pragma unroll
   for (int q = 0; q < IPT; ++q)
     if (g0 + q < a.NW) wf[g0 + q] = f[q];
@@ -1517,6 +1552,38 @@ struct Counter {
     ea.tr = trd.get();
   }
 
+  // Fill the word-slot table and probe it once per forward window.
+  template <int SWD>
+  void window_flags_sw(const ExArgs& ea, const WordSlots& ws, const SortedView& bv, const uint8_t* sfl, uint64_t* btab,
+                       uint64_t nb, uint64_t NW, uint64_t words, uint8_t* wf, uint64_t nS) {
+    if constexpr (SWD <= W) {
+      {
+        Stage st_(c, "bucket_fill", nS * (8 * W + 1) + nb * (WS_SLOTS * SWD * 8 + 8));
+        k_wslot_fill<W, SWD><<<grid1(nb), SDBG_BLOCK, 0, c.s>>>(bv, sfl, btab, nb, ws.rbits);
+        c.check_launch("bucket_fill");
+      }
+      // each probe reads its bucket of 4 slots
+      Stage st_(c, "window_flags", 3 * words * 8 + NW + NW * WS_SLOTS * SWD * 8);
+      constexpr int WIPT = W == 2 ? 4 : W == 4 ? 2 : 1;
+      k_window_flags<W, SWD, WIPT><<<grid1(ceil_div(NW, WIPT)), SDBG_BLOCK, 0, c.s>>>(ea, btab, ws.bb, ws.rbits, bv,
+                                                                                    sfl, wf);
+      c.check_launch("window_flags");
+    } else {
+      throw Error(-4, "slot wider than a key");
+    }
+  }
+
+  void window_flags_ws(const ExArgs& ea, const WordSlots& ws, const SortedView& bv, const uint8_t* sfl, uint64_t* btab,
+                       uint64_t nb, uint64_t NW, uint64_t words, uint8_t* wf, uint64_t nS) {
+    switch (ws.swd) {
+      case 1: window_flags_sw<1>(ea, ws, bv, sfl, btab, nb, NW, words, wf, nS); break;
+      case 2: window_flags_sw<2>(ea, ws, bv, sfl, btab, nb, NW, words, wf, nS); break;
+      case 3: window_flags_sw<3>(ea, ws, bv, sfl, btab, nb, NW, words, wf, nS); break;
+      case 4: window_flags_sw<4>(ea, ws, bv, sfl, btab, nb, NW, words, wf, nS); break;
+      default: throw Error(-4, "bad slot width");
+    }
+  }
+
   void run(const DevReads& R, const CountParams& P, EdgesOut* out) {
     const int k = P.k, kb = 2 * (k + 1);
     Prep pr;
@@ -1559,14 +1626,47 @@ struct Counter {
       SDBG_CHECK(N <= max_keys, -3, "memory budget cannot hold the keys and prefix_len is 0");
       groups.push_back({0u, 1u << ea.pb});
     } else {
-      DBuf<unsigned long long> ph = c.buf<unsigned long long>(1ull << ea.pb);
-      fill<uint64_t>(reinterpret_cast<uint64_t*>(ph.get()), 1ull << ea.pb, 0, c);
-      k_ex_hist_prefix<W, IPT><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(ea, ph.get());
-      c.check_launch("ex_hist_prefix");
-      std::vector<unsigned long long> h(1ull << ea.pb);
-      c.d2h(h.data(), ph.get(), h.size());
       const int ub = std::max(0, ea.pb - 2 * P.prefix_len);  // block = 2^ub prefix values
-      const uint32_t unit = 1u << ub, nvals = 1u << ea.pb;
+      const uint32_t nvals = 1u << ea.pb;
+      // Key counts per first-cut digit come from the scanned histogram table
+      // already at hand; when every digit fits the budget and digit ranges
+      // are unions of prefix blocks, groups are planned on digits and no
+      // finer histogram is needed.
+      const int dshift = ea.pb - ea.dbits;  // prefix values per digit = 2^dshift
+      std::vector<uint64_t> dstart(nbins + 1);
+      {
+        DBuf<uint64_t> ds = c.buf<uint64_t>(nbins);
+        k_gather_strided<<<grid1(nbins), SDBG_BLOCK, 0, c.s>>>(tab.get(), ntiles, nbins, ds.get());
+        c.check_launch("gather_strided");
+        c.d2h(dstart.data(), ds.get(), nbins);
+        dstart[nbins] = N & 0xFFFFFFFFull;
+      }
+      // The table holds 32-bit positions, so starts are exact modulo 2^32;
+      // the differences are the digit counts if they add up to N (no digit
+      // holds 2^32 keys or more).
+      std::vector<uint64_t> dcount(nbins);
+      uint64_t dsum = 0;
+      for (uint32_t d = 0; d < nbins; ++d) {
+        dcount[d] = (uint32_t)(dstart[d + 1] - dstart[d]);
+        dsum += dcount[d];
+      }
+      bool digits_fit = ub <= dshift && dsum == N;
+      for (uint32_t d = 0; d < nbins && digits_fit; ++d) digits_fit = dcount[d] <= max_keys;
+      std::vector<unsigned long long> h;
+      uint32_t unit;
+      if (digits_fit) {
+        unit = 1u << dshift;
+        h.assign(nvals, 0);
+        for (uint32_t d = 0; d < nbins; ++d) h[(uint64_t)d << dshift] = dcount[d];
+      } else {
+        unit = 1u << ub;
+        DBuf<unsigned long long> ph = c.buf<unsigned long long>(nvals);
+        fill<uint64_t>(reinterpret_cast<uint64_t*>(ph.get()), nvals, 0, c);
+        k_ex_hist_prefix<W, IPT><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(ea, ph.get());
+        c.check_launch("ex_hist_prefix");
+        h.resize(nvals);
+        c.d2h(h.data(), ph.get(), h.size());
+      }
       uint32_t g0 = 0;
       uint64_t acc = 0;
       for (uint32_t u = 0; u < nvals; u += unit) {
@@ -1690,28 +1790,14 @@ struct Counter {
           c.check_launch("window_flags");
         }
       } else {
-        // bucket table: about SL/2 solid keys per bucket
-        constexpr int SL = Bucket<W>::SL;
-        int bb = 4;
-        while (bb < 30 && bb < kb && ((uint64_t)SL << bb) < 2 * nS) ++bb;
-        const uint64_t nb = 1ull << bb;
+        // word-slot buckets, about 2 solid keys per bucket of 4
+        const WordSlots ws = word_slots_shape(kb, W, nS);
+        const uint64_t nb = 1ull << ws.bb;
         DBuf<uint64_t> bdir;
-        SortedView bv = make_view_db(S.get(), nS, kb, bb, bdir);
-        DBuf<uint64_t> btab = c.buf<uint64_t>(nb * SL * W);
-        DBuf<uint8_t> ovf = c.buf<uint8_t>(nb);
-        {
-          Stage st_(c, "bucket_fill", nS * (8 * W + 1) + nb * (SL * 8 * W + 1 + 8));
-          k_bucket_fill<W><<<grid1(nb * SL), SDBG_BLOCK, 0, c.s>>>(bv, sfl.get(), btab.get(), ovf.get(), nb);
-          c.check_launch("bucket_fill");
-        }
-        {
-          // each probe reads its bucket of SL keys
-          Stage st_(c, "window_flags", 3 * words * 8 + NW + NW * SL * 8 * W);
-          constexpr int WIPT = W == 2 ? 4 : W == 4 ? 2 : 1;
-          k_window_flags<W, WIPT><<<grid1(ceil_div(NW, WIPT)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), ovf.get(), bv,
-                                                                                     sfl.get(), wf.get());
-          c.check_launch("window_flags");
-        }
+        SortedView bv = make_view_db(S.get(), nS, kb, ws.bb, bdir);
+        DBuf<uint64_t> btab = c.buf<uint64_t>(nb * WS_SLOTS * ws.swd);
+        VLOG("mercy table: 2^%d buckets of %d x %d words", ws.bb, WS_SLOTS, ws.swd);
+        window_flags_ws(ea, ws, bv, sfl.get(), btab.get(), nb, NW, words, wf.get(), nS);
       }
       DBuf<uint64_t> mcount = c.buf<uint64_t>(R.n_reads), mpos = c.buf<uint64_t>(R.n_reads);
       {
