@@ -902,75 +902,85 @@ DEV uint8_t wslot_flags(const uint64_t* __restrict__ tab, const SortedView& S, c
   return f;
 }
 
-// One-word keys use a denser table: 32-byte buckets, so that a lookup reads
-// one 32-byte sector instead of a 64-byte line (random reads over a table of
-// several GB are bound by the bytes they move).  Slot j of a bucket holds
-// bits [j*sb, (j+1)*sb) of the 256-bit bucket: the key's low rbits bits
-// (its top bb bits are the bucket number) and 4 flag bits (valid | dead-end
-// flags); bit 255 marks a bucket with more keys than slots, whose keys are
-// then searched in the sorted set.
-struct Packed32 {
-  int bb, rbits, sb, slots;
+// One-word keys use a denser table: buckets of BWN = 2 words (one 16-byte
+// load per probe) when three or more slots fit, else 4 words.  Slot j of a
+// bucket holds bits [j*sb, (j+1)*sb) of the bucket read as one little-endian
+// integer: the key's low rbits bits (its top bb bits are the bucket number)
+// and 4 flag bits (valid | dead-end flags); the bucket's top bit marks a
+// bucket with more keys than slots, whose keys are then searched in the
+// sorted set.
+struct PackedBits {
+  int bb, rbits, sb, slots, bwn;
 };
 
-inline Packed32 packed32_shape(int kb, uint64_t nS) {
-  Packed32 p{};
+inline PackedBits packed_shape_bw(int kb, uint64_t nS, int bwn) {
+  PackedBits p{};
+  p.bwn = bwn;
   for (p.bb = std::max(1, kb - 59);; ++p.bb) {
     p.rbits = std::max(0, kb - p.bb);
     p.sb = p.rbits + 4;
-    p.slots = 255 / p.sb;
+    p.slots = (64 * bwn - 1) / p.sb;
     if (p.bb >= 30 || p.bb >= kb || ((uint64_t)p.slots << p.bb) >= 2 * nS) return p;
   }
+}
+
+inline PackedBits packed_shape(int kb, uint64_t nS) {
+  const PackedBits p = packed_shape_bw(kb, nS, 2);
+  return p.slots >= 3 ? p : packed_shape_bw(kb, nS, 4);
 }
 
 // One thread per bucket: its keys are a contiguous range of the sorted set
 // (S's directory is over the top bb bits).  Slots are shifted in from the
 // last to the first.
-__global__ void k_bucket32_fill(SortedView S, const uint8_t* __restrict__ sfl, uint64_t* __restrict__ tab,
-                                uint64_t nb, Packed32 p) {
+template <int BWN>
+__global__ void k_bucket_fill_bits(SortedView S, const uint8_t* __restrict__ sfl, uint64_t* __restrict__ tab,
+                                   uint64_t nb, PackedBits p) {
   const uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (b >= nb) return;
   const uint64_t lo = S.dir[b], n = S.dir[b + 1] - lo;
   const uint64_t m = n < (uint64_t)p.slots ? n : (uint64_t)p.slots;
   const uint64_t rmask = p.rbits ? (~0ull >> (64 - p.rbits)) : 0;
   const int sb = p.sb;
-  uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+  uint64_t w[BWN];
+#pragma unroll
+  for (int i = 0; i < BWN; ++i) w[i] = 0;
   for (uint64_t j = m; j-- > 0;) {
     const uint64_t slot = (S.keys[lo + j] & rmask) | ((uint64_t)(8u | sfl[lo + j]) << p.rbits);
-    w3 = (w3 << sb) | (w2 >> (64 - sb));
-    w2 = (w2 << sb) | (w1 >> (64 - sb));
-    w1 = (w1 << sb) | (w0 >> (64 - sb));
-    w0 = (w0 << sb) | slot;
+#pragma unroll
+    for (int i = BWN - 1; i > 0; --i) w[i] = (w[i] << sb) | (w[i - 1] >> (64 - sb));
+    w[0] = (w[0] << sb) | slot;
   }
-  if (n > (uint64_t)p.slots) w3 |= 1ull << 63;
-  uint64_t* out = tab + b * 4;
-  out[0] = w0;
-  out[1] = w1;
-  out[2] = w2;
-  out[3] = w3;
+  if (n > (uint64_t)p.slots) w[BWN - 1] |= 1ull << 63;
+  uint64_t* out = tab + b * BWN;
+#pragma unroll
+  for (int i = 0; i < BWN; ++i) out[i] = w[i];
 }
 
-DEV uint8_t bucket32_flags(const uint64_t* __restrict__ tab, const SortedView& S, const uint8_t* __restrict__ sfl,
-                           uint64_t q, const Packed32& p) {
+template <int BWN>
+DEV uint8_t bucket_flags_bits(const uint64_t* __restrict__ tab, const SortedView& S, const uint8_t* __restrict__ sfl,
+                              uint64_t q, const PackedBits& p) {
   const uint64_t b = p.rbits ? q >> p.rbits : q;
-  const uint4* v = reinterpret_cast<const uint4*>(tab + b * 4);
-  const uint4 a = v[0], c = v[1];
-  uint64_t w0 = a.x | ((uint64_t)a.y << 32), w1 = a.z | ((uint64_t)a.w << 32);
-  uint64_t w2 = c.x | ((uint64_t)c.y << 32), w3 = c.z | ((uint64_t)c.w << 32);
-  const bool ovf = (w3 >> 63) != 0;
+  const uint4* v = reinterpret_cast<const uint4*>(tab + b * BWN);
+  uint64_t w[BWN];
+#pragma unroll
+  for (int i = 0; i < BWN / 2; ++i) {
+    const uint4 x = v[i];
+    w[2 * i] = x.x | ((uint64_t)x.y << 32);
+    w[2 * i + 1] = x.z | ((uint64_t)x.w << 32);
+  }
+  const bool ovf = (w[BWN - 1] >> 63) != 0;
   const uint64_t rmask = p.rbits ? (~0ull >> (64 - p.rbits)) : 0;
   const uint64_t smask = ~0ull >> (64 - p.sb);
   const uint64_t qr = q & rmask;
   const int sb = p.sb;
   uint8_t f = 0;
   for (int j = 0; j < p.slots; ++j) {
-    const uint64_t x = w0 & smask;
+    const uint64_t x = w[0] & smask;
     const uint32_t fl = (uint32_t)(x >> p.rbits);
     if ((fl & 8u) && (x & rmask) == qr) f = (uint8_t)(fl & 7u);
-    w0 = (w0 >> sb) | (w1 << (64 - sb));
-    w1 = (w1 >> sb) | (w2 << (64 - sb));
-    w2 = (w2 >> sb) | (w3 << (64 - sb));
-    w3 >>= sb;
+#pragma unroll
+    for (int i = 0; i < BWN - 1; ++i) w[i] = (w[i] >> sb) | (w[i + 1] << (64 - sb));
+    w[BWN - 1] >>= sb;
   }
   if (!f && ovf) {
     uint64_t ix;
@@ -981,10 +991,11 @@ DEV uint8_t bucket32_flags(const uint64_t* __restrict__ tab, const SortedView& S
   return f;
 }
 
-template <int IPT>
-__global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags32(ExArgs a, const uint64_t* __restrict__ tab, Packed32 p,
-                                                               SortedView S, const uint8_t* __restrict__ sfl,
-                                                               uint8_t* __restrict__ wf) {
+template <int BWN, int IPT>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags_bits(ExArgs a, const uint64_t* __restrict__ tab,
+                                                                  PackedBits p, SortedView S,
+                                                                  const uint8_t* __restrict__ sfl,
+                                                                  uint8_t* __restrict__ wf) {
   const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
   if (g0 >= a.NW) return;
   WinIter it;
@@ -1006,7 +1017,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags32(ExArgs a, const u
   }
   uint8_t f[IPT];
 #pragma unroll
-  for (int q = 0; q < IPT; ++q) f[q] = ok[q] ? bucket32_flags(tab, S, sfl, key[q], p) : (uint8_t)0x80;
+  for (int q = 0; q < IPT; ++q) f[q] = ok[q] ? bucket_flags_bits<BWN>(tab, S, sfl, key[q], p) : (uint8_t)0x80;
 #pragma unroll
   for (int q = 0; q < IPT; ++q)
     if (g0 + q < a.NW) wf[g0 + q] = f[q];
@@ -1771,22 +1782,30 @@ struct Counter {
       }
       DBuf<uint8_t> wf = c.buf<uint8_t>(NW);
       if constexpr (W == 1) {
-        // packed 32-byte buckets, about slots/2 solid keys per bucket
-        const Packed32 pk = packed32_shape(kb, nS);
+        // packed buckets, about slots/2 solid keys per bucket
+        const PackedBits pk = packed_shape(kb, nS);
         const uint64_t nb = 1ull << pk.bb;
         DBuf<uint64_t> bdir;
         SortedView bv = make_view_db(S.get(), nS, kb, pk.bb, bdir);
-        DBuf<uint64_t> btab = c.buf<uint64_t>(nb * 4);
+        DBuf<uint64_t> btab = c.buf<uint64_t>(nb * pk.bwn);
+        VLOG("mercy table: 2^%d buckets of %d words, %d slots", pk.bb, pk.bwn, pk.slots);
         {
-          Stage st_(c, "bucket_fill", nS * 9 + nb * (32 + 8));
-          k_bucket32_fill<<<grid1(nb), SDBG_BLOCK, 0, c.s>>>(bv, sfl.get(), btab.get(), nb, pk);
+          Stage st_(c, "bucket_fill", nS * 9 + nb * (8 * pk.bwn + 8));
+          if (pk.bwn == 2)
+            k_bucket_fill_bits<2><<<grid1(nb), SDBG_BLOCK, 0, c.s>>>(bv, sfl.get(), btab.get(), nb, pk);
+          else
+            k_bucket_fill_bits<4><<<grid1(nb), SDBG_BLOCK, 0, c.s>>>(bv, sfl.get(), btab.get(), nb, pk);
           c.check_launch("bucket_fill");
         }
         {
-          // each probe reads its 32-byte bucket
-          Stage st_(c, "window_flags", 3 * words * 8 + NW + NW * 32);
-          k_window_flags32<8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), pk, bv, sfl.get(),
-                                                                               wf.get());
+          // each probe reads its bucket
+          Stage st_(c, "window_flags", 3 * words * 8 + NW + NW * 8 * pk.bwn);
+          if (pk.bwn == 2)
+            k_window_flags_bits<2, 8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), pk, bv, sfl.get(),
+                                                                                   wf.get());
+          else
+            k_window_flags_bits<4, 8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), pk, bv, sfl.get(),
+                                                                                   wf.get());
           c.check_launch("window_flags");
         }
       } else {
