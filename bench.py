@@ -27,6 +27,39 @@ METRIC = "Gmer/s sort+count+SdBG build (frac of HBM roofline); p99 job latency v
 HBM_PEAK_GBS = 8000.0
 
 
+# HBM traffic of the dominant kernels, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counter runs scaled by a 1 GiB device copy (profiles/), valid
+# while the kernel sources hash to the value recorded there.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_metagenome_k31.md")
+KERNEL_SOURCES = ["paper_1409_7208_amd/csrc/count.hip", "paper_1409_7208_amd/csrc/device.h",
+                  "paper_1409_7208_amd/csrc/kernels.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(stage: str, workload: str):
+    """Bytes per launch recorded for `stage` on the headline workload, or None."""
+    if workload != "metagenome" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    src = kernel_source_hash()
+    for line in open(TRAFFIC_FILE):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 3 and cells[0] == stage and cells[-1] == src:
+            try:
+                return float(cells[-2])
+            except ValueError:
+                return None
+    return None
+
+
 def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
@@ -355,8 +388,9 @@ def main():
     dom = max(agg.items(), key=lambda x: x[1][1])
     dn, (dcnt, dms, dbytes) = dom
     achieved = dbytes / (dms * 1e-3) / 1e9
+    traffic = recorded_traffic(dn, args.workload) if args.scale == 1.0 else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dn,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dn,
                 "avg_launch_ms": round(dms / dcnt, 4), "bytes_per_launch": int(dbytes / dcnt)}
 
     # Whole step against the HBM roofline: every profiled launch's algorithmic
