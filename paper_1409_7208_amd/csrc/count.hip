@@ -837,33 +837,40 @@ DEV int ws_bits(int rbits, int i) { return rbits - 64 * i >= 64 ? 64 : (rbits - 
 
 DEV uint64_t ws_mask(int nbits) { return nbits >= 64 ? ~0ull : (nbits ? (~0ull >> (64 - nbits)) : 0ull); }
 
+// One thread per solid key; the first key of each bucket (the sorted set
+// holds a bucket's keys together) writes the whole bucket.  Empty buckets
+// stay as the table was cleared.
 template <int W, int SWD>
-__global__ void k_wslot_fill(SortedView S, const uint8_t* __restrict__ sfl, uint64_t* __restrict__ tab, uint64_t nb,
-                             int rbits) {
-  const uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  const uint64_t lo = S.dir[b], n = S.dir[b + 1] - lo;
+__global__ void k_wslot_fill(const uint64_t* __restrict__ keys, uint64_t nS, const uint8_t* __restrict__ sfl,
+                             uint64_t* __restrict__ tab, int bb, int rbits) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= nS) return;
+  const uint32_t b = key_bits<W>(key_load<W>(keys + i * W), rbits, bb);
+  if (i > 0 && key_bits<W>(key_load<W>(keys + (i - 1) * W), rbits, bb) == b) return;
   const int fw = rbits >> 6, fs = rbits & 63;
-  uint64_t* out = tab + b * (WS_SLOTS * SWD);
+  uint64_t* out = tab + (uint64_t)b * (WS_SLOTS * SWD);
+  bool more = true;  // key i + j is still in bucket b
 #pragma unroll
   for (int j = 0; j < WS_SLOTS; ++j) {
     uint64_t w[SWD];
 #pragma unroll
-    for (int i = 0; i < SWD; ++i) w[i] = 0;
-    if ((uint64_t)j < n) {
-      const Key<W> x = key_load<W>(S.keys + (lo + j) * W);
+    for (int x = 0; x < SWD; ++x) w[x] = 0;
+    more = more && i + j < nS && (j == 0 || key_bits<W>(key_load<W>(keys + (i + j) * W), rbits, bb) == b);
+    if (more) {
+      const Key<W> k = key_load<W>(keys + (i + j) * W);
 #pragma unroll
-      for (int i = 0; i < SWD; ++i) w[i] = x.w[W - 1 - i] & ws_mask(ws_bits(rbits, i));
-      const uint64_t fl = 8u | sfl[lo + j];
+      for (int x = 0; x < SWD; ++x) w[x] = k.w[W - 1 - x] & ws_mask(ws_bits(rbits, x));
+      const uint64_t fl = 8u | sfl[i + j];
 #pragma unroll
-      for (int i = 0; i < SWD; ++i) {
-        if (i == fw) w[i] |= fl << fs;
-        if (i == fw + 1 && fs > 60) w[i] |= fl >> (64 - fs);
+      for (int x = 0; x < SWD; ++x) {
+        if (x == fw) w[x] |= fl << fs;
+        if (x == fw + 1 && fs > 60) w[x] |= fl >> (64 - fs);
       }
     }
-    if (j == 0 && n > (uint64_t)WS_SLOTS) w[SWD - 1] |= 1ull << 63;
+    if (j == 0 && i + WS_SLOTS < nS && key_bits<W>(key_load<W>(keys + (i + WS_SLOTS) * W), rbits, bb) == b)
+      w[SWD - 1] |= 1ull << 63;
 #pragma unroll
-    for (int i = 0; i < SWD; ++i) out[j * SWD + i] = w[i];
+    for (int x = 0; x < SWD; ++x) out[j * SWD + x] = w[x];
   }
 }
 
@@ -929,31 +936,35 @@ inline PackedBits packed_shape(int kb, uint64_t nS) {
   return p.slots >= 3 ? p : packed_shape_bw(kb, nS, 4);
 }
 
-// One thread per bucket: its keys are a contiguous range of the sorted set
-// (S's directory is over the top bb bits).  Slots are shifted in from the
-// last to the first.
+// One thread per solid key; the first key of each bucket (the sorted set
+// holds a bucket's keys together) writes the whole bucket, shifting its
+// slots in from the last to the first.  Empty buckets stay as the table
+// was cleared.
 template <int BWN>
-__global__ void k_bucket_fill_bits(SortedView S, const uint8_t* __restrict__ sfl, uint64_t* __restrict__ tab,
-                                   uint64_t nb, PackedBits p) {
-  const uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  const uint64_t lo = S.dir[b], n = S.dir[b + 1] - lo;
+__global__ void k_bucket_fill_bits(const uint64_t* __restrict__ keys, uint64_t nS, const uint8_t* __restrict__ sfl,
+                                   uint64_t* __restrict__ tab, PackedBits p) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= nS) return;
+  const uint64_t b = p.rbits ? keys[i] >> p.rbits : keys[i];
+  if (i > 0 && (p.rbits ? keys[i - 1] >> p.rbits : keys[i - 1]) == b) return;
+  uint64_t n = 1;  // keys of bucket b from i on, counted up to slots + 1
+  while (n <= (uint64_t)p.slots && i + n < nS && (p.rbits ? keys[i + n] >> p.rbits : keys[i + n]) == b) ++n;
   const uint64_t m = n < (uint64_t)p.slots ? n : (uint64_t)p.slots;
   const uint64_t rmask = p.rbits ? (~0ull >> (64 - p.rbits)) : 0;
   const int sb = p.sb;
   uint64_t w[BWN];
 #pragma unroll
-  for (int i = 0; i < BWN; ++i) w[i] = 0;
+  for (int x = 0; x < BWN; ++x) w[x] = 0;
   for (uint64_t j = m; j-- > 0;) {
-    const uint64_t slot = (S.keys[lo + j] & rmask) | ((uint64_t)(8u | sfl[lo + j]) << p.rbits);
+    const uint64_t slot = (keys[i + j] & rmask) | ((uint64_t)(8u | sfl[i + j]) << p.rbits);
 #pragma unroll
-    for (int i = BWN - 1; i > 0; --i) w[i] = (w[i] << sb) | (w[i - 1] >> (64 - sb));
+    for (int x = BWN - 1; x > 0; --x) w[x] = (w[x] << sb) | (w[x - 1] >> (64 - sb));
     w[0] = (w[0] << sb) | slot;
   }
   if (n > (uint64_t)p.slots) w[BWN - 1] |= 1ull << 63;
   uint64_t* out = tab + b * BWN;
 #pragma unroll
-  for (int i = 0; i < BWN; ++i) out[i] = w[i];
+  for (int x = 0; x < BWN; ++x) out[x] = w[x];
 }
 
 template <int BWN>
@@ -1066,19 +1077,32 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags(ExArgs a, const uin
 // Mercy rule along each read (forward strand): consecutive solid windows
 // p < q of one ACGT stretch, q - p >= 2, p without outgoing and q without
 // incoming solid edge: windows p+1..q-1 and their reverse complements are
-// mercy edges.  Pass 0 counts keys per read, pass 1 writes them.
+// mercy edges.  Pass 0 counts keys per read, pass 1 writes them (only for
+// reads with a count).  Flags are read eight at a time (wf is padded to a
+// whole word).
 template <int W>
 __global__ void k_mercy(ExArgs a, const uint8_t* __restrict__ wf, int pass, uint64_t* __restrict__ mcount,
                         const uint64_t* __restrict__ mpos, uint64_t* __restrict__ cand) {
   uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (r >= a.n_reads) return;
+  if (pass && mcount[r] == 0) return;
   const uint64_t g0 = a.woff[r], g1 = a.woff[r + 1];
   const uint64_t rs = a.offsets[r];
   uint64_t out = pass ? mpos[r] : 0, c = 0;
   int64_t p = -1;
   bool p_noout = false;
+  const uint64_t* wf64 = reinterpret_cast<const uint64_t*>(wf);
+  uint64_t wi = g0 >> 3;
+  uint64_t word = g0 < g1 ? wf64[wi] >> (8 * (g0 & 7)) : 0;
+  int avail = 8 - (int)(g0 & 7);
   for (uint64_t g = g0; g < g1; ++g) {
-    const uint8_t f = wf[g];
+    if (!avail) {
+      word = wf64[++wi];
+      avail = 8;
+    }
+    const uint8_t f = (uint8_t)word;
+    word >>= 8;
+    --avail;
     if (f & 0x80) {
       p = -1;
       continue;
@@ -1565,12 +1589,13 @@ struct Counter {
 
   // Fill the word-slot table and probe it once per forward window.
   template <int SWD>
-  void window_flags_sw(const ExArgs& ea, const WordSlots& ws, const SortedView& bv, const uint8_t* sfl, uint64_t* btab,
-                       uint64_t nb, uint64_t NW, uint64_t words, uint8_t* wf, uint64_t nS) {
+  void window_flags_sw(const ExArgs& ea, const WordSlots& ws, const SortedView& bv, const uint64_t* skeys,
+                       const uint8_t* sfl, uint64_t* btab, uint64_t nb, uint64_t NW, uint64_t words, uint8_t* wf,
+                       uint64_t nS) {
     if constexpr (SWD <= W) {
       {
-        Stage st_(c, "bucket_fill", nS * (8 * W + 1) + nb * (WS_SLOTS * SWD * 8 + 8));
-        k_wslot_fill<W, SWD><<<grid1(nb), SDBG_BLOCK, 0, c.s>>>(bv, sfl, btab, nb, ws.rbits);
+        Stage st_(c, "bucket_fill", nS * (8 * W + 1) + nb * WS_SLOTS * SWD * 8);
+        k_wslot_fill<W, SWD><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(skeys, nS, sfl, btab, ws.bb, ws.rbits);
         c.check_launch("bucket_fill");
       }
       // each probe reads its bucket of 4 slots
@@ -1584,13 +1609,14 @@ struct Counter {
     }
   }
 
-  void window_flags_ws(const ExArgs& ea, const WordSlots& ws, const SortedView& bv, const uint8_t* sfl, uint64_t* btab,
-                       uint64_t nb, uint64_t NW, uint64_t words, uint8_t* wf, uint64_t nS) {
+  void window_flags_ws(const ExArgs& ea, const WordSlots& ws, const SortedView& bv, const uint64_t* skeys,
+                       const uint8_t* sfl, uint64_t* btab, uint64_t nb, uint64_t NW, uint64_t words, uint8_t* wf,
+                       uint64_t nS) {
     switch (ws.swd) {
-      case 1: window_flags_sw<1>(ea, ws, bv, sfl, btab, nb, NW, words, wf, nS); break;
-      case 2: window_flags_sw<2>(ea, ws, bv, sfl, btab, nb, NW, words, wf, nS); break;
-      case 3: window_flags_sw<3>(ea, ws, bv, sfl, btab, nb, NW, words, wf, nS); break;
-      case 4: window_flags_sw<4>(ea, ws, bv, sfl, btab, nb, NW, words, wf, nS); break;
+      case 1: window_flags_sw<1>(ea, ws, bv, skeys, sfl, btab, nb, NW, words, wf, nS); break;
+      case 2: window_flags_sw<2>(ea, ws, bv, skeys, sfl, btab, nb, NW, words, wf, nS); break;
+      case 3: window_flags_sw<3>(ea, ws, bv, skeys, sfl, btab, nb, NW, words, wf, nS); break;
+      case 4: window_flags_sw<4>(ea, ws, bv, skeys, sfl, btab, nb, NW, words, wf, nS); break;
       default: throw Error(-4, "bad slot width");
     }
   }
@@ -1780,31 +1806,30 @@ struct Counter {
         k_dead_ends<W><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(sv, k, sfl.get());
         c.check_launch("dead_ends");
       }
-      DBuf<uint8_t> wf = c.buf<uint8_t>(NW);
+      DBuf<uint8_t> wf = c.buf<uint8_t>(NW + 8);
       if constexpr (W == 1) {
         // packed buckets, about slots/2 solid keys per bucket
         const PackedBits pk = packed_shape(kb, nS);
         const uint64_t nb = 1ull << pk.bb;
-        DBuf<uint64_t> bdir;
-        SortedView bv = make_view_db(S.get(), nS, kb, pk.bb, bdir);
         DBuf<uint64_t> btab = c.buf<uint64_t>(nb * pk.bwn);
+        fill<uint64_t>(btab.get(), nb * pk.bwn, 0, c);
         VLOG("mercy table: 2^%d buckets of %d words, %d slots", pk.bb, pk.bwn, pk.slots);
         {
-          Stage st_(c, "bucket_fill", nS * 9 + nb * (8 * pk.bwn + 8));
+          Stage st_(c, "bucket_fill", nS * 9 + nb * 8 * pk.bwn);
           if (pk.bwn == 2)
-            k_bucket_fill_bits<2><<<grid1(nb), SDBG_BLOCK, 0, c.s>>>(bv, sfl.get(), btab.get(), nb, pk);
+            k_bucket_fill_bits<2><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(S.get(), nS, sfl.get(), btab.get(), pk);
           else
-            k_bucket_fill_bits<4><<<grid1(nb), SDBG_BLOCK, 0, c.s>>>(bv, sfl.get(), btab.get(), nb, pk);
+            k_bucket_fill_bits<4><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(S.get(), nS, sfl.get(), btab.get(), pk);
           c.check_launch("bucket_fill");
         }
         {
           // each probe reads its bucket
           Stage st_(c, "window_flags", 3 * words * 8 + NW + NW * 8 * pk.bwn);
           if (pk.bwn == 2)
-            k_window_flags_bits<2, 8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), pk, bv, sfl.get(),
+            k_window_flags_bits<2, 8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), pk, sv, sfl.get(),
                                                                                    wf.get());
           else
-            k_window_flags_bits<4, 8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), pk, bv, sfl.get(),
+            k_window_flags_bits<4, 8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), pk, sv, sfl.get(),
                                                                                    wf.get());
           c.check_launch("window_flags");
         }
@@ -1812,11 +1837,10 @@ struct Counter {
         // word-slot buckets, about 2 solid keys per bucket of 4
         const WordSlots ws = word_slots_shape(kb, W, nS);
         const uint64_t nb = 1ull << ws.bb;
-        DBuf<uint64_t> bdir;
-        SortedView bv = make_view_db(S.get(), nS, kb, ws.bb, bdir);
         DBuf<uint64_t> btab = c.buf<uint64_t>(nb * WS_SLOTS * ws.swd);
+        fill<uint64_t>(btab.get(), nb * WS_SLOTS * ws.swd, 0, c);
         VLOG("mercy table: 2^%d buckets of %d x %d words", ws.bb, WS_SLOTS, ws.swd);
-        window_flags_ws(ea, ws, bv, sfl.get(), btab.get(), nb, NW, words, wf.get(), nS);
+        window_flags_ws(ea, ws, sv, S.get(), sfl.get(), btab.get(), nb, NW, words, wf.get(), nS);
       }
       DBuf<uint64_t> mcount = c.buf<uint64_t>(R.n_reads), mpos = c.buf<uint64_t>(R.n_reads);
       {
@@ -1848,7 +1872,7 @@ struct Counter {
         DBuf<uint64_t> cand = c.buf<uint64_t>(NC * W);
         {
           Stage st_(c, "mercy_emit", NW + R.n_reads * 24 + NC * 8 * W);
-          k_mercy<W><<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(ea, wf.get(), 1, nullptr, mpos.get(), cand.get());
+          k_mercy<W><<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(ea, wf.get(), 1, mcount.get(), mpos.get(), cand.get());
           c.check_launch("mercy_emit");
         }
         wf.free();
