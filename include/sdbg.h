@@ -132,7 +132,12 @@ typedef struct sdbg_graph {
 int sdbg_count_solid(const sdbg_reads *reads, const sdbg_params *params, sdbg_edges **out);
 
 /* SdBG arrays of an edge set (Section 2, first and second paragraphs).
- * Uses params->stream only; the other fields are ignored. */
+ * Uses params->stream only (params may be NULL: null stream); the other
+ * fields are ignored.  An edge set made by sdbg_edges_from_host is checked
+ * first: SDBG_E_INVAL if its keys are not strictly ascending or have bits
+ * above 2(k+1); edge sets the library computed are sorted by construction
+ * and not checked again.  SDBG_E_INVAL also for an object this library did
+ * not return. */
 int sdbg_build(const sdbg_edges *edges, const sdbg_params *params, sdbg_graph **out);
 
 /* Batched form: count (and, if graphs_out is not NULL, build) n_sets

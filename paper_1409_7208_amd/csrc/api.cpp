@@ -20,6 +20,9 @@ namespace sdbg_abi {
 thread_local std::string t_err;
 
 enum ObjKind { kEdges = 1, kGraph = 2 };
+// Edge sets the library computed itself are sorted and in range by
+// construction; sdbg_build checks the others.
+constexpr int kSortedByConstruction = 0x100;
 
 // Every object handed out is registered with its kind, so that sdbg_free
 // can release any of them and rejects unknown pointers.
@@ -43,11 +46,13 @@ int reg_take(void* p) {
   return k;
 }
 
-int reg_kind(const void* p) {
+int reg_entry(const void* p) {
   std::lock_guard<std::mutex> lk(g_reg_mu);
   auto it = registry().find(const_cast<void*>(p));
   return it == registry().end() ? 0 : it->second;
 }
+
+int reg_kind(const void* p) { return reg_entry(p) & 0xFF; }
 
 void pool_free(void* p) {
   if (p) sdbg::Pool::get().release(p, nullptr, false);
@@ -70,7 +75,7 @@ sdbg_edges* wrap_edges(const sdbg::EdgesOut& eo, uint32_t k) {
   e->n_occ = eo.n_occ;
   e->keys = eo.keys;
   e->count = eo.count;
-  reg_add(e, kEdges);
+  reg_add(e, kEdges | kSortedByConstruction);
   return e;
 }
 
@@ -211,16 +216,7 @@ int sdbg_count_solid(const sdbg_reads* reads, const sdbg_params* params, sdbg_ed
     sdbg::count_solid(R, P, c, &eo);
     c.sync();
     sdbg::prof_flush();
-    sdbg_edges* e = new sdbg_edges();
-    e->k = params->k;
-    e->w = (uint32_t)sdbg::key_words((int)params->k);
-    e->n = eo.n;
-    e->n_mercy = eo.n_mercy;
-    e->n_occ = eo.n_occ;
-    e->keys = eo.keys;
-    e->count = eo.count;
-    reg_add(e, kEdges);
-    *out = e;
+    *out = wrap_edges(eo, params->k);
     return SDBG_OK;
   });
 }
@@ -233,7 +229,8 @@ int sdbg_build(const sdbg_edges* edges, const sdbg_params* params, sdbg_graph** 
     check_k(edges->k);
     sdbg::Ctx c(params ? params->stream : nullptr);
     sdbg::GraphOut go;
-    sdbg::build_graph(edges->keys, edges->count, edges->n, (int)edges->k, c, &go);
+    sdbg::build_graph(edges->keys, edges->count, edges->n, (int)edges->k, c, &go,
+                      (reg_entry(edges) & kSortedByConstruction) == 0);
     c.sync();
     sdbg::prof_flush();
     sdbg_graph* g = new sdbg_graph();
@@ -377,7 +374,7 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
                 const uint64_t i = next.fetch_add(1);
                 if (i >= n_sets || failed.load()) break;
                 sdbg::GraphOut go;
-                sdbg::build_graph(edges_out[i]->keys, edges_out[i]->count, edges_out[i]->n, (int)k, c2, &go);
+                sdbg::build_graph(edges_out[i]->keys, edges_out[i]->count, edges_out[i]->n, (int)k, c2, &go, false);
                 c2.sync();
                 graphs_out[i] = wrap_graph(go, k);
               }
@@ -555,7 +552,7 @@ int sdbg_graph_to_host(const sdbg_graph* g, uint8_t* W, uint64_t* last, uint64_t
 
 void sdbg_free(void* obj) {
   if (!obj) return;
-  int kind = reg_take(obj);
+  int kind = reg_take(obj) & 0xFF;
   try {
     if (kind == kEdges) {
       sdbg_edges* e = static_cast<sdbg_edges*>(obj);

@@ -307,11 +307,11 @@ struct Builder {
     }
   }
 
-  void run(const uint64_t* keys, const uint32_t* count, uint64_t n, int k, GraphOut* g) {
+  void run(const uint64_t* keys, const uint32_t* count, uint64_t n, int k, GraphOut* g, bool check) {
     const int kb = 2 * (k + 1);
     *g = GraphOut{};
     if (n == 0) return;
-    {
+    if (check) {
       DBuf<uint32_t> flags = c.buf<uint32_t>(1);
       fill<uint32_t>(flags.get(), 1, 0, c);
       k_check_sorted_b<W><<<grid1(n), SDBG_BLOCK, 0, c.s>>>(keys, n, kb, flags.get());
@@ -392,12 +392,12 @@ struct Builder {
 
 }  // namespace
 
-void build_graph(const uint64_t* keys, const uint32_t* count, uint64_t n, int k, Ctx& c, GraphOut* out) {
+void build_graph(const uint64_t* keys, const uint32_t* count, uint64_t n, int k, Ctx& c, GraphOut* out, bool check) {
   switch (key_words(k)) {
-    case 1: Builder<1>(c).run(keys, count, n, k, out); break;
-    case 2: Builder<2>(c).run(keys, count, n, k, out); break;
-    case 3: Builder<3>(c).run(keys, count, n, k, out); break;
-    case 4: Builder<4>(c).run(keys, count, n, k, out); break;
+    case 1: Builder<1>(c).run(keys, count, n, k, out, check); break;
+    case 2: Builder<2>(c).run(keys, count, n, k, out, check); break;
+    case 3: Builder<3>(c).run(keys, count, n, k, out, check); break;
+    case 4: Builder<4>(c).run(keys, count, n, k, out, check); break;
     default: throw Error(-1, "k out of range");
   }
 }

@@ -91,6 +91,8 @@ void count_solid(const DevReads& r, const CountParams& p, Ctx& c, EdgesOut* out)
 // off; outs[s] equals count_solid of set s alone.
 void count_solid_sets(const DevReads& r, const std::vector<uint64_t>& rb, const CountParams& p, Ctx& c,
                       std::vector<EdgesOut>* outs);
-void build_graph(const uint64_t* keys, const uint32_t* count, uint64_t n, int k, Ctx& c, GraphOut* out);
+// check = false skips the order check for edge sets the library computed.
+void build_graph(const uint64_t* keys, const uint32_t* count, uint64_t n, int k, Ctx& c, GraphOut* out,
+                 bool check = true);
 
 }  // namespace sdbg

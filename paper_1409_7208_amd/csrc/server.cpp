@@ -157,7 +157,7 @@ struct sdbg_server {
       }
       e = sdbg_abi::wrap_edges(eo, j->params.k);
       if (cfg.build) {
-        sdbg::build_graph(e->keys, e->count, e->n, (int)j->params.k, c, &go);
+        sdbg::build_graph(e->keys, e->count, e->n, (int)j->params.k, c, &go, false);
         c.sync();
         j->graph = sdbg_abi::wrap_graph(go, j->params.k);
       }
