@@ -553,7 +553,7 @@ struct LeafShape {
 };
 
 template <int W, int CAP>
-__global__ __launch_bounds__(SDBG_BLOCK) void k_leaf(SegView v, uint64_t* const* __restrict__ bufs,
+__global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* const* __restrict__ bufs,
                                                      uint32_t* __restrict__ cnt, uint32_t dmin, int want_low,
                                                      uint64_t* __restrict__ nsolid, uint64_t* __restrict__ nlow) {
   constexpr int PER = LeafShape<CAP>::PER, H = LeafShape<CAP>::H, MAXB = LeafShape<CAP>::MAXB;
@@ -838,15 +838,22 @@ DEV int ws_bits(int rbits, int i) { return rbits - 64 * i >= 64 ? 64 : (rbits - 
 DEV uint64_t ws_mask(int nbits) { return nbits >= 64 ? ~0ull : (nbits ? (~0ull >> (64 - nbits)) : 0ull); }
 
 // One thread per solid key; the first key of each bucket (the sorted set
-// holds a bucket's keys together) writes the whole bucket.  Empty buckets
-// stay as the table was cleared.
+// holds a bucket's keys together) writes the whole bucket and clears the
+// empty buckets between the previous key's bucket and its own (the last one
+// also those after it), so every bucket is written exactly once.
 template <int W, int SWD>
 __global__ void k_wslot_fill(const uint64_t* __restrict__ keys, uint64_t nS, const uint8_t* __restrict__ sfl,
-                             uint64_t* __restrict__ tab, int bb, int rbits) {
+                             uint64_t* __restrict__ tab, uint64_t nb, int bb, int rbits) {
   const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (i >= nS) return;
   const uint32_t b = key_bits<W>(key_load<W>(keys + i * W), rbits, bb);
-  if (i > 0 && key_bits<W>(key_load<W>(keys + (i - 1) * W), rbits, bb) == b) return;
+  const uint64_t prev = i > 0 ? (uint64_t)key_bits<W>(key_load<W>(keys + (i - 1) * W), rbits, bb) : ~0ull;
+  if (i > 0 && prev == b) return;
+  const uint64_t lastb = key_bits<W>(key_load<W>(keys + (nS - 1) * W), rbits, bb);
+  const uint64_t z1 = b == lastb ? nb : b;
+  for (uint64_t e = prev + 1; e < z1; ++e)
+    if (e != b)
+      for (int x = 0; x < WS_SLOTS * SWD; ++x) tab[e * (WS_SLOTS * SWD) + x] = 0;
   const int fw = rbits >> 6, fs = rbits & 63;
   uint64_t* out = tab + (uint64_t)b * (WS_SLOTS * SWD);
   bool more = true;  // key i + j is still in bucket b
@@ -938,15 +945,24 @@ inline PackedBits packed_shape(int kb, uint64_t nS) {
 
 // One thread per solid key; the first key of each bucket (the sorted set
 // holds a bucket's keys together) writes the whole bucket, shifting its
-// slots in from the last to the first.  Empty buckets stay as the table
-// was cleared.
+// slots in from the last to the first, and clears the empty buckets between
+// the previous key's bucket and its own (the last one also those after it),
+// so every bucket is written exactly once.
 template <int BWN>
 __global__ void k_bucket_fill_bits(const uint64_t* __restrict__ keys, uint64_t nS, const uint8_t* __restrict__ sfl,
-                                   uint64_t* __restrict__ tab, PackedBits p) {
+                                   uint64_t* __restrict__ tab, uint64_t nb, PackedBits p) {
   const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (i >= nS) return;
   const uint64_t b = p.rbits ? keys[i] >> p.rbits : keys[i];
-  if (i > 0 && (p.rbits ? keys[i - 1] >> p.rbits : keys[i - 1]) == b) return;
+  const uint64_t prev = i > 0 ? (p.rbits ? keys[i - 1] >> p.rbits : keys[i - 1]) : ~0ull;
+  if (i > 0 && prev == b) return;
+  const uint64_t lastb = p.rbits ? keys[nS - 1] >> p.rbits : keys[nS - 1];
+  const uint64_t z1 = b == lastb ? nb : b;
+  for (uint64_t e = prev + 1; e < z1; ++e)
+    if (e != b) {
+#pragma unroll
+      for (int x = 0; x < BWN; ++x) tab[e * BWN + x] = 0;
+    }
   uint64_t n = 1;  // keys of bucket b from i on, counted up to slots + 1
   while (n <= (uint64_t)p.slots && i + n < nS && (p.rbits ? keys[i + n] >> p.rbits : keys[i + n]) == b) ++n;
   const uint64_t m = n < (uint64_t)p.slots ? n : (uint64_t)p.slots;
@@ -1595,7 +1611,7 @@ struct Counter {
     if constexpr (SWD <= W) {
       {
         Stage st_(c, "bucket_fill", nS * (8 * W + 1) + nb * WS_SLOTS * SWD * 8);
-        k_wslot_fill<W, SWD><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(skeys, nS, sfl, btab, ws.bb, ws.rbits);
+        k_wslot_fill<W, SWD><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(skeys, nS, sfl, btab, nb, ws.bb, ws.rbits);
         c.check_launch("bucket_fill");
       }
       // each probe reads its bucket of 4 slots
@@ -1812,14 +1828,13 @@ struct Counter {
         const PackedBits pk = packed_shape(kb, nS);
         const uint64_t nb = 1ull << pk.bb;
         DBuf<uint64_t> btab = c.buf<uint64_t>(nb * pk.bwn);
-        fill<uint64_t>(btab.get(), nb * pk.bwn, 0, c);
         VLOG("mercy table: 2^%d buckets of %d words, %d slots", pk.bb, pk.bwn, pk.slots);
         {
           Stage st_(c, "bucket_fill", nS * 9 + nb * 8 * pk.bwn);
           if (pk.bwn == 2)
-            k_bucket_fill_bits<2><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(S.get(), nS, sfl.get(), btab.get(), pk);
+            k_bucket_fill_bits<2><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(S.get(), nS, sfl.get(), btab.get(), nb, pk);
           else
-            k_bucket_fill_bits<4><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(S.get(), nS, sfl.get(), btab.get(), pk);
+            k_bucket_fill_bits<4><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(S.get(), nS, sfl.get(), btab.get(), nb, pk);
           c.check_launch("bucket_fill");
         }
         {
@@ -1838,7 +1853,6 @@ struct Counter {
         const WordSlots ws = word_slots_shape(kb, W, nS);
         const uint64_t nb = 1ull << ws.bb;
         DBuf<uint64_t> btab = c.buf<uint64_t>(nb * WS_SLOTS * ws.swd);
-        fill<uint64_t>(btab.get(), nb * WS_SLOTS * ws.swd, 0, c);
         VLOG("mercy table: 2^%d buckets of %d x %d words", ws.bb, WS_SLOTS, ws.swd);
         window_flags_ws(ea, ws, sv, S.get(), sfl.get(), btab.get(), nb, NW, words, wf.get(), nS);
       }
