@@ -1841,7 +1841,7 @@ struct Counter {
           // each probe reads its bucket
           Stage st_(c, "window_flags", 3 * words * 8 + NW + NW * 8 * pk.bwn);
           if (pk.bwn == 2)
-            k_window_flags_bits<2, 8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), pk, sv, sfl.get(),
+            k_window_flags_bits<2, 4><<<grid1(ceil_div(NW, 4)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), pk, sv, sfl.get(),
                                                                                    wf.get());
           else
             k_window_flags_bits<4, 8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), pk, sv, sfl.get(),
