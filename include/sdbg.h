@@ -167,6 +167,10 @@ int sdbg_batch_run(const sdbg_reads *sets, uint64_t n_sets, const sdbg_params *p
  *                   0 or 1 (0)
  *   first_bits      key bits of the first cut, which is taken straight from
  *                   the packed reads, 4..8 (6)
+ *   mercy_shift     the mercy-kmer lookup table gets 2^mercy_shift times
+ *                   fewer buckets than it is sized for, 0..8 (0); above 0
+ *                   more lookups take the slower overfull-bucket path, which
+ *                   is what this setting is for (testing that path)
  * (The autotuner varies the first four.) */
 typedef struct sdbg_tune {
   uint32_t digit_bits;
@@ -174,7 +178,8 @@ typedef struct sdbg_tune {
   uint32_t leaf_wg_per_cu;
   uint32_t leaf_cap_shift;
   uint32_t first_bits;
-  uint32_t reserved[3];
+  uint32_t mercy_shift;
+  uint32_t reserved[2];
 } sdbg_tune;
 
 int sdbg_tune_get(sdbg_tune *t);

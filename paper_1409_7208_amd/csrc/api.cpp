@@ -419,7 +419,8 @@ int sdbg_tune_get(sdbg_tune* t) {
     t->leaf_wg_per_cu = (uint32_t)x.leaf_wg_per_cu;
     t->leaf_cap_shift = (uint32_t)x.leaf_cap_shift;
     t->first_bits = (uint32_t)x.first_bits;
-    t->reserved[0] = t->reserved[1] = t->reserved[2] = 0;
+    t->mercy_shift = (uint32_t)x.mercy_shift;
+    t->reserved[0] = t->reserved[1] = 0;
     return SDBG_OK;
   });
 }
@@ -433,6 +434,7 @@ int sdbg_tune_set(const sdbg_tune* t) {
       x.leaf_wg_per_cu = (int)t->leaf_wg_per_cu;
       x.leaf_cap_shift = (int)t->leaf_cap_shift;
       x.first_bits = (int)t->first_bits;
+      x.mercy_shift = (int)t->mercy_shift;
     }
     sdbg::set_sort_tune(x);
     return SDBG_OK;

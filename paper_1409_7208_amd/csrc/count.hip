@@ -823,10 +823,12 @@ struct WordSlots {
   int bb, rbits, swd;
 };
 
-inline WordSlots word_slots_shape(int kb, int W, uint64_t nS) {
+inline WordSlots word_slots_shape(int kb, int W, uint64_t nS, int shrink) {
   WordSlots p{};
-  p.bb = std::max(1, kb + 5 - 64 * W);  // the slot must fit W words
+  const int bmin = std::max(1, kb + 5 - 64 * W);  // the slot must fit W words
+  p.bb = bmin;
   while (p.bb < 30 && p.bb < kb && ((uint64_t)WS_SLOTS << p.bb) < 2 * nS) ++p.bb;
+  p.bb = std::max(bmin, p.bb - shrink);
   p.rbits = kb - p.bb;
   p.swd = (p.rbits + 5 + 63) / 64;
   return p;
@@ -916,138 +918,375 @@ DEV uint8_t wslot_flags(const uint64_t* __restrict__ tab, const SortedView& S, c
   return f;
 }
 
-// One-word keys use a denser table: buckets of BWN = 2 words (one 16-byte
-// load per probe) when three or more slots fit, else 4 words.  Slot j of a
-// bucket holds bits [j*sb, (j+1)*sb) of the bucket read as one little-endian
-// integer: the key's low rbits bits (its top bb bits are the bucket number)
-// and 4 flag bits (valid | dead-end flags); the bucket's top bit marks a
-// bucket with more keys than slots, whose keys are then searched in the
-// sorted set.
-struct PackedBits {
-  int bb, rbits, sb, slots, bwn;
+// One-word keys (k <= 31) use a table of k-mer NODES instead of edges.  A
+// node's entry holds its in-set (bit c: the solid edge c + node exists) and
+// its out-set (bit 4 + c: node + c exists), so one lookup answers both
+// windows of a read that meet at that node, and the dead-end flags of a
+// window are empty sets of its end nodes (no pass over the solid set for
+// them).  Node key NK (2k bits) of the k-mer b[0..k-1]: the digits b[k-2],
+// ..., b[0], b[k-1], i.e. key_from_fwd of its forward packing.  For an edge
+// key x (digits e[k-1], ..., e[0], e[k]):
+//   source node e[0..k-1]: NK = (x mod 4^k) with its low digit replaced by
+//                          e[k-1] = x div 4^k; contributes out-bit e[k];
+//   target node e[1..k]:   NK = ((x div 16) * 4) + e[k]; contributes in-bit
+//                          e[0] = (x div 4) mod 4.
+// Bucket = NK >> rbits, BW 64-bit words: slot j holds bits [j*sb, (j+1)*sb)
+// of the bucket read as one little-endian integer, (NK mod 2^rbits) | sets
+// << rbits, nodes in increasing NK, sb = rbits + 8; the bucket's top bit
+// marks a bucket with more nodes than slots.  The nodes that did not fit
+// their bucket go to the spill line of their block of 2^s buckets (4 words,
+// slots of NK mod 2^(rbits+s) | sets << (rbits+s), increasing NK); its top
+// bit marks a block with more such nodes than the line holds, whose other
+// nodes are then looked up in the sorted set.  Stored nodes have a
+// non-empty set byte; absent nodes have none.
+constexpr int NODE_BLOCK_SHIFT = 6;  // buckets per fill workgroup and spill line: one per thread
+constexpr int NODE_FILL_THREADS = 1 << NODE_BLOCK_SHIFT;
+constexpr int SPILL_WORDS = 4;
+constexpr int NODE_BW = 2;           // bucket words
+constexpr int NODE_LOAD = 2;         // slots per solid edge
+
+struct NodeShape {
+  int nkb, bw, bb, rbits, sb, slots;
+  int s, ssb, sslots;  // block shift; spill slot bits and slots
 };
 
-inline PackedBits packed_shape_bw(int kb, uint64_t nS, int bwn) {
-  PackedBits p{};
-  p.bwn = bwn;
-  for (p.bb = std::max(1, kb - 59);; ++p.bb) {
-    p.rbits = std::max(0, kb - p.bb);
-    p.sb = p.rbits + 4;
-    p.slots = (64 * bwn - 1) / p.sb;
-    if (p.bb >= 30 || p.bb >= kb || ((uint64_t)p.slots << p.bb) >= 2 * nS) return p;
+// Smallest table with slots * buckets >= load * nS (at most 2 nS nodes).
+inline NodeShape node_shape(int k, uint64_t nS, int shrink, int bw, int load) {
+  NodeShape p{};
+  p.nkb = 2 * k;
+  p.bw = bw;
+  const int bmin = std::max(1, p.nkb + NODE_BLOCK_SHIFT + 8 - 63);  // spill slots fit a word
+  auto set = [&](int bb) {
+    p.bb = bb;
+    p.rbits = p.nkb - bb;
+    p.sb = p.rbits + 8;
+    p.slots = (64 * bw - 1) / p.sb;
+    p.s = std::min(NODE_BLOCK_SHIFT, bb);
+    p.ssb = p.rbits + p.s + 8;
+    p.sslots = (64 * SPILL_WORDS - 1) / p.ssb;
+  };
+  for (int bb = bmin;; ++bb) {
+    set(bb);
+    if (bb >= 30 || bb >= p.nkb - 2 || ((uint64_t)p.slots << bb) >= (uint64_t)load * nS) break;
   }
+  if (shrink) set(std::max(bmin, p.bb - shrink));
+  return p;
 }
 
-inline PackedBits packed_shape(int kb, uint64_t nS) {
-  const PackedBits p = packed_shape_bw(kb, nS, 2);
-  return p.slots >= 3 ? p : packed_shape_bw(kb, nS, 4);
+struct NodeTab {
+  const uint64_t* tab;
+  const uint64_t* spill;
+  SortedView S;  // the solid edge set
+  int nkb, bw, rbits, sb, slots, s, ssb, sslots;
+};
+
+DEV uint64_t node_of_target(uint64_t x) { return ((x >> 4) << 2) | (x & 3); }
+DEV uint64_t node_of_source(uint64_t x, int nkb) {
+  return (x & (~0ull >> (64 - nkb)) & ~3ull) | (x >> nkb);
 }
 
-// One thread per solid key; the first key of each bucket (the sorted set
-// holds a bucket's keys together) writes the whole bucket, shifting its
-// slots in from the last to the first, and clears the empty buckets between
-// the previous key's bucket and its own (the last one also those after it),
-// so every bucket is written exactly once.
-template <int BWN>
-__global__ void k_bucket_fill_bits(const uint64_t* __restrict__ keys, uint64_t nS, const uint8_t* __restrict__ sfl,
-                                   uint64_t* __restrict__ tab, uint64_t nb, PackedBits p) {
-  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (i >= nS) return;
-  const uint64_t b = p.rbits ? keys[i] >> p.rbits : keys[i];
-  const uint64_t prev = i > 0 ? (p.rbits ? keys[i - 1] >> p.rbits : keys[i - 1]) : ~0ull;
-  if (i > 0 && prev == b) return;
-  const uint64_t lastb = p.rbits ? keys[nS - 1] >> p.rbits : keys[nS - 1];
-  const uint64_t z1 = b == lastb ? nb : b;
-  for (uint64_t e = prev + 1; e < z1; ++e)
-    if (e != b) {
-#pragma unroll
-      for (int x = 0; x < BWN; ++x) tab[e * BWN + x] = 0;
-    }
-  uint64_t n = 1;  // keys of bucket b from i on, counted up to slots + 1
-  while (n <= (uint64_t)p.slots && i + n < nS && (p.rbits ? keys[i + n] >> p.rbits : keys[i + n]) == b) ++n;
-  const uint64_t m = n < (uint64_t)p.slots ? n : (uint64_t)p.slots;
-  const uint64_t rmask = p.rbits ? (~0ull >> (64 - p.rbits)) : 0;
-  const int sb = p.sb;
-  uint64_t w[BWN];
-#pragma unroll
-  for (int x = 0; x < BWN; ++x) w[x] = 0;
-  for (uint64_t j = m; j-- > 0;) {
-    const uint64_t slot = (keys[i + j] & rmask) | ((uint64_t)(8u | sfl[i + j]) << p.rbits);
-#pragma unroll
-    for (int x = BWN - 1; x > 0; --x) w[x] = (w[x] << sb) | (w[x - 1] >> (64 - sb));
-    w[0] = (w[0] << sb) | slot;
+// Sets of node nk from the sorted solid set: out-edges are the keys F*4 + c
+// (F = forward packing of the node), in-edges the keys (c + 4*F[0..k-2])*4
+// + F[k-1], which lie among the keys sharing x div 16.
+DEV uint32_t node_sets_sorted(const SortedView& S, uint64_t nk, int nkb) {
+  const uint64_t F = (nk >> 2) | ((nk & 3) << (nkb - 2));
+  uint32_t f = 0;
+  Key<1> q;
+  q.w[0] = F << 2;
+  for (uint64_t i = sv_lower<1>(S, q); i < S.n; ++i) {
+    const uint64_t x = S.keys[i];
+    if ((x >> 2) != F) break;
+    f |= 16u << (x & 3);
   }
-  if (n > (uint64_t)p.slots) w[BWN - 1] |= 1ull << 63;
-  uint64_t* out = tab + b * BWN;
-#pragma unroll
-  for (int x = 0; x < BWN; ++x) out[x] = w[x];
-}
-
-template <int BWN>
-DEV uint8_t bucket_flags_bits(const uint64_t* __restrict__ tab, const SortedView& S, const uint8_t* __restrict__ sfl,
-                              uint64_t q, const PackedBits& p) {
-  const uint64_t b = p.rbits ? q >> p.rbits : q;
-  const uint4* v = reinterpret_cast<const uint4*>(tab + b * BWN);
-  uint64_t w[BWN];
-#pragma unroll
-  for (int i = 0; i < BWN / 2; ++i) {
-    const uint4 x = v[i];
-    w[2 * i] = x.x | ((uint64_t)x.y << 32);
-    w[2 * i + 1] = x.z | ((uint64_t)x.w << 32);
-  }
-  const bool ovf = (w[BWN - 1] >> 63) != 0;
-  const uint64_t rmask = p.rbits ? (~0ull >> (64 - p.rbits)) : 0;
-  const uint64_t smask = ~0ull >> (64 - p.sb);
-  const uint64_t qr = q & rmask;
-  const int sb = p.sb;
-  uint8_t f = 0;
-  for (int j = 0; j < p.slots; ++j) {
-    const uint64_t x = w[0] & smask;
-    const uint32_t fl = (uint32_t)(x >> p.rbits);
-    if ((fl & 8u) && (x & rmask) == qr) f = (uint8_t)(fl & 7u);
-#pragma unroll
-    for (int i = 0; i < BWN - 1; ++i) w[i] = (w[i] >> sb) | (w[i + 1] << (64 - sb));
-    w[BWN - 1] >>= sb;
-  }
-  if (!f && ovf) {
-    uint64_t ix;
-    Key<1> k1;
-    k1.w[0] = q;
-    f = sv_find<1>(S, k1, &ix) ? sfl[ix] : 0;
+  const uint64_t last = F >> (nkb - 2);
+  const uint64_t base = ((F & (~0ull >> (66 - nkb))) << 4) | last;
+  q.w[0] = base;
+  for (uint64_t i = sv_lower<1>(S, q); i < S.n; ++i) {
+    const uint64_t x = S.keys[i];
+    if ((x >> 4) != (base >> 4)) break;
+    if ((x & 3) == last) f |= 1u << ((x >> 2) & 3);
   }
   return f;
 }
 
-template <int BWN, int IPT>
-__global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags_bits(ExArgs a, const uint64_t* __restrict__ tab,
-                                                                  PackedBits p, SortedView S,
-                                                                  const uint8_t* __restrict__ sfl,
-                                                                  uint8_t* __restrict__ wf) {
+// Sets stored for q in a packed line of BW words (slots of sb bits: low
+// rbits bits of the node key, then its sets); *ovf = the line's top bit.
+template <int BW>
+DEV uint32_t line_sets(const uint64_t* line, uint64_t q, int rbits, int sb, int slots, bool* ovf) {
+  const uint4* v = reinterpret_cast<const uint4*>(line);
+  uint64_t w[BW];
+#pragma unroll
+  for (int i = 0; i < BW / 2; ++i) {
+    const uint4 x = v[i];
+    w[2 * i] = x.x | ((uint64_t)x.y << 32);
+    w[2 * i + 1] = x.z | ((uint64_t)x.w << 32);
+  }
+  *ovf = (w[BW - 1] >> 63) != 0;
+  const uint64_t rmask = ~0ull >> (64 - rbits);
+  const uint64_t smask = ~0ull >> (64 - sb);
+  const uint64_t qr = q & rmask;
+  uint32_t f = 0;
+  for (int j = 0; j < slots; ++j) {
+    const uint64_t x = w[0] & smask;
+    const uint32_t sets = (uint32_t)(x >> rbits);
+    if (sets && (x & rmask) == qr) f = sets;
+#pragma unroll
+    for (int i = 0; i < BW - 1; ++i) w[i] = (w[i] >> sb) | (w[i + 1] << (64 - sb));
+    w[BW - 1] >>= sb;
+  }
+  return f;
+}
+
+template <int BW>
+DEV uint32_t node_sets_bw(const NodeTab& t, uint64_t nk) {
+  bool ovf;
+  uint32_t f = line_sets<BW>(t.tab + (nk >> t.rbits) * BW, nk, t.rbits, t.sb, t.slots, &ovf);
+  if (!f && ovf) {
+    f = line_sets<SPILL_WORDS>(t.spill + (nk >> (t.rbits + t.s)) * SPILL_WORDS, nk, t.rbits + t.s, t.ssb, t.sslots,
+                               &ovf);
+    if (!f && ovf) f = node_sets_sorted(t.S, nk, t.nkb);
+  }
+  return f;
+}
+
+DEV uint32_t node_sets(const NodeTab& t, uint64_t nk) {
+  return t.bw == 4 ? node_sets_bw<4>(t, nk) : node_sets_bw<2>(t, nk);
+}
+
+// First index of S whose key is >= key, for a key whose bits below its top
+// p bits are zero: straight from the directory when p <= its bits.
+DEV uint64_t sv_prefix_lower(const SortedView& S, uint64_t key, int p) {
+  if (p <= S.db) return S.dir[key >> (S.kbits - S.db)];
+  Key<1> q;
+  q.w[0] = key;
+  return sv_lower<1>(S, q);
+}
+
+// Sets a packed slot into words w at bit position pos.
+template <int BW>
+DEV void put_slot(uint64_t* w, uint64_t slot, int pos, int sb) {
+  const int wd = pos >> 6, off = pos & 63;
+#pragma unroll
+  for (int x = 0; x < BW; ++x) {
+    if (x == wd) w[x] |= slot << off;
+    if (x == wd + 1 && off + sb > 64) w[x] |= slot >> (64 - off);
+  }
+}
+
+// Table fill: persistent one-wave workgroups, each taking blocks of 2^s
+// buckets in turn (one-wave workgroups keep many blocks' dependent loads in
+// flight per compute unit; the next block's stretch bounds are loaded while
+// the current one is processed).  A block's nodes come from five stretches
+// of the sorted solid set: the edges whose target node falls in the block
+// (keys sharing their top bb - s bits), and for each top digit c the edges
+// whose source node falls in it (keys c, then the block's bb - s bits).
+// Each contribution (node key, set bit) claims its node's entry in a list
+// of NODE_LIST entries per bucket in LDS (compare-and-swap on the key, then
+// OR of the bit); then one thread per bucket sorts its list by node key
+// (a sorting network), packs the first slots nodes into the bucket and
+// hands the rest to the block's spill line in bucket order.  A bucket with
+// more nodes than its list marks itself and the spill line overfull.  The
+// barriers order LDS only: no thread reads another's global data.
+constexpr int NODE_LIST = 8;
+
+DEV uint64_t node_stretch_bound(const SortedView& S, const NodeShape& p, uint64_t B, int r) {
+  const uint64_t nblk = 1ull << (p.bb - p.s);
+  const int t = r >> 1;
+  const uint64_t v = B + (r & 1);
+  if (v == nblk && (t == 0 || t == 4)) return S.n;  // past the last key (the bound would not fit the key width)
+  if (t == 0)  // v << (rbits + 2 + s) with a shift of 64 only when v = 0 (one block)
+    return sv_prefix_lower(S, v ? v << (p.rbits + 2 + p.s) : 0, p.bb - p.s);
+  return sv_prefix_lower(S, ((uint64_t)(t - 1) << p.nkb) + (v << (p.rbits + p.s)), p.bb - p.s + 2);
+}
+
+template <int BW>
+__global__ __launch_bounds__(NODE_FILL_THREADS) void k_node_fill(SortedView S, NodeShape p,
+                                                                 uint64_t* __restrict__ tab,
+                                                                 uint64_t* __restrict__ spill) {
+  constexpr int NT = NODE_FILL_THREADS;
+  constexpr uint64_t EMPTY = ~0ull;
+  __shared__ unsigned long long lk[NT * NODE_LIST];
+  __shared__ uint32_t lf[NT * NODE_LIST];
+  __shared__ uint32_t lost[NT];
+  __shared__ uint64_t rg[10];
+  __shared__ unsigned long long sw[SPILL_WORDS];
+  const int s = p.s;
+  const uint64_t nblk = 1ull << (p.bb - s);
+  const uint32_t nbk = 1u << s;
+  const uint32_t lmask = nbk - 1;
+  const uint64_t kmask = ~0ull >> (64 - (p.rbits + s));  // node key below the block
+  const uint32_t j = threadIdx.x;
+  uint64_t nxt = 0;
+  if (j < 10 && blockIdx.x < nblk) nxt = node_stretch_bound(S, p, blockIdx.x, j);
+  for (uint64_t B = blockIdx.x; B < nblk; B += gridDim.x) {
+    if (j < 10) rg[j] = nxt;
+#pragma unroll
+    for (int r = 0; r < NODE_LIST; ++r) {
+      lk[r * NT + j] = EMPTY;
+      lf[r * NT + j] = 0;
+    }
+    lost[j] = 0;
+    if (j < SPILL_WORDS) sw[j] = 0;
+    lds_barrier();
+    uint64_t lo[5], base[6];
+    base[0] = 0;
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+      lo[t] = rg[2 * t];
+      base[t + 1] = base[t] + (rg[2 * t + 1] - rg[2 * t]);
+    }
+    const uint64_t total = base[5];
+    if (j < 10 && B + gridDim.x < nblk) nxt = node_stretch_bound(S, p, B + gridDim.x, j);
+    // contributions i = 0 .. total-1 over the five stretches; each thread
+    // loads four before it inserts them
+    for (uint64_t i0 = 0; i0 < total; i0 += 4 * NT) {
+      uint64_t x[4];
+      uint32_t tt[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t i = i0 + q * NT + j;
+        uint64_t src = 0;
+        tt[q] = 5;
+#pragma unroll
+        for (int t = 0; t < 5; ++t)
+          if (i >= base[t] && i < base[t + 1]) {
+            src = lo[t] + (i - base[t]);
+            tt[q] = t;
+          }
+        x[q] = tt[q] < 5 ? S.keys[src] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (tt[q] == 5) continue;
+        const uint64_t nk = tt[q] == 0 ? node_of_target(x[q]) : node_of_source(x[q], p.nkb);
+        const uint32_t bit = tt[q] == 0 ? 1u << ((x[q] >> 2) & 3) : 16u << (x[q] & 3);
+        const uint32_t b = (uint32_t)(nk >> p.rbits) & lmask;
+        const unsigned long long key = (unsigned long long)(nk & kmask);
+        bool done = false;
+        for (int r = 0; r < NODE_LIST && !done; ++r) {
+          const unsigned long long old = atomicCAS(&lk[r * NT + b], (unsigned long long)EMPTY, key);
+          if (old == EMPTY || old == key) {
+            atomicOr(&lf[r * NT + b], bit);
+            done = true;
+          }
+        }
+        if (!done) lost[b] = 1;
+      }
+    }
+    lds_barrier();
+    // thread j: bucket j's nodes, sorted by key (empty entries last)
+    uint64_t nk[NODE_LIST];
+    uint32_t fs[NODE_LIST];
+#pragma unroll
+    for (int r = 0; r < NODE_LIST; ++r) {
+      nk[r] = lk[r * NT + j];
+      fs[r] = lf[r * NT + j];
+    }
+#pragma unroll
+    for (int u = 0; u < NODE_LIST; ++u)
+#pragma unroll
+      for (int r = (u & 1); r + 1 < NODE_LIST; r += 2)
+        if (nk[r + 1] < nk[r]) {
+          const uint64_t tk = nk[r];
+          nk[r] = nk[r + 1];
+          nk[r + 1] = tk;
+          const uint32_t tf = fs[r];
+          fs[r] = fs[r + 1];
+          fs[r + 1] = tf;
+        }
+    uint32_t nn = 0;
+#pragma unroll
+    for (int r = 0; r < NODE_LIST; ++r) nn += nk[r] != EMPTY;
+    const bool lst = j < nbk && lost[j] != 0;
+    const uint32_t nsp = nn > (uint32_t)p.slots ? nn - (uint32_t)p.slots : 0;
+    const uint32_t incl = wave_incl_scan<uint32_t>(nsp);
+    const uint32_t total_sp = __shfl(incl, NT - 1, NT);
+    const bool any_lost = __any(lst);
+    uint32_t spos = incl - nsp;  // this bucket's first spill slot
+    const uint64_t rmask = ~0ull >> (64 - p.rbits);
+    uint64_t w[BW];
+#pragma unroll
+    for (int x = 0; x < BW; ++x) w[x] = 0;
+#pragma unroll
+    for (int r = 0; r < NODE_LIST; ++r) {
+      if (nk[r] == EMPTY) continue;
+      if (r < p.slots) {
+        put_slot<BW>(w, (nk[r] & rmask) | ((uint64_t)fs[r] << p.rbits), r * p.sb, p.sb);
+      } else if (spos < (uint32_t)p.sslots) {
+        const uint64_t slot = nk[r] | ((uint64_t)fs[r] << (p.rbits + s));
+        const int pos = (int)spos * p.ssb, wd = pos >> 6, off = pos & 63;
+        atomicOr(&sw[wd], (unsigned long long)(slot << off));
+        if (off + p.ssb > 64) atomicOr(&sw[wd + 1], (unsigned long long)(slot >> (64 - off)));
+        ++spos;
+      }
+    }
+    if (nn > (uint32_t)p.slots || lst) w[BW - 1] |= 1ull << 63;
+    if (j < nbk) {
+      uint64_t* out = tab + (uint64_t)BW * ((B << s) + j);
+#pragma unroll
+      for (int x = 0; x < BW; ++x) out[x] = w[x];
+    }
+    lds_barrier();
+    if (j < SPILL_WORDS)
+      spill[(uint64_t)SPILL_WORDS * B + j] =
+          sw[j] | (j == SPILL_WORDS - 1 && (any_lost || total_sp > (uint32_t)p.sslots) ? 1ull << 63 : 0);
+    lds_barrier();  // LDS is reused by the next block
+  }
+}
+
+// Per forward-strand window: 0x80 if it holds a non-ACGT base, else its
+// flags from one node: a window at an even index looks up its target node
+// (which gives its solidity and its no-out flag; no-in is left unknown,
+// 0x08), one at an odd index its source node (solidity and no-in; no-out
+// unknown, 0x10).  The windows 2m, 2m+1 of one read share that node, so a
+// thread's IPT windows (IPT even) need about IPT/2 lookups.  Non-solid
+// windows get 0.
+DEV uint8_t node_window_flag(uint64_t x, uint32_t sets, bool odd) {
+  if (!odd) {
+    if (!((sets >> ((x >> 2) & 3)) & 1)) return 0;
+    return (uint8_t)(1 | ((sets >> 4) == 0 ? 2 : 0) | 0x08);
+  }
+  if (!((sets >> (4 + (x & 3))) & 1)) return 0;
+  return (uint8_t)(1 | ((sets & 15) == 0 ? 4 : 0) | 0x10);
+}
+
+template <int BW, int IPT>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_node_window_flags(ExArgs a, NodeTab t, uint8_t* __restrict__ wf) {
+  static_assert(IPT % 2 == 0, "windows come in pairs");
   const uint64_t g0 = ((uint64_t)blockIdx.x * SDBG_BLOCK + threadIdx.x) * IPT;
   if (g0 >= a.NW) return;
   WinIter it;
   it.init(a, g0);
-  uint64_t key[IPT];
+  uint64_t key[IPT], nk[IPT];
   bool ok[IPT];
 #pragma unroll
   for (int q = 0; q < IPT; ++q) {
     ok[q] = false;
     key[q] = 0;
+    nk[q] = 0;
     if (g0 + q < a.NW) {
       const uint64_t j = it.pos();
       if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
         ok[q] = true;
         key[q] = key_from_fwd<1>(stream_bits<1>(a.packed, 2 * j, a.kb), a.kb).w[0];
+        nk[q] = (q & 1) ? node_of_source(key[q], t.nkb) : node_of_target(key[q]);
       }
       it.next(a);
     }
   }
-  uint8_t f[IPT];
+  bool dup[IPT];
+  uint32_t sets[IPT];
 #pragma unroll
-  for (int q = 0; q < IPT; ++q) f[q] = ok[q] ? bucket_flags_bits<BWN>(tab, S, sfl, key[q], p) : (uint8_t)0x80;
+  for (int q = 0; q < IPT; ++q) {
+    dup[q] = (q & 1) && ok[q] && ok[q - 1] && nk[q] == nk[q - 1];
+    sets[q] = ok[q] && !dup[q] ? node_sets_bw<BW>(t, nk[q]) : 0u;
+  }
+#pragma unroll
+  for (int q = 1; q < IPT; q += 2)
+    if (dup[q]) sets[q] = sets[q - 1];
 #pragma unroll
   for (int q = 0; q < IPT; ++q)
-    if (g0 + q < a.NW) wf[g0 + q] = f[q];
+    if (g0 + q < a.NW) wf[g0 + q] = ok[q] ? node_window_flag(key[q], sets[q], q & 1) : (uint8_t)0x80;
 }
 
 // Per forward-strand window: 0x80 if it holds a non-ACGT base, else the
@@ -1095,10 +1334,11 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags(ExArgs a, const uin
 // incoming solid edge: windows p+1..q-1 and their reverse complements are
 // mercy edges.  Pass 0 counts keys per read, pass 1 writes them (only for
 // reads with a count).  Flags are read eight at a time (wf is padded to a
-// whole word).
+// whole word).  A flag the node lookups left unknown (one-word keys: 0x10
+// no-out, 0x08 no-in) is looked up in the node table when a pair needs it.
 template <int W>
 __global__ void k_mercy(ExArgs a, const uint8_t* __restrict__ wf, int pass, uint64_t* __restrict__ mcount,
-                        const uint64_t* __restrict__ mpos, uint64_t* __restrict__ cand) {
+                        const uint64_t* __restrict__ mpos, uint64_t* __restrict__ cand, NodeTab nt) {
   uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (r >= a.n_reads) return;
   if (pass && mcount[r] == 0) return;
@@ -1106,7 +1346,7 @@ __global__ void k_mercy(ExArgs a, const uint8_t* __restrict__ wf, int pass, uint
   const uint64_t rs = a.offsets[r];
   uint64_t out = pass ? mpos[r] : 0, c = 0;
   int64_t p = -1;
-  bool p_noout = false;
+  uint8_t fp = 0;
   const uint64_t* wf64 = reinterpret_cast<const uint64_t*>(wf);
   uint64_t wi = g0 >> 3;
   uint64_t word = g0 < g1 ? wf64[wi] >> (8 * (g0 & 7)) : 0;
@@ -1125,7 +1365,22 @@ __global__ void k_mercy(ExArgs a, const uint8_t* __restrict__ wf, int pass, uint
     }
     if (!(f & 1)) continue;
     const int64_t q = (int64_t)(g - g0);
-    if (p >= 0 && q - p >= 2 && p_noout && (f & 4)) {
+    bool fire = false;
+    if (p >= 0 && q - p >= 2) {
+      bool noout = (fp & 2) != 0, noin = (f & 4) != 0;
+      if constexpr (W == 1) {
+        if (fp & 0x10) {
+          const uint64_t x = key_from_fwd<1>(stream_bits<1>(a.packed, 2 * (rs + (uint64_t)p), a.kb), a.kb).w[0];
+          noout = (node_sets(nt, node_of_target(x)) >> 4) == 0;
+        }
+        if (noout && (f & 0x08)) {
+          const uint64_t x = key_from_fwd<1>(stream_bits<1>(a.packed, 2 * (rs + (uint64_t)q), a.kb), a.kb).w[0];
+          noin = (node_sets(nt, node_of_source(x, nt.nkb)) & 15) == 0;
+        }
+      }
+      fire = noout && noin;
+    }
+    if (fire) {
       if (!pass) {
         c += 2 * (uint64_t)(q - p - 1);
       } else {
@@ -1139,7 +1394,7 @@ __global__ void k_mercy(ExArgs a, const uint8_t* __restrict__ wf, int pass, uint
       }
     }
     p = q;
-    p_noout = (f & 2) != 0;
+    fp = f;
   }
   if (!pass) mcount[r] = c;
 }
@@ -1270,6 +1525,19 @@ int cu_count() {
       n = 256;
   }
   return n;
+}
+
+// Resident grid of the persistent node-table fill.
+template <int BW>
+unsigned node_fill_grid(uint64_t nblk) {
+  static int resident = 0;
+  if (!resident) {
+    int r = 0;
+    SDBG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, reinterpret_cast<const void*>(&k_node_fill<BW>),
+                                                          NODE_FILL_THREADS, 0));
+    resident = std::max(1, std::min(r, 32));
+  }
+  return (unsigned)std::min<uint64_t>(nblk, (uint64_t)cu_count() * resident);
 }
 
 struct SegList {
@@ -1816,59 +2084,64 @@ struct Counter {
     if (P.mercy && P.d >= 2 && nS > 0) {
       DBuf<uint64_t> sdir;
       SortedView sv = make_view(S.get(), nS, kb, sdir);
-      DBuf<uint8_t> sfl = c.buf<uint8_t>(nS);
-      {
-        Stage st_(c, "dead_ends", nS * (8 * W + 1));
-        k_dead_ends<W><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(sv, k, sfl.get());
-        c.check_launch("dead_ends");
-      }
+      DBuf<uint8_t> sfl;
       DBuf<uint8_t> wf = c.buf<uint8_t>(NW + 8);
+      DBuf<uint64_t> btab, spill;
+      NodeTab nt{};
       if constexpr (W == 1) {
-        // packed buckets, about slots/2 solid keys per bucket
-        const PackedBits pk = packed_shape(kb, nS);
-        const uint64_t nb = 1ull << pk.bb;
-        DBuf<uint64_t> btab = c.buf<uint64_t>(nb * pk.bwn);
-        VLOG("mercy table: 2^%d buckets of %d words, %d slots", pk.bb, pk.bwn, pk.slots);
+        // node table, about slots/2 nodes per bucket
+        const NodeShape ns = node_shape(k, nS, tune.mercy_shift, NODE_BW, NODE_LOAD);
+        const uint64_t nb = 1ull << ns.bb, nblk = nb >> ns.s;
+        btab = c.buf<uint64_t>(ns.bw * nb);
+        spill = c.buf<uint64_t>(SPILL_WORDS * nblk);
+        nt = NodeTab{btab.get(), spill.get(), sv, ns.nkb, ns.bw, ns.rbits, ns.sb, ns.slots, ns.s, ns.ssb, ns.sslots};
+        VLOG("mercy node table: 2^%d buckets of %d words, %d slots of %d bits; spill lines of %d slots", ns.bb, ns.bw,
+             ns.slots, ns.sb, ns.sslots);
         {
-          Stage st_(c, "bucket_fill", nS * 9 + nb * 8 * pk.bwn);
-          if (pk.bwn == 2)
-            k_bucket_fill_bits<2><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(S.get(), nS, sfl.get(), btab.get(), nb, pk);
+          // every solid edge is staged twice (as an in-edge and as an out-edge)
+          Stage st_(c, "node_fill", nS * 16 + nb * 8 * ns.bw + nblk * 8 * SPILL_WORDS);
+          if (ns.bw == 4)
+            k_node_fill<4><<<node_fill_grid<4>(nblk), NODE_FILL_THREADS, 0, c.s>>>(sv, ns, btab.get(), spill.get());
           else
-            k_bucket_fill_bits<4><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(S.get(), nS, sfl.get(), btab.get(), nb, pk);
-          c.check_launch("bucket_fill");
+            k_node_fill<2><<<node_fill_grid<2>(nblk), NODE_FILL_THREADS, 0, c.s>>>(sv, ns, btab.get(), spill.get());
+          c.check_launch("node_fill");
         }
         {
-          // each probe reads its bucket
-          Stage st_(c, "window_flags", 3 * words * 8 + NW + NW * 8 * pk.bwn);
-          if (pk.bwn == 2)
-            k_window_flags_bits<2, 4><<<grid1(ceil_div(NW, 4)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), pk, sv, sfl.get(),
-                                                                                   wf.get());
+          // one bucket per pair of windows
+          Stage st_(c, "window_flags", 3 * words * 8 + NW + ceil_div(NW, 2) * 8 * ns.bw);
+          if (ns.bw == 4)
+            k_node_window_flags<4, 8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, nt, wf.get());
           else
-            k_window_flags_bits<4, 8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, btab.get(), pk, sv, sfl.get(),
-                                                                                   wf.get());
+            k_node_window_flags<2, 8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, nt, wf.get());
           c.check_launch("window_flags");
         }
       } else {
+        sfl = c.buf<uint8_t>(nS);
+        {
+          Stage st_(c, "dead_ends", nS * (8 * W + 1));
+          k_dead_ends<W><<<grid1(nS), SDBG_BLOCK, 0, c.s>>>(sv, k, sfl.get());
+          c.check_launch("dead_ends");
+        }
         // word-slot buckets, about 2 solid keys per bucket of 4
-        const WordSlots ws = word_slots_shape(kb, W, nS);
+        const WordSlots ws = word_slots_shape(kb, W, nS, tune.mercy_shift);
         const uint64_t nb = 1ull << ws.bb;
-        DBuf<uint64_t> btab = c.buf<uint64_t>(nb * WS_SLOTS * ws.swd);
+        btab = c.buf<uint64_t>(nb * WS_SLOTS * ws.swd);
         VLOG("mercy table: 2^%d buckets of %d x %d words", ws.bb, WS_SLOTS, ws.swd);
         window_flags_ws(ea, ws, sv, S.get(), sfl.get(), btab.get(), nb, NW, words, wf.get(), nS);
       }
       DBuf<uint64_t> mcount = c.buf<uint64_t>(R.n_reads), mpos = c.buf<uint64_t>(R.n_reads);
       {
         Stage st_(c, "mercy_count", NW + R.n_reads * 24);
-        k_mercy<W><<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(ea, wf.get(), 0, mcount.get(), nullptr, nullptr);
+        k_mercy<W><<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(ea, wf.get(), 0, mcount.get(), nullptr, nullptr, nt);
         c.check_launch("mercy_count");
       }
       scan_excl<uint64_t, uint64_t>(mcount.get(), mpos.get(), R.n_reads, tot.get(), c);
       const uint64_t NC = c.d2h_one(tot.get());
       VLOG("mercy: %llu solid edges, %llu candidate keys", (unsigned long long)nS, (unsigned long long)NC);
       if (const char* dd = std::getenv("SDBG_DUMP_DIR")) {  // debugging aid: intermediate arrays
-        std::vector<uint8_t> h1(nS), h2(NW);
+        std::vector<uint8_t> h1(sfl.get() ? nS : 0), h2(NW);
         std::vector<uint64_t> h3(R.n_reads);
-        c.d2h(h1.data(), sfl.get(), nS);
+        if (sfl.get()) c.d2h(h1.data(), sfl.get(), nS);
         c.d2h(h2.data(), wf.get(), NW);
         c.d2h(h3.data(), mcount.get(), R.n_reads);
         auto dump = [&](const char* name, const void* p, size_t bytes) {
@@ -1878,7 +2151,7 @@ struct Counter {
             std::fclose(f);
           }
         };
-        dump("sfl.bin", h1.data(), nS);
+        if (sfl.get()) dump("sfl.bin", h1.data(), nS);
         dump("wf.bin", h2.data(), NW);
         dump("mcount.bin", h3.data(), 8 * R.n_reads);
       }
@@ -1886,7 +2159,8 @@ struct Counter {
         DBuf<uint64_t> cand = c.buf<uint64_t>(NC * W);
         {
           Stage st_(c, "mercy_emit", NW + R.n_reads * 24 + NC * 8 * W);
-          k_mercy<W><<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(ea, wf.get(), 1, mcount.get(), mpos.get(), cand.get());
+          k_mercy<W><<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(ea, wf.get(), 1, mcount.get(), mpos.get(), cand.get(),
+                                                               nt);
           c.check_launch("mercy_emit");
         }
         wf.free();
@@ -2038,6 +2312,7 @@ void set_sort_tune(const SortTune& t) {
   SDBG_CHECK(t.leaf_wg_per_cu >= 1 && t.leaf_wg_per_cu <= 32, -1, "leaf_wg_per_cu must be in [1, 32]");
   SDBG_CHECK(t.leaf_cap_shift == 0 || t.leaf_cap_shift == 1, -1, "leaf_cap_shift must be 0 or 1");
   SDBG_CHECK(t.first_bits >= 4 && t.first_bits <= 8, -1, "first_bits must be in [4, 8]");
+  SDBG_CHECK(t.mercy_shift >= 0 && t.mercy_shift <= 8, -1, "mercy_shift must be in [0, 8]");
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune = t;
 }

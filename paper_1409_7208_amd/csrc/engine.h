@@ -82,6 +82,7 @@ struct SortTune {
   int leaf_wg_per_cu = 16;  // persistent leaf workgroups per compute unit (1..32)
   int leaf_cap_shift = 0;   // largest leaf = the width's default >> leaf_cap_shift (0 or 1)
   int first_bits = 6;       // key bits of the first cut, taken from the packed reads (4..8)
+  int mercy_shift = 0;      // mercy lookup table 2^mercy_shift times smaller than sized (0..8)
 };
 SortTune sort_tune();
 void set_sort_tune(const SortTune& t);

@@ -298,7 +298,8 @@ class _Tune(ctypes.Structure):
         ("leaf_wg_per_cu", ctypes.c_uint32),
         ("leaf_cap_shift", ctypes.c_uint32),
         ("first_bits", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 3),
+        ("mercy_shift", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 2),
     ]
 
 
@@ -325,7 +326,7 @@ def tune_get() -> dict:
 
 def _tune_dict(t) -> dict:
     return {"digit_bits": t.digit_bits, "tile_shift": t.tile_shift, "leaf_wg_per_cu": t.leaf_wg_per_cu,
-            "leaf_cap_shift": t.leaf_cap_shift, "first_bits": t.first_bits}
+            "leaf_cap_shift": t.leaf_cap_shift, "first_bits": t.first_bits, "mercy_shift": t.mercy_shift}
 
 
 def tune_set(t: dict | None = None):

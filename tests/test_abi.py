@@ -85,19 +85,21 @@ def test_tune_parameters_validated_on_host():
     sdbg.load()
     sdbg.tune_set(None)
     default = sdbg.tune_get()
-    assert default == {"digit_bits": 7, "tile_shift": 0, "leaf_wg_per_cu": 16, "leaf_cap_shift": 0, "first_bits": 6}
+    assert default == {"digit_bits": 7, "tile_shift": 0, "leaf_wg_per_cu": 16, "leaf_cap_shift": 0, "first_bits": 6,
+                       "mercy_shift": 0}
     for bad in ({"digit_bits": 3, "tile_shift": 0, "leaf_wg_per_cu": 16},
                 {"digit_bits": 9, "tile_shift": 0, "leaf_wg_per_cu": 16},
                 {"digit_bits": 8, "tile_shift": 2, "leaf_wg_per_cu": 16},
                 {"digit_bits": 8, "tile_shift": 0, "leaf_wg_per_cu": 0},
                 {"digit_bits": 8, "tile_shift": 0, "leaf_wg_per_cu": 33},
                 {"digit_bits": 8, "tile_shift": 0, "leaf_wg_per_cu": 16, "leaf_cap_shift": 2},
-                {"first_bits": 3}, {"first_bits": 9}):
+                {"first_bits": 3}, {"first_bits": 9}, {"mercy_shift": 9}):
         with pytest.raises(sdbg.SdbgError) as ei:
             sdbg.tune_set(bad)
         assert ei.value.code == -1
         assert sdbg.tune_get() == default
-    t = {"digit_bits": 6, "tile_shift": 1, "leaf_wg_per_cu": 8, "leaf_cap_shift": 1, "first_bits": 6}
+    t = {"digit_bits": 6, "tile_shift": 1, "leaf_wg_per_cu": 8, "leaf_cap_shift": 1, "first_bits": 6,
+         "mercy_shift": 3}
     sdbg.tune_set(t)
     assert sdbg.tune_get() == t
     sdbg.tune_set(None)

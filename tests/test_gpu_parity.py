@@ -189,3 +189,26 @@ def test_three_word_keys_mercy_repeatable():
         e, keys, cnt = gpu_count(rs, 81, 2, True)
         assert e.n_mercy == o.n_mercy
         assert np.array_equal(keys, o.keys) and np.array_equal(cnt, o.counts)
+
+
+@pytest.mark.parametrize("k", [5, 21, 31, 41])
+def test_mercy_lookup_table_overfull_paths(k):
+    """A mercy lookup table 4x, 32x and 256x smaller than it is sized for
+    (mercy_shift): more and more buckets hold more entries than slots, and
+    at 256x whole fill blocks overflow their LDS stage, so lookups take the
+    sorted-set path; results must not change."""
+    if k < 8:
+        rs = synth.random_small(300, k, k + 60, 200, 0.05, 42)
+    else:
+        rs = synth.metagenome_long(scale=0.0015, k=k)
+    o = oracle.count_solid(rs.seq, rs.offsets, k, 2, True)
+    assert o.n_mercy > 0
+    try:
+        for shift in (2, 5, 8):
+            say(f"k={k} mercy_shift={shift}")
+            sdbg.tune_set({"mercy_shift": shift})
+            e, keys, cnt = gpu_count(rs, k, 2, True)
+            assert e.n_mercy == o.n_mercy
+            assert np.array_equal(keys, o.keys) and np.array_equal(cnt, o.counts)
+    finally:
+        sdbg.tune_set(None)
