@@ -158,7 +158,7 @@ int sdbg_batch_run(const sdbg_reads *sets, uint64_t n_sets, const sdbg_params *p
  * not depend on them.
  *   digit_bits      most key bits one refinement pass cuts, 4..8 (7)
  *   tile_shift      refinement pass tile = the key width's default tile
- *                   (4096, 2048, 1024, 1024 keys for w = 1..4) >> tile_shift,
+ *                   (3584, 2048, 1024, 1024 keys for w = 1..4) >> tile_shift,
  *                   0 or 1 (0)
  *   leaf_wg_per_cu  persistent workgroups per compute unit of the in-LDS
  *                   sort and count, 1..32 (16; fewer if fewer fit)

@@ -275,9 +275,11 @@ struct Builder {
   Ctx& c;
   explicit Builder(Ctx& c_) : c(c_) {}
 
+  // Directory of about two keys per entry (at most 2^27 entries): the row
+  // placement's lookups then take one or two steps after it.
   SortedView view(const uint64_t* keys, uint64_t n, int kbits, DBuf<uint64_t>& dir) {
     int db = 1;
-    while (db < 24 && db < kbits && (n >> (db + 3)) > 0) ++db;
+    while (db < 27 && db < kbits && (n >> (db + 1)) > 0) ++db;
     dir = c.buf<uint64_t>((1ull << db) + 1);
     k_dir_b<W><<<grid1(n + 1), SDBG_BLOCK, 0, c.s>>>(keys, n, kbits, db, dir.get());
     c.check_launch("dir");

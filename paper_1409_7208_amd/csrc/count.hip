@@ -418,6 +418,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_seg_scatter(SegView v, uint64_t*
                                                             const uint64_t* __restrict__ tile_first,
                                                             const uint64_t* __restrict__ tab_base,
                                                             const uint32_t* __restrict__ tabscan) {
+  static_assert(TK % SDBG_BLOCK == 0, "whole keys per thread");
   constexpr int PER = TK / SDBG_BLOCK;
   __shared__ uint64_t lk[TK * W];
   __shared__ uint32_t cnt[256], lst[256], gb[256];
@@ -932,10 +933,10 @@ DEV uint8_t wslot_flags(const uint64_t* __restrict__ tab, const SortedView& S, c
 //                          e[0] = (x div 4) mod 4.
 // Bucket = NK >> rbits, BW 64-bit words: slot j holds bits [j*sb, (j+1)*sb)
 // of the bucket read as one little-endian integer, (NK mod 2^rbits) | sets
-// << rbits, nodes in increasing NK, sb = rbits + 8; the bucket's top bit
-// marks a bucket with more nodes than slots.  The nodes that did not fit
+// << rbits, sb = rbits + 8; the bucket's top bit marks a bucket with more
+// nodes than slots.  The nodes that did not fit
 // their bucket go to the spill line of their block of 2^s buckets (4 words,
-// slots of NK mod 2^(rbits+s) | sets << (rbits+s), increasing NK); its top
+// slots of NK mod 2^(rbits+s) | sets << (rbits+s), in bucket order); its top
 // bit marks a block with more such nodes than the line holds, whose other
 // nodes are then looked up in the sorted set.  Stored nodes have a
 // non-empty set byte; absent nodes have none.
@@ -1082,10 +1083,12 @@ DEV void put_slot(uint64_t* w, uint64_t slot, int pos, int sb) {
 // whose source node falls in it (keys c, then the block's bb - s bits).
 // Each contribution (node key, set bit) claims its node's entry in a list
 // of NODE_LIST entries per bucket in LDS (compare-and-swap on the key, then
-// OR of the bit); then one thread per bucket sorts its list by node key
-// (a sorting network), packs the first slots nodes into the bucket and
-// hands the rest to the block's spill line in bucket order.  A bucket with
-// more nodes than its list marks itself and the spill line overfull.  The
+// OR of the bit); then one thread per bucket packs the first slots nodes of
+// its list into the bucket and hands the rest to the block's spill line in
+// bucket order.  The order of a bucket's nodes (first come, first placed)
+// may differ between runs; lookups compare keys, so their results do not.
+// A bucket with more nodes than its list marks itself and the spill line
+// overfull.  The
 // barriers order LDS only: no thread reads another's global data.
 constexpr int NODE_LIST = 8;
 
@@ -1174,29 +1177,11 @@ __global__ __launch_bounds__(NODE_FILL_THREADS) void k_node_fill(SortedView S, N
       }
     }
     lds_barrier();
-    // thread j: bucket j's nodes, sorted by key (empty entries last)
-    uint64_t nk[NODE_LIST];
-    uint32_t fs[NODE_LIST];
-#pragma unroll
-    for (int r = 0; r < NODE_LIST; ++r) {
-      nk[r] = lk[r * NT + j];
-      fs[r] = lf[r * NT + j];
-    }
-#pragma unroll
-    for (int u = 0; u < NODE_LIST; ++u)
-#pragma unroll
-      for (int r = (u & 1); r + 1 < NODE_LIST; r += 2)
-        if (nk[r + 1] < nk[r]) {
-          const uint64_t tk = nk[r];
-          nk[r] = nk[r + 1];
-          nk[r + 1] = tk;
-          const uint32_t tf = fs[r];
-          fs[r] = fs[r + 1];
-          fs[r + 1] = tf;
-        }
+    // thread j: bucket j's nodes, entries 0 .. nn-1 (a bucket's list fills
+    // from its first entry on)
     uint32_t nn = 0;
-#pragma unroll
-    for (int r = 0; r < NODE_LIST; ++r) nn += nk[r] != EMPTY;
+    if (j < nbk)
+      while (nn < (uint32_t)NODE_LIST && lk[nn * NT + j] != EMPTY) ++nn;
     const bool lst = j < nbk && lost[j] != 0;
     const uint32_t nsp = nn > (uint32_t)p.slots ? nn - (uint32_t)p.slots : 0;
     const uint32_t incl = wave_incl_scan<uint32_t>(nsp);
@@ -1207,13 +1192,13 @@ __global__ __launch_bounds__(NODE_FILL_THREADS) void k_node_fill(SortedView S, N
     uint64_t w[BW];
 #pragma unroll
     for (int x = 0; x < BW; ++x) w[x] = 0;
-#pragma unroll
-    for (int r = 0; r < NODE_LIST; ++r) {
-      if (nk[r] == EMPTY) continue;
-      if (r < p.slots) {
-        put_slot<BW>(w, (nk[r] & rmask) | ((uint64_t)fs[r] << p.rbits), r * p.sb, p.sb);
+    for (uint32_t r = 0; r < nn; ++r) {
+      const uint64_t key = lk[r * NT + j];
+      const uint64_t f = lf[r * NT + j];
+      if (r < (uint32_t)p.slots) {
+        put_slot<BW>(w, (key & rmask) | (f << p.rbits), (int)r * p.sb, p.sb);
       } else if (spos < (uint32_t)p.sslots) {
-        const uint64_t slot = nk[r] | ((uint64_t)fs[r] << (p.rbits + s));
+        const uint64_t slot = key | (f << (p.rbits + s));
         const int pos = (int)spos * p.ssb, wd = pos >> 6, off = pos & 63;
         atomicOr(&sw[wd], (unsigned long long)(slot << off));
         if (off + p.ssb > 64) atomicOr(&sw[wd + 1], (unsigned long long)(slot >> (64 - off)));

@@ -7,13 +7,14 @@ namespace sdbg {
 
 // Tile shapes per key width W (64-bit words per key).
 //   IPT : windows per thread in the extraction partition (2 keys each)
-//   TK  : keys per workgroup tile in the segment partition
+//   TK  : keys per workgroup tile in the segment partition, a multiple of
+//         512 (one word: 28 KB of keys, so five workgroups fit a CU's LDS)
 //   CAP : most keys a leaf workgroup sorts in LDS
 template <int W>
 struct Tune;
 template <>
 struct Tune<1> {
-  static constexpr int IPT = 8, TK = 4096, CAP = 2048;
+  static constexpr int IPT = 6, TK = 3584, CAP = 2048;
 };
 template <>
 struct Tune<2> {
