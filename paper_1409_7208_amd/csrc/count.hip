@@ -103,6 +103,9 @@ struct ExArgs {
   const uint32_t* tset;
   const uint64_t* sw;
   const uint64_t* st;
+  // 1: each window emits only its canonical key (the smaller of its two
+  // strands' keys), twice if both are equal; 0: both keys.
+  int canon;
 };
 
 // Windows and histogram-table column of one extraction tile.
@@ -215,6 +218,24 @@ DEV void window_keys(const ExArgs& a, uint64_t j, Key<W>* kf, Key<W>* kr) {
   *kr = key_from_fwd<W>(revcomp_fwd<W>(F, a.kb), a.kb);
 }
 
+// Keys a window emits into the count: both strands' keys, or (canon) its
+// canonical key, once, or twice when the window is its own reverse
+// complement -- so every canonical key's count is the count of either of
+// its strands' keys over both strands.  Returns how many (1 or 2).
+template <int W>
+DEV int window_emit(const ExArgs& a, uint64_t j, Key<W>* k0, Key<W>* k1) {
+  Key<W> kf, kr;
+  window_keys<W>(a, j, &kf, &kr);
+  if (!a.canon) {
+    *k0 = kf;
+    *k1 = kr;
+    return 2;
+  }
+  *k0 = key_less<W>(kr, kf) ? kr : kf;
+  *k1 = *k0;
+  return key_eq<W>(kf, kr) ? 2 : 1;
+}
+
 template <int W>
 DEV bool ex_pass(const ExArgs& a, const Key<W>& key) {
   uint32_t p = key_bits<W>(key, a.kb - a.pb, a.pb);
@@ -222,12 +243,13 @@ DEV bool ex_pass(const ExArgs& a, const Key<W>& key) {
 }
 
 // Histogram of the partition digit per tile of 256*IPT windows, written
-// digit-major: tab[d * ntiles + tile].  If occ is given, also counts the
-// produced occurrences (one global atomic per wave; only for diagnostics).
+// digit-major: tab[d * ntiles + tile].  If occ is given, occ[tile] = the
+// tile's occurrences, two per clean window.
 template <int W, int IPT>
 __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_hist(ExArgs a, uint32_t* __restrict__ tab, uint64_t ntiles,
-                                                        unsigned long long* __restrict__ occ) {
+                                                        uint64_t* __restrict__ occ) {
   __shared__ uint32_t h[256];
+  __shared__ uint32_t wsum[SDBG_WAVES];
   h[threadIdx.x] = 0;
   __syncthreads();
   uint32_t produced = 0;
@@ -241,11 +263,11 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_hist(ExArgs a, uint32_t* __re
       if (g0 + q < tg.gend) {
         uint64_t j = it.pos();
         if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
-          Key<W> kf, kr;
-          window_keys<W>(a, j, &kf, &kr);
+          Key<W> k0, k1;
+          const int ne = window_emit<W>(a, j, &k0, &k1);
           produced += 2;
-          if (ex_pass<W>(a, kf)) atomicAdd(&h[key_bits<W>(kf, a.dlo, a.dbits)], 1u);
-          if (ex_pass<W>(a, kr)) atomicAdd(&h[key_bits<W>(kr, a.dlo, a.dbits)], 1u);
+          if (ex_pass<W>(a, k0)) atomicAdd(&h[key_bits<W>(k0, a.dlo, a.dbits)], 1u);
+          if (ne == 2 && ex_pass<W>(a, k1)) atomicAdd(&h[key_bits<W>(k1, a.dlo, a.dbits)], 1u);
         }
         it.next(a);
       }
@@ -254,8 +276,15 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_hist(ExArgs a, uint32_t* __re
   __syncthreads();
   if (threadIdx.x < (1u << a.dbits)) tab[tg.col + (uint64_t)threadIdx.x * tg.stride] = h[threadIdx.x];
   if (occ) {
-    uint32_t s = wave_sum(produced);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd(occ, (unsigned long long)s);
+    const uint32_t s = wave_sum(produced);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t t = 0;
+#pragma unroll
+      for (int i = 0; i < SDBG_WAVES; ++i) t += wsum[i];
+      occ[blockIdx.x] = t;
+    }
   }
 }
 
@@ -287,10 +316,10 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_scatter(ExArgs a, const uint3
       if (g0 + q < tg.gend) {
         uint64_t j = it.pos();
         if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
-          window_keys<W>(a, j, &keys[2 * q], &keys[2 * q + 1]);
+          const int ne = window_emit<W>(a, j, &keys[2 * q], &keys[2 * q + 1]);
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            if (ex_pass<W>(a, keys[2 * q + h])) {
+            if (h < ne && ex_pass<W>(a, keys[2 * q + h])) {
               uint32_t d = key_bits<W>(keys[2 * q + h], a.dlo, a.dbits);
               uint32_t s = atomicAdd(&cnt[d], 1u);
               pos[2 * q + h] = (d << 16) | s;
@@ -333,10 +362,10 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_hist_prefix(ExArgs a, unsigne
   for (int q = 0; q < IPT && g0 + q < a.NW; ++q) {
     uint64_t j = it.pos();
     if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
-      Key<W> kf, kr;
-      window_keys<W>(a, j, &kf, &kr);
-      atomicAdd(&h[key_bits<W>(kf, a.kb - a.pb, a.pb)], 1ull);
-      atomicAdd(&h[key_bits<W>(kr, a.kb - a.pb, a.pb)], 1ull);
+      Key<W> k0, k1;
+      const int ne = window_emit<W>(a, j, &k0, &k1);
+      atomicAdd(&h[key_bits<W>(k0, a.kb - a.pb, a.pb)], 1ull);
+      if (ne == 2) atomicAdd(&h[key_bits<W>(k1, a.kb - a.pb, a.pb)], 1ull);
     }
     it.next(a);
   }
@@ -1384,14 +1413,67 @@ __global__ void k_mercy(ExArgs a, const uint8_t* __restrict__ wf, int pass, uint
   if (!pass) mcount[r] = c;
 }
 
-// Counts of mercy edges from the low-count set (d > 2).
+// Counts of mercy edges from the low-count set (d > 2); with canon, the set
+// holds canonical keys only and an edge is looked up by its canonical key.
 template <int W>
 __global__ void k_lookup_counts(const uint64_t* __restrict__ keys, uint64_t n, SortedView L,
-                                const uint32_t* __restrict__ lcnt, uint32_t* __restrict__ out) {
+                                const uint32_t* __restrict__ lcnt, int canon, int kb, uint32_t* __restrict__ out) {
   uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
+  Key<W> q = key_load<W>(keys + i * W);
+  if (canon) {
+    const Key<W> r = key_revcomp<W>(q, kb);
+    if (key_less<W>(r, q)) q = r;
+  }
   uint64_t ix;
-  out[i] = sv_find<W>(L, key_load<W>(keys + i * W), &ix) ? lcnt[ix] : 0;
+  out[i] = sv_find<W>(L, q, &ix) ? lcnt[ix] : 0;
+}
+
+// Counted canonical one-word keys -> the other strand's keys.  Every key
+// that is not its own reverse complement gives its reverse complement with
+// the same count, packed as a two-word key (key << 32 | count) so that the
+// partition engine sorts the pairs by key.  Pass 0 counts such keys per
+// block of SDBG_BLOCK, pass 1 writes them at the scanned block offsets.
+__global__ __launch_bounds__(SDBG_BLOCK) void k_rc_pack(const uint64_t* __restrict__ S,
+                                                        const uint32_t* __restrict__ Sc, uint64_t n, int kb, int pass,
+                                                        uint64_t* __restrict__ bpos, uint64_t* __restrict__ R2) {
+  __shared__ uint32_t wc[SDBG_WAVES];
+  const uint64_t i = blockIdx.x * (uint64_t)SDBG_BLOCK + threadIdx.x;
+  uint64_t r = 0;
+  bool emit = false;
+  if (i < n) {
+    Key<1> x;
+    x.w[0] = S[i];
+    r = key_revcomp<1>(x, kb).w[0];
+    emit = r != x.w[0];
+  }
+  const uint64_t m = __ballot(emit);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) wc[wid] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (pass == 0) {
+    if (threadIdx.x == 0) {
+      uint64_t t = 0;
+#pragma unroll
+      for (int w = 0; w < SDBG_WAVES; ++w) t += wc[w];
+      bpos[blockIdx.x] = t;
+    }
+    return;
+  }
+  if (!emit) return;
+  uint64_t pos = bpos[blockIdx.x] + (uint64_t)__popcll(m & ((1ull << lane) - 1));
+  for (int w = 0; w < wid; ++w) pos += wc[w];
+  R2[2 * pos] = r >> 32;
+  R2[2 * pos + 1] = (r << 32) | Sc[i];
+}
+
+__global__ void k_rc_unpack(const uint64_t* __restrict__ R2, uint64_t n, uint64_t* __restrict__ keys,
+                            uint32_t* __restrict__ cnt) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t hi = R2[2 * i], lo = R2[2 * i + 1];
+  keys[i] = (hi << 32) | (lo >> 32);
+  cnt[i] = (uint32_t)lo;
 }
 
 // Merge of two disjoint sorted key sets (with their counts) along the merge
@@ -1775,6 +1857,74 @@ struct Counter {
     c.sync();
   }
 
+  // Merge of two disjoint sorted key sets with their counts.
+  void merge_sets(const char* name, const uint64_t* A, const uint32_t* Ac, uint64_t nA, const uint64_t* B,
+                  const uint32_t* Bc, uint64_t nB, DBuf<uint64_t>& E, DBuf<uint32_t>& Ec) {
+    E = c.buf<uint64_t>((nA + nB) * W);
+    Ec = c.buf<uint32_t>(nA + nB);
+    const uint64_t mt = ceil_div(nA + nB, MergeTile<W>::T);
+    SDBG_CHECK(mt < (1ull << 31), -3, "merge too large");
+    DBuf<uint64_t> split = c.buf<uint64_t>(mt + 1);
+    k_merge_split<W><<<grid1(mt + 1), SDBG_BLOCK, 0, c.s>>>(A, nA, B, nB, mt, split.get());
+    c.check_launch("merge_split");
+    {
+      Stage st_(c, name, 2 * (nA + nB) * (8 * W + 4));
+      k_merge_tile<W><<<(unsigned)mt, SDBG_BLOCK, 0, c.s>>>(A, Ac, nA, B, Bc, nB, split.get(), E.get(), Ec.get());
+      c.check_launch(name);
+    }
+    c.sync();
+  }
+
+  // Canonical counted keys -> both strands' keys: the reverse complements
+  // (with the same counts) are sorted as two-word (key, count) keys and
+  // merged in.  One-word keys only.
+  void expand_rc(DBuf<uint64_t>& S, DBuf<uint32_t>& Sc, uint64_t* nS, int kb) {
+    if constexpr (W == 1) {
+      const uint64_t n = *nS;
+      const uint64_t nblk = ceil_div(n, SDBG_BLOCK);
+      DBuf<uint64_t> bpos = c.buf<uint64_t>(nblk), tot = c.buf<uint64_t>(1);
+      k_rc_pack<<<(unsigned)nblk, SDBG_BLOCK, 0, c.s>>>(S.get(), Sc.get(), n, kb, 0, bpos.get(), nullptr);
+      c.check_launch("rc_count");
+      scan_excl<uint64_t, uint64_t>(bpos.get(), bpos.get(), nblk, tot.get(), c);
+      const uint64_t nR = c.d2h_one(tot.get());
+      DBuf<uint64_t> R2 = c.buf<uint64_t>(2 * nR);
+      {
+        Stage st_(c, "rc_pack", n * 12 + nR * 16);
+        k_rc_pack<<<(unsigned)nblk, SDBG_BLOCK, 0, c.s>>>(S.get(), Sc.get(), n, kb, 1, bpos.get(), R2.get());
+        c.check_launch("rc_pack");
+      }
+      if (nR == 0) return;
+      DBuf<uint64_t> R2s;
+      uint64_t nR2 = 0;
+      {
+        Counter<2> c2(c);
+        c2.sort_unique(R2, nR, kb + 32, R2s, &nR2);
+      }
+      SDBG_CHECK(nR2 == nR, -4, "reverse complement keys are not distinct");
+      R2.free();
+      DBuf<uint64_t> Rk = c.buf<uint64_t>(nR);
+      DBuf<uint32_t> Rc = c.buf<uint32_t>(nR);
+      {
+        Stage st_(c, "rc_unpack", nR * 16 + nR * 12);
+        k_rc_unpack<<<grid1(nR), SDBG_BLOCK, 0, c.s>>>(R2s.get(), nR, Rk.get(), Rc.get());
+        c.check_launch("rc_unpack");
+      }
+      R2s.free();
+      DBuf<uint64_t> E;
+      DBuf<uint32_t> Ec;
+      merge_sets("rc_merge", S.get(), Sc.get(), n, Rk.get(), Rc.get(), nR, E, Ec);
+      S = std::move(E);
+      Sc = std::move(Ec);
+      *nS = n + nR;
+    } else {
+      (void)S;
+      (void)Sc;
+      (void)nS;
+      (void)kb;
+      throw Error(-4, "canonical counting is for one-word keys");
+    }
+  }
+
   SortedView make_view(const uint64_t* keys, uint64_t n, int kbits, DBuf<uint64_t>& dir) {
     int db = 1;
     while (db < 24 && db < kbits && (n >> (db + 3)) > 0) ++db;
@@ -1898,6 +2048,9 @@ struct Counter {
     if (pr.NW == 0) return;
     const uint64_t NW = pr.NW, words = pr.words;
     ExArgs ea = pr.ea;
+    // One-word keys are counted on one strand (canonical keys) and expanded
+    // to both strands afterwards: half the keys pass the partition.
+    ea.canon = W == 1 ? 1 : 0;
     const uint32_t nbins = 1u << ea.dbits;
     const uint64_t win_per_tile = (uint64_t)SDBG_BLOCK * IPT;
     const uint64_t ntiles = ceil_div(NW, win_per_tile);
@@ -1905,18 +2058,29 @@ struct Counter {
 
     // ---- first-digit histogram over all keys
     // Every key passes the unfiltered histogram, so the scan total is the
-    // number of occurrences N; for a single group the scanned table is
-    // also the scatter's offset table.
+    // number N of keys to sort; for a single group the scanned table is
+    // also the scatter's offset table.  The occurrences (two per clean
+    // window) are counted alongside.
     DBuf<uint32_t> tab = c.buf<uint32_t>(ntiles * nbins);
     DBuf<uint64_t> tot = c.buf<uint64_t>(1);
+    DBuf<uint64_t> occ = c.buf<uint64_t>(ea.any_bad ? ntiles : 0);
     {
       Stage st_(c, "ex_hist", 3 * words * 8 + ntiles * nbins * 4);
-      k_ex_hist<W, IPT><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(ea, tab.get(), ntiles, nullptr);
+      k_ex_hist<W, IPT><<<(unsigned)ntiles, SDBG_BLOCK, 0, c.s>>>(ea, tab.get(), ntiles,
+                                                                  ea.any_bad ? occ.get() : nullptr);
       c.check_launch("ex_hist");
     }
     scan_excl<uint32_t, uint32_t>(tab.get(), tab.get(), ntiles * nbins, tot.get(), c);
     const uint64_t N = c.d2h_one(tot.get());
-    out->n_occ = N;
+    if (ea.any_bad) {
+      // (tot keeps N: a single group's scatter reads it again)
+      DBuf<uint64_t> otot = c.buf<uint64_t>(1);
+      scan_excl<uint64_t, uint64_t>(occ.get(), occ.get(), ntiles, otot.get(), c);
+      out->n_occ = c.d2h_one(otot.get());
+    } else {
+      out->n_occ = 2 * NW;
+    }
+    occ.free();
 
     // ---- groups of consecutive prefix blocks within the memory budget
     uint64_t budget = P.mem_budget;
@@ -2062,6 +2226,9 @@ struct Counter {
       l_cnt.clear();
     }
 
+    // ---- both strands
+    if (ea.canon && nS > 0) expand_rc(S, Sc, &nS, kb);
+
     // ---- mercy-kmers
     DBuf<uint64_t> M;
     DBuf<uint32_t> Mc;
@@ -2157,7 +2324,7 @@ struct Counter {
         } else {
           DBuf<uint64_t> ldir;
           SortedView lv = make_view(Lk.get(), nL, kb, ldir);
-          k_lookup_counts<W><<<grid1(nM), SDBG_BLOCK, 0, c.s>>>(M.get(), nM, lv, Lc.get(), Mc.get());
+          k_lookup_counts<W><<<grid1(nM), SDBG_BLOCK, 0, c.s>>>(M.get(), nM, lv, Lc.get(), ea.canon, kb, Mc.get());
           c.check_launch("lookup_counts");
           c.sync();
         }
@@ -2170,20 +2337,9 @@ struct Counter {
       out->keys = S.release_ownership();
       out->count = Sc.release_ownership();
     } else {
-      DBuf<uint64_t> E = c.buf<uint64_t>((nS + nM) * W);
-      DBuf<uint32_t> Ec = c.buf<uint32_t>(nS + nM);
-      const uint64_t mt = ceil_div(nS + nM, MergeTile<W>::T);
-      DBuf<uint64_t> split = c.buf<uint64_t>(mt + 1);
-      k_merge_split<W><<<grid1(mt + 1), SDBG_BLOCK, 0, c.s>>>(S.get(), nS, M.get(), nM, mt, split.get());
-      c.check_launch("merge_split");
-      {
-        Stage st_(c, "merge", 2 * (nS + nM) * (8 * W + 4));
-        SDBG_CHECK(mt < (1ull << 31), -3, "merge too large");
-        k_merge_tile<W><<<(unsigned)mt, SDBG_BLOCK, 0, c.s>>>(S.get(), Sc.get(), nS, M.get(), Mc.get(), nM, split.get(),
-                                                               E.get(), Ec.get());
-        c.check_launch("merge");
-      }
-      c.sync();
+      DBuf<uint64_t> E;
+      DBuf<uint32_t> Ec;
+      merge_sets("merge", S.get(), Sc.get(), nS, M.get(), Mc.get(), nM, E, Ec);
       out->keys = E.release_ownership();
       out->count = Ec.release_ownership();
     }

@@ -123,6 +123,15 @@ DEV bool sv_has_target(const SortedView& v, const Key<W>& P, int k) {
   return false;
 }
 
+// Edge key of the reverse complement of the (k+1)-mer with edge key x
+// (kb = 2(k+1) bits): back to the forward packing (rotate right by one
+// base), complement-reverse, rotate left again.
+template <int W>
+DEV Key<W> key_revcomp(const Key<W>& x, int kb) {
+  const Key<W> F = key_or2<W>(key_shr<W>(x, 2), kb - 2, x.w[W - 1] & 3);
+  return key_from_fwd<W>(revcomp_fwd<W>(F, kb), kb);
+}
+
 // Target node x[1..k] of edge key x (2k bits): (x >> 4) + x[k] * 4^(k-1).
 template <int W>
 DEV Key<W> edge_target(const Key<W>& x, int k) {
