@@ -410,12 +410,22 @@ __global__ void k_seg_mark(SegView v, uint64_t cap, int D, int tk, uint64_t* __r
   tabsz[s] = nt << d;
 }
 
-__global__ void k_seg_tiles(SegView v, const uint64_t* __restrict__ tile_first, const uint64_t* __restrict__ ntiles,
+// Segment of each tile t < NT: the last segment whose first tile is <= t
+// (tile_first is the exclusive scan of the tile counts, so a run of equal
+// entries ends with the one segment of the run that has tiles).
+__global__ void k_seg_tiles(SegView v, const uint64_t* __restrict__ tile_first, uint64_t NT,
                             uint32_t* __restrict__ tile_seg) {
-  uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (s >= v.n) return;
-  uint64_t nt = ntiles[s], f = tile_first[s];
-  for (uint64_t i = 0; i < nt; ++i) tile_seg[f + i] = (uint32_t)s;
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (t >= NT) return;
+  uint64_t lo = 0, hi = v.n;  // first segment whose first tile is > t
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (tile_first[mid] <= t)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  tile_seg[t] = (uint32_t)(lo - 1);
 }
 
 template <int W, int TK>
@@ -1349,9 +1359,10 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags(ExArgs a, const uin
 // mercy edges.  Pass 0 counts keys per read, pass 1 writes them (only for
 // reads with a count).  Flags are read eight at a time (wf is padded to a
 // whole word).  A flag the node lookups left unknown (one-word keys: 0x10
-// no-out, 0x08 no-in) is looked up in the node table when a pair needs it.
+// no-out, 0x08 no-in) is looked up in the node table when a pair needs it;
+// pass 0 writes it back into wf (each thread only its own read's bytes).
 template <int W>
-__global__ void k_mercy(ExArgs a, const uint8_t* __restrict__ wf, int pass, uint64_t* __restrict__ mcount,
+__global__ void k_mercy(ExArgs a, uint8_t* __restrict__ wf, int pass, uint64_t* __restrict__ mcount,
                         const uint64_t* __restrict__ mpos, uint64_t* __restrict__ cand, NodeTab nt) {
   uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (r >= a.n_reads) return;
@@ -1383,13 +1394,16 @@ __global__ void k_mercy(ExArgs a, const uint8_t* __restrict__ wf, int pass, uint
     if (p >= 0 && q - p >= 2) {
       bool noout = (fp & 2) != 0, noin = (f & 4) != 0;
       if constexpr (W == 1) {
+        // pass 0 stores what it looked up, so pass 1 finds the flags known
         if (fp & 0x10) {
           const uint64_t x = key_from_fwd<1>(stream_bits<1>(a.packed, 2 * (rs + (uint64_t)p), a.kb), a.kb).w[0];
           noout = (node_sets(nt, node_of_target(x)) >> 4) == 0;
+          wf[g0 + (uint64_t)p] = (uint8_t)((fp & ~0x10) | (noout ? 2 : 0));
         }
         if (noout && (f & 0x08)) {
           const uint64_t x = key_from_fwd<1>(stream_bits<1>(a.packed, 2 * (rs + (uint64_t)q), a.kb), a.kb).w[0];
           noin = (node_sets(nt, node_of_source(x, nt.nkb)) & 15) == 0;
+          wf[g] = (uint8_t)((f & ~0x08) | (noin ? 4 : 0));
         }
       }
       fire = noout && noin;
@@ -1768,7 +1782,7 @@ struct Counter {
       const uint64_t NT = ht[0], NTab = ht[1];
       SDBG_CHECK(NT < (1ull << 31), -3, "too many partition tiles");
       DBuf<uint32_t> tile_seg = c.buf<uint32_t>(NT), tab = c.buf<uint32_t>(NTab);
-      k_seg_tiles<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), tile_first.get(), ntiles.get(), tile_seg.get());
+      k_seg_tiles<<<grid1(NT), SDBG_BLOCK, 0, c.s>>>(L.view(), tile_first.get(), NT, tile_seg.get());
       c.check_launch("seg_tiles");
       if (tk == TK)
         seg_pass<TK>(L, d_bufs, NT, NTab, hs[1], tile_seg, tile_first, tab_base, tab);
