@@ -1,6 +1,9 @@
 // Counting path (Section 2, third paragraph): reads -> 2-bit packing ->
 // both-strand (k+1)-mer keys -> MSD radix partition in HBM -> per-leaf LDS
 // sort + run-length count + solid filter -> mercy-kmers -> sorted edge set.
+// One-word keys are counted as canonical keys (one per window, see
+// window_emit) and the counted set is expanded to both strands before the
+// mercy step (expand_rc).
 //
 // Keys are the colex edge keys (Section 2, second paragraph): digits
 // e[k-1], ..., e[0], e[k] of the (k+1)-mer e.  The partition cuts the key
@@ -595,7 +598,8 @@ struct LeafShape {
 template <int W, int CAP>
 __global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* const* __restrict__ bufs,
                                                      uint32_t* __restrict__ cnt, uint32_t dmin, int want_low,
-                                                     uint64_t* __restrict__ nsolid, uint64_t* __restrict__ nlow) {
+                                                     int distinct, uint64_t* __restrict__ nsolid,
+                                                     uint64_t* __restrict__ nlow) {
   constexpr int PER = LeafShape<CAP>::PER, H = LeafShape<CAP>::H, MAXB = LeafShape<CAP>::MAXB;
   constexpr uint32_t EMPTY = 0xFFFFFFFFu;
   static_assert(CAP <= 4096 && H <= 65536, "leaf sizes");
@@ -657,7 +661,12 @@ __global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* con
       const int i = q * SDBG_BLOCK + threadIdx.x;
       if (i < n) key_store<W>(&A[i * W], nk[q]);
     }
-    for (int i = threadIdx.x; i < Hs; i += SDBG_BLOCK) hs[i] = EMPTY;
+    if (distinct) {
+      // keys known to be distinct: each is its own slot, count 1
+      for (int i = threadIdx.x; i < n; i += SDBG_BLOCK) hs[i] = ((uint32_t)i << 16) | 1u;
+    } else {
+      for (int i = threadIdx.x; i < Hs; i += SDBG_BLOCK) hs[i] = EMPTY;
+    }
     fetch(s + G);
     lds_barrier();
     // 1. merge duplicates; the element that claims a slot represents its key
@@ -667,7 +676,9 @@ __global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* con
     for (int q = 0; q < PER; ++q) {
       rep[q] = EMPTY;
       const int i = q * SDBG_BLOCK + threadIdx.x;
-      if (i < n) {
+      if (i < n && distinct) {
+        rep[q] = (uint32_t)i;
+      } else if (i < n) {
         const Key<W> kx = key_load<W>(&A[i * W]);
         uint32_t h = leaf_hash<W>(kx) >> hshift;
         for (;;) {
@@ -1710,6 +1721,7 @@ struct Counter {
   Ctx& c;
   SortTune tune;
   explicit Counter(Ctx& c_) : c(c_), tune(sort_tune()) {}
+  bool distinct_keys = false;  // the next leaves() call sorts keys known to be distinct
 
   // Largest segment a leaf sorts (the refinement cuts until segments fit).
   uint64_t leaf_cap() const { return (uint64_t)CAP >> tune.leaf_cap_shift; }
@@ -1728,7 +1740,8 @@ struct Counter {
     }
     const int per_cu = std::max(1, std::min(resident, tune.leaf_wg_per_cu));
     const unsigned lgrid = (unsigned)std::min<uint64_t>(L.n, (uint64_t)cu_count() * per_cu);
-    k_leaf<W, CAPX><<<lgrid, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, cnt, dmin, want_low ? 1 : 0, ns, nl);
+    k_leaf<W, CAPX><<<lgrid, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, cnt, dmin, want_low ? 1 : 0,
+                                                   distinct_keys ? 1 : 0, ns, nl);
     c.check_launch("leaf");
   }
 
@@ -1845,7 +1858,10 @@ struct Counter {
   }
 
   // Sorted distinct keys of an arbitrary key array (consumed).
-  void sort_unique(DBuf<uint64_t>& keys, uint64_t n, int kb, DBuf<uint64_t>& out, uint64_t* nout) {
+  // distinct: the keys are known to be pairwise different (the leaves skip
+  // their duplicate merge).
+  void sort_unique(DBuf<uint64_t>& keys, uint64_t n, int kb, DBuf<uint64_t>& out, uint64_t* nout,
+                   bool distinct = false) {
     SDBG_CHECK(n < (1ull << 32), -3, "key array too large for one partition group");
     DBuf<uint64_t> other = c.buf<uint64_t>(n * W);
     DBuf<uint32_t> cnt = c.buf<uint32_t>(n);
@@ -1867,7 +1883,9 @@ struct Counter {
     DBuf<uint64_t> lk;
     DBuf<uint32_t> lc;
     uint64_t nl;
+    distinct_keys = distinct;
     leaves(L, n, db.get(), cnt.get(), 1, false, out, ocnt, nout, lk, lc, &nl);
+    distinct_keys = false;
     c.sync();
   }
 
@@ -1912,7 +1930,7 @@ struct Counter {
       uint64_t nR2 = 0;
       {
         Counter<2> c2(c);
-        c2.sort_unique(R2, nR, kb + 32, R2s, &nR2);
+        c2.sort_unique(R2, nR, kb + 32, R2s, &nR2, true);
       }
       SDBG_CHECK(nR2 == nR, -4, "reverse complement keys are not distinct");
       R2.free();
