@@ -1504,8 +1504,9 @@ __global__ void k_rc_unpack(const uint64_t* __restrict__ R2, uint64_t n, uint64_
 // Merge of two disjoint sorted key sets (with their counts) along the merge
 // path: output tile t covers positions [t*T, (t+1)*T); the split of each
 // tile boundary between A and B is found by one binary search on the
-// cross diagonal, then a workgroup stages its A and B runs in LDS, ranks each
-// element in the other run there and writes it to its place in the tile.
+// cross diagonal, then a workgroup stages its A and B runs in LDS, each
+// thread merges a stretch of the tile's output along the same path, and the
+// merged tile is written out through LDS.
 template <int W>
 struct MergeTile {
   static constexpr int T = W == 1 ? 2048 : W == 2 ? 1024 : 512;
@@ -1545,32 +1546,48 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_merge_tile(const uint64_t* __res
   for (int i = threadIdx.x; i < nA; i += SDBG_BLOCK) key_store<W>(&la[i * W], key_load<W>(A + (a0 + i) * W));
   for (int i = threadIdx.x; i < nB; i += SDBG_BLOCK) key_store<W>(&lb[i * W], key_load<W>(B + (b0 + i) * W));
   lds_barrier();
-  // rank of each element in the other run (the sets are disjoint)
-  for (int i = threadIdx.x; i < nA; i += SDBG_BLOCK) {
-    const Key<W> x = key_load<W>(&la[i * W]);
-    int lo = 0, hi = nB;
-    while (lo < hi) {
-      const int m = (lo + hi) >> 1;
-      if (key_less<W>(key_load<W>(&lb[m * W]), x))
-        lo = m + 1;
-      else
-        hi = m;
-    }
-    key_store<W>(E + (d0 + i + lo) * W, x);
-    Ec[d0 + i + lo] = Ac[a0 + i];
+  // each thread merges PT consecutive outputs of the tile into registers:
+  // its start on the merge path by one search along its diagonal, then a
+  // sequential merge (the sets are disjoint, so there are no ties) ...
+  static_assert(T % SDBG_BLOCK == 0, "whole outputs per thread");
+  constexpr int PT = T / SDBG_BLOCK;
+  const int n = nA + nB;
+  const int o0 = min((int)threadIdx.x * PT, n);
+  int lo = max(0, o0 - nB), hi = min(o0, nA);
+  while (lo < hi) {
+    const int m = (lo + hi) >> 1;
+    if (key_less<W>(key_load<W>(&la[m * W]), key_load<W>(&lb[(o0 - m - 1) * W])))
+      lo = m + 1;
+    else
+      hi = m;
   }
-  for (int i = threadIdx.x; i < nB; i += SDBG_BLOCK) {
-    const Key<W> x = key_load<W>(&lb[i * W]);
-    int lo = 0, hi = nA;
-    while (lo < hi) {
-      const int m = (lo + hi) >> 1;
-      if (key_less<W>(key_load<W>(&la[m * W]), x))
-        lo = m + 1;
-      else
-        hi = m;
+  int ia = lo, ib = o0 - lo;
+  Key<W> ok[PT];
+  uint32_t oc[PT];
+#pragma unroll
+  for (int q = 0; q < PT; ++q) {
+    if (o0 + q < n) {
+      const bool ta = ib >= nB || (ia < nA && key_less<W>(key_load<W>(&la[ia * W]), key_load<W>(&lb[ib * W])));
+      ok[q] = key_load<W>(ta ? &la[ia * W] : &lb[ib * W]);
+      oc[q] = ta ? Ac[a0 + ia] : Bc[b0 + ib];
+      ia += ta;
+      ib += !ta;
     }
-    key_store<W>(E + (d0 + i + lo) * W, x);
-    Ec[d0 + i + lo] = Bc[b0 + i];
+  }
+  // ... then the tile goes back through LDS (keys over la, counts over lb)
+  // so that the stores are coalesced
+  lds_barrier();
+  uint32_t* lc = reinterpret_cast<uint32_t*>(lb);
+#pragma unroll
+  for (int q = 0; q < PT; ++q)
+    if (o0 + q < n) {
+      key_store<W>(&la[(o0 + q) * W], ok[q]);
+      lc[o0 + q] = oc[q];
+    }
+  lds_barrier();
+  for (int i = threadIdx.x; i < n; i += SDBG_BLOCK) {
+    key_store_g<W>(E + (d0 + i) * W, key_load<W>(&la[i * W]));
+    Ec[d0 + i] = lc[i];
   }
 }
 
