@@ -520,47 +520,58 @@ __device__ __forceinline__ void child_range(const SegView& v, uint64_t s, int tk
   *end = (d + 1 < (1u << D)) ? (uint64_t)(tabscan[tb + (uint64_t)(d + 1) * nt] - s0) : v.len[s];
 }
 
+// One wave per segment; its lanes take the children of a cut segment in
+// turn (2^D <= 256 of them).
 __global__ void k_seg_newcount(SegView v, int tk, const uint64_t* __restrict__ tab_base,
                                const uint32_t* __restrict__ tabscan, uint64_t* __restrict__ cnt) {
-  uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (s >= v.n) return;
+  const uint64_t s = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const uint32_t lane = threadIdx.x & 63;
+  if (s >= v.n) return;  // whole waves
   const int D = v.D[s];
   if (!D) {
-    cnt[s] = 1;
+    if (lane == 0) cnt[s] = 1;
     return;
   }
   uint64_t c = 0;
-  for (uint32_t d = 0; d < (1u << D); ++d) {
+  for (uint32_t d = lane; d < (1u << D); d += 64) {
     uint64_t a, b;
     child_range(v, s, tk, tab_base, tabscan, d, &a, &b);
     c += b > a;
   }
-  cnt[s] = c;
+  c = wave_sum(c);
+  if (lane == 0) cnt[s] = c;
 }
 
 __global__ void k_seg_newwrite(SegView v, int tk, const uint64_t* __restrict__ tab_base,
                                const uint32_t* __restrict__ tabscan, const uint64_t* __restrict__ newpos, SegView nv) {
-  uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (s >= v.n) return;
+  const uint64_t s = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const uint32_t lane = threadIdx.x & 63;
+  if (s >= v.n) return;  // whole waves
   uint64_t p = newpos[s];
   const int D = v.D[s];
   if (!D) {
-    nv.off[p] = v.off[s];
-    nv.len[p] = v.len[s];
-    nv.bit[p] = v.bit[s];
-    nv.buf[p] = v.buf[s];
+    if (lane == 0) {
+      nv.off[p] = v.off[s];
+      nv.len[p] = v.len[s];
+      nv.bit[p] = v.bit[s];
+      nv.buf[p] = v.buf[s];
+    }
     return;
   }
-  for (uint32_t d = 0; d < (1u << D); ++d) {
-    uint64_t a, b;
-    child_range(v, s, tk, tab_base, tabscan, d, &a, &b);
-    if (b > a) {
-      nv.off[p] = v.off[s] + a;
-      nv.len[p] = b - a;
-      nv.bit[p] = (uint16_t)(v.bit[s] - D);
-      nv.buf[p] = (uint8_t)(v.buf[s] ^ 1);
-      ++p;
+  for (uint32_t d0 = 0; d0 < (1u << D); d0 += 64) {
+    const uint32_t d = d0 + lane;
+    uint64_t a = 0, b = 0;
+    if (d < (1u << D)) child_range(v, s, tk, tab_base, tabscan, d, &a, &b);
+    const uint32_t ne = b > a ? 1u : 0u;
+    const uint32_t incl = wave_incl_scan<uint32_t>(ne);
+    if (ne) {
+      const uint64_t q = p + incl - 1;
+      nv.off[q] = v.off[s] + a;
+      nv.len[q] = b - a;
+      nv.bit[q] = (uint16_t)(v.bit[s] - D);
+      nv.buf[q] = (uint8_t)(v.buf[s] ^ 1);
     }
+    p += __shfl(incl, 63, 64);
   }
 }
 
@@ -1819,13 +1830,14 @@ struct Counter {
       else
         seg_pass<TK / 2>(L, d_bufs, NT, NTab, hs[1], tile_seg, tile_first, tab_base, tab);
       DBuf<uint64_t> ncnt = c.buf<uint64_t>(L.n), npos = c.buf<uint64_t>(L.n);
-      k_seg_newcount<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), tk, tab_base.get(), tab.get(), ncnt.get());
+      k_seg_newcount<<<grid1(L.n * 64), SDBG_BLOCK, 0, c.s>>>(L.view(), tk, tab_base.get(), tab.get(), ncnt.get());
       c.check_launch("seg_newcount");
       scan_excl<uint64_t, uint64_t>(ncnt.get(), npos.get(), L.n, tot.get(), c);
       const uint64_t nn = c.d2h_one(tot.get());
       SegList N;
       N.alloc(c, nn);
-      k_seg_newwrite<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), tk, tab_base.get(), tab.get(), npos.get(), N.view());
+      k_seg_newwrite<<<grid1(L.n * 64), SDBG_BLOCK, 0, c.s>>>(L.view(), tk, tab_base.get(), tab.get(), npos.get(),
+                                                             N.view());
       c.check_launch("seg_newwrite");
       L = std::move(N);
     }
