@@ -1375,6 +1375,18 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags(ExArgs a, const uin
     if (g0 + q < a.NW) wf[g0 + q] = f[q];
 }
 
+// 1 where x[i] != 0; then, at the scanned positions, the indices themselves.
+__global__ void k_nonzero(const uint64_t* __restrict__ x, uint64_t n, uint64_t* __restrict__ f) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i < n) f[i] = x[i] != 0;
+}
+
+__global__ void k_list_nonzero(const uint64_t* __restrict__ x, uint64_t n, const uint64_t* __restrict__ pos,
+                               uint64_t* __restrict__ list) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i < n && x[i]) list[pos[i]] = i;
+}
+
 // Mercy rule along each read (forward strand): consecutive solid windows
 // p < q of one ACGT stretch, q - p >= 2, p without outgoing and q without
 // incoming solid edge: windows p+1..q-1 and their reverse complements are
@@ -1385,10 +1397,17 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_window_flags(ExArgs a, const uin
 // pass 0 writes it back into wf (each thread only its own read's bytes).
 template <int W>
 __global__ void k_mercy(ExArgs a, uint8_t* __restrict__ wf, int pass, uint64_t* __restrict__ mcount,
-                        const uint64_t* __restrict__ mpos, uint64_t* __restrict__ cand, NodeTab nt) {
+                        const uint64_t* __restrict__ mpos, uint64_t* __restrict__ cand, NodeTab nt,
+                        const uint64_t* __restrict__ rlist, uint64_t nlist) {
   uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (r >= a.n_reads) return;
-  if (pass && mcount[r] == 0) return;
+  if (pass) {
+    // pass 1 runs over the list of reads with candidates, so that its waves
+    // are full
+    if (r >= nlist) return;
+    r = rlist[r];
+  } else if (r >= a.n_reads) {
+    return;
+  }
   const uint64_t g0 = a.woff[r], g1 = a.woff[r + 1];
   const uint64_t rs = a.offsets[r];
   uint64_t out = pass ? mpos[r] : 0, c = 0;
@@ -2345,7 +2364,8 @@ struct Counter {
       DBuf<uint64_t> mcount = c.buf<uint64_t>(R.n_reads), mpos = c.buf<uint64_t>(R.n_reads);
       {
         Stage st_(c, "mercy_count", NW + R.n_reads * 24);
-        k_mercy<W><<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(ea, wf.get(), 0, mcount.get(), nullptr, nullptr, nt);
+        k_mercy<W><<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(ea, wf.get(), 0, mcount.get(), nullptr, nullptr, nt,
+                                                            nullptr, 0);
         c.check_launch("mercy_count");
       }
       scan_excl<uint64_t, uint64_t>(mcount.get(), mpos.get(), R.n_reads, tot.get(), c);
@@ -2370,10 +2390,19 @@ struct Counter {
       }
       if (NC) {
         DBuf<uint64_t> cand = c.buf<uint64_t>(NC * W);
+        // reads with candidates, in read order
+        DBuf<uint64_t> rpos = c.buf<uint64_t>(R.n_reads);
+        k_nonzero<<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(mcount.get(), R.n_reads, rpos.get());
+        c.check_launch("mercy_reads");
+        scan_excl<uint64_t, uint64_t>(rpos.get(), rpos.get(), R.n_reads, tot.get(), c);
+        const uint64_t NR = c.d2h_one(tot.get());
+        DBuf<uint64_t> rlist = c.buf<uint64_t>(NR);
+        k_list_nonzero<<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(mcount.get(), R.n_reads, rpos.get(), rlist.get());
+        c.check_launch("mercy_reads");
         {
-          Stage st_(c, "mercy_emit", NW + R.n_reads * 24 + NC * 8 * W);
-          k_mercy<W><<<grid1(R.n_reads), SDBG_BLOCK, 0, c.s>>>(ea, wf.get(), 1, mcount.get(), mpos.get(), cand.get(),
-                                                               nt);
+          Stage st_(c, "mercy_emit", NW + NR * 32 + NC * 8 * W);
+          k_mercy<W><<<grid1(NR), SDBG_BLOCK, 0, c.s>>>(ea, wf.get(), 1, mcount.get(), mpos.get(), cand.get(), nt,
+                                                        rlist.get(), NR);
           c.check_launch("mercy_emit");
         }
         wf.free();
