@@ -36,6 +36,34 @@ inline unsigned grid1(uint64_t n) {
 // Per edge: bit0 minus, bit1 '$' row for its target (target has no
 // out-edge, and this is the first edge into it), bit2 dummy row for its
 // source (first edge of the source, source has no in-edge), bit3 last.
+// Lower bounds of two queries in one sorted view, searched in lockstep so
+// that the loads of the two searches overlap (v.n >= 1).
+template <int W>
+DEV void sv_lower2(const SortedView& v, const Key<W>& q1, const Key<W>& q2, uint64_t* r1, uint64_t* r2) {
+  const uint32_t b1 = key_bits<W>(q1, v.kbits - v.db, v.db), b2 = key_bits<W>(q2, v.kbits - v.db, v.db);
+  uint64_t lo1 = v.dir[b1], hi1 = v.dir[b1 + 1], lo2 = v.dir[b2], hi2 = v.dir[b2 + 1];
+  while (lo1 < hi1 || lo2 < hi2) {
+    const bool a1 = lo1 < hi1, a2 = lo2 < hi2;
+    const uint64_t m1 = (lo1 + hi1) >> 1, m2 = (lo2 + hi2) >> 1;
+    const Key<W> k1 = key_load<W>(v.keys + (a1 ? m1 : 0) * W);
+    const Key<W> k2 = key_load<W>(v.keys + (a2 ? m2 : 0) * W);
+    if (a1) {
+      if (key_less<W>(k1, q1))
+        lo1 = m1 + 1;
+      else
+        hi1 = m1;
+    }
+    if (a2) {
+      if (key_less<W>(k2, q2))
+        lo2 = m2 + 1;
+      else
+        hi2 = m2;
+    }
+  }
+  *r1 = lo1;
+  *r2 = lo2;
+}
+
 template <int W>
 __global__ void k_row_flags(SortedView E, int k, uint8_t* __restrict__ fl) {
   uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -54,8 +82,26 @@ __global__ void k_row_flags(SortedView E, int k, uint8_t* __restrict__ fl) {
   }
   const bool first = i == 0 || !key_eq<W>(key_shr<W>(key_load<W>(E.keys + (i - 1) * W), 2), src);
   const bool last = i + 1 == E.n || !key_eq<W>(key_shr<W>(key_load<W>(E.keys + (i + 1) * W), 2), src);
-  const bool zout = !minus && !sv_has_source<W>(E, edge_target<W>(x, k));
-  const bool zin = first && !sv_has_target<W>(E, src, k);
+  // out-edges of the target: keys T*4 + c'; in-edges of the source: keys
+  // (c' + 4*src[0..k-2])*4 + src[k-1], among the keys sharing key div 16
+  const Key<W> T = edge_target<W>(x, k);
+  const uint64_t top = key_bits<W>(src, 2 * k - 2, 2);
+  const Key<W> base = key_or_low<W>(key_shl<W>(key_lowbits<W>(src, 2 * k - 2), 4), top);
+  uint64_t io, ii;
+  sv_lower2<W>(E, key_shl<W>(T, 2), base, &io, &ii);
+  const bool has_out = io < E.n && key_eq<W>(key_shr<W>(key_load<W>(E.keys + io * W), 2), T);
+  bool has_in = false;
+  const Key<W> hi4 = key_shr<W>(base, 4);
+  for (; ii < E.n; ++ii) {
+    const Key<W> y = key_load<W>(E.keys + ii * W);
+    if (!key_eq<W>(key_shr<W>(y, 4), hi4)) break;
+    if ((y.w[W - 1] & 3) == top) {
+      has_in = true;
+      break;
+    }
+  }
+  const bool zout = !minus && !has_out;
+  const bool zin = first && !has_in;
   fl[i] = (uint8_t)((minus ? 1 : 0) | (zout ? 2 : 0) | (zin ? 4 : 0) | (last ? 8 : 0));
 }
 
