@@ -204,6 +204,36 @@ __global__ void k_merge4(const uint64_t* __restrict__ in, uint64_t t, const uint
   key_store<W>(out + r * W, x);
 }
 
+// Lower bound of q1 in v1 and upper bound (first key > q2) of q2 in v2,
+// searched in lockstep so that the loads of the two searches overlap.
+template <int W>
+DEV void sv_lower_upper(const SortedView& v1, const Key<W>& q1, const SortedView& v2, const Key<W>& q2,
+                        uint64_t* r1, uint64_t* r2) {
+  const uint32_t b1 = key_bits<W>(q1, v1.kbits - v1.db, v1.db), b2 = key_bits<W>(q2, v2.kbits - v2.db, v2.db);
+  uint64_t lo1 = v1.dir[b1], hi1 = v1.dir[b1 + 1], lo2 = v2.dir[b2], hi2 = v2.dir[b2 + 1];
+  while (lo1 < hi1 || lo2 < hi2) {
+    const bool a1 = lo1 < hi1, a2 = lo2 < hi2;
+    const uint64_t m1 = (lo1 + hi1) >> 1, m2 = (lo2 + hi2) >> 1;
+    Key<W> k1 = key_zero<W>(), k2 = key_zero<W>();
+    if (a1) k1 = key_load<W>(v1.keys + m1 * W);
+    if (a2) k2 = key_load<W>(v2.keys + m2 * W);
+    if (a1) {
+      if (key_less<W>(k1, q1))
+        lo1 = m1 + 1;
+      else
+        hi1 = m1;
+    }
+    if (a2) {
+      if (!key_less<W>(q2, k2))
+        lo2 = m2 + 1;
+      else
+        hi2 = m2;
+    }
+  }
+  *r1 = lo1;
+  *r2 = lo2;
+}
+
 // Row placement.  rf: bit0 last, bit1 valid, bit2 tip.
 template <int W>
 __global__ void k_place_real(SortedView E, const uint32_t* __restrict__ cnt, const uint8_t* __restrict__ fl,
@@ -213,7 +243,9 @@ __global__ void k_place_real(SortedView E, const uint32_t* __restrict__ cnt, con
   if (i >= E.n) return;
   const Key<W> x = key_load<W>(E.keys + i * W);
   const Key<W> hi3 = key_or_low<W>(key_shl<W>(key_shr<W>(x, 4), 2), 3);
-  const uint64_t p = i + sv_lower<W>(Zo, key_shr<W>(x, 2)) + sv_upper<W>(Zi, hi3);
+  uint64_t ro, ri;
+  sv_lower_upper<W>(Zo, key_shr<W>(x, 2), Zi, hi3, &ro, &ri);
+  const uint64_t p = i + ro + ri;
   const uint8_t f = fl[i];
   Wb[p] = (uint8_t)(((x.w[W - 1] & 3) + 1) | ((f & 1) ? 8 : 0));
   mult[p] = cnt[i];
