@@ -108,12 +108,21 @@ __global__ void k_row_flags(SortedView E, int k, uint8_t* __restrict__ fl) {
 // Split of the flagged edges into 4 classes, keeping edge order within a
 // class.  mode 0: '$' rows, class = label, value = target vertex P(z);
 // mode 1: dummy rows, class = last base of the source, value = dummy key.
-constexpr int SPLIT_IPT = 8;
+constexpr int SPLIT_IPT = 8;  // one 8-byte word of flags per thread
 constexpr int SPLIT_TILE = SDBG_BLOCK * SPLIT_IPT;
 
+// The flag bytes of edges [base, base + 8) as one word (one load; byte by
+// byte at the end of the array, zero past it).  base is a multiple of 8.
+DEV uint64_t flags8(const uint8_t* __restrict__ fl, uint64_t n, uint64_t base) {
+  if (base + 8 <= n) return *reinterpret_cast<const uint64_t*>(fl + base);
+  uint64_t f = 0;
+  for (uint64_t q = 0; base + q < n && q < 8; ++q) f |= (uint64_t)fl[base + q] << (8 * q);
+  return f;
+}
+
+// Class and value of flagged edge i.
 template <int W>
-DEV bool split_item(const SortedView& E, const uint8_t* fl, int mode, int k, uint64_t i, uint32_t* cls, Key<W>* val) {
-  if (!(fl[i] & (mode ? 4 : 2))) return false;
+DEV void split_item(const SortedView& E, int mode, int k, uint64_t i, uint32_t* cls, Key<W>* val) {
   Key<W> x = key_load<W>(E.keys + i * W);
   if (mode == 0) {
     *cls = (uint32_t)(x.w[W - 1] & 3);
@@ -124,7 +133,6 @@ DEV bool split_item(const SortedView& E, const uint8_t* fl, int mode, int k, uin
     *cls = (uint32_t)top;
     *val = key_or_low<W>(key_shl<W>(key_lowbits<W>(P, 2 * k - 2), 2), top);
   }
-  return true;
 }
 
 template <int W>
@@ -134,11 +142,14 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_split_count(SortedView E, const 
   if (threadIdx.x < 4) h[threadIdx.x] = 0;
   __syncthreads();
   const uint64_t base = blockIdx.x * (uint64_t)SPLIT_TILE + threadIdx.x * SPLIT_IPT;
+  const uint64_t f8 = flags8(fl, E.n, base);
+  const uint64_t bit = mode ? 4 : 2;
   for (int q = 0; q < SPLIT_IPT; ++q) {
-    uint64_t i = base + q;
+    if (!((f8 >> (8 * q)) & bit)) continue;
     uint32_t cl;
     Key<W> v;
-    if (i < E.n && split_item<W>(E, fl, mode, k, i, &cl, &v)) atomicAdd(&h[cl], 1u);
+    split_item<W>(E, mode, k, base + q, &cl, &v);
+    atomicAdd(&h[cl], 1u);
   }
   __syncthreads();
   if (threadIdx.x < 4) tc[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
@@ -150,12 +161,15 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_split_write(SortedView E, const 
                                                             uint64_t* __restrict__ out) {
   __shared__ uint64_t sc[SDBG_WAVES + 1];
   const uint64_t base = blockIdx.x * (uint64_t)SPLIT_TILE + threadIdx.x * SPLIT_IPT;
+  const uint64_t f8 = flags8(fl, E.n, base);
+  const uint64_t bit = mode ? 4 : 2;
   uint64_t packed = 0;  // 4 x 16-bit per-class counts of this thread
   for (int q = 0; q < SPLIT_IPT; ++q) {
-    uint64_t i = base + q;
+    if (!((f8 >> (8 * q)) & bit)) continue;
     uint32_t cl;
     Key<W> v;
-    if (i < E.n && split_item<W>(E, fl, mode, k, i, &cl, &v)) packed += 1ull << (16 * cl);
+    split_item<W>(E, mode, k, base + q, &cl, &v);
+    packed += 1ull << (16 * cl);
   }
   uint64_t tot;
   uint64_t ex = block_excl_scan<uint64_t>(packed, sc, &tot);
@@ -163,10 +177,11 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_split_write(SortedView E, const 
 #pragma unroll
   for (int c = 0; c < 4; ++c) pos[c] = tcs[c * ntiles + blockIdx.x] + ((ex >> (16 * c)) & 0xFFFF);
   for (int q = 0; q < SPLIT_IPT; ++q) {
-    uint64_t i = base + q;
+    if (!((f8 >> (8 * q)) & bit)) continue;
     uint32_t cl;
     Key<W> v;
-    if (i < E.n && split_item<W>(E, fl, mode, k, i, &cl, &v)) {
+    split_item<W>(E, mode, k, base + q, &cl, &v);
+    {
       uint64_t p = 0;
 #pragma unroll
       for (int c = 0; c < 4; ++c)
