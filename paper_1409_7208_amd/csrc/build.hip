@@ -219,11 +219,12 @@ __global__ void k_merge4(const uint64_t* __restrict__ in, uint64_t t, const uint
   key_store<W>(out + r * W, x);
 }
 
-// Lower bound of q1 in v1 and upper bound (first key > q2) of q2 in v2,
-// searched in lockstep so that the loads of the two searches overlap.
-template <int W>
-DEV void sv_lower_upper(const SortedView& v1, const Key<W>& q1, const SortedView& v2, const Key<W>& q2,
-                        uint64_t* r1, uint64_t* r2) {
+// Lower bound of q1 in v1 and lower (first key >= q2) or, with UPPER2,
+// upper bound (first key > q2) of q2 in v2, searched in lockstep so that the
+// loads of the two searches overlap.
+template <int W, bool UPPER2>
+DEV void sv_bounds2(const SortedView& v1, const Key<W>& q1, const SortedView& v2, const Key<W>& q2, uint64_t* r1,
+                    uint64_t* r2) {
   const uint32_t b1 = key_bits<W>(q1, v1.kbits - v1.db, v1.db), b2 = key_bits<W>(q2, v2.kbits - v2.db, v2.db);
   uint64_t lo1 = v1.dir[b1], hi1 = v1.dir[b1 + 1], lo2 = v2.dir[b2], hi2 = v2.dir[b2 + 1];
   while (lo1 < hi1 || lo2 < hi2) {
@@ -239,7 +240,7 @@ DEV void sv_lower_upper(const SortedView& v1, const Key<W>& q1, const SortedView
         hi1 = m1;
     }
     if (a2) {
-      if (!key_less<W>(q2, k2))
+      if (UPPER2 ? !key_less<W>(q2, k2) : key_less<W>(k2, q2))
         lo2 = m2 + 1;
       else
         hi2 = m2;
@@ -259,7 +260,7 @@ __global__ void k_place_real(SortedView E, const uint32_t* __restrict__ cnt, con
   const Key<W> x = key_load<W>(E.keys + i * W);
   const Key<W> hi3 = key_or_low<W>(key_shl<W>(key_shr<W>(x, 4), 2), 3);
   uint64_t ro, ri;
-  sv_lower_upper<W>(Zo, key_shr<W>(x, 2), Zi, hi3, &ro, &ri);
+  sv_bounds2<W, true>(Zo, key_shr<W>(x, 2), Zi, hi3, &ro, &ri);
   const uint64_t p = i + ro + ri;
   const uint8_t f = fl[i];
   Wb[p] = (uint8_t)(((x.w[W - 1] & 3) + 1) | ((f & 1) ? 8 : 0));
@@ -274,7 +275,9 @@ __global__ void k_place_zout(SortedView E, SortedView Zo, SortedView Zi, uint8_t
   if (j >= Zo.n) return;
   const Key<W> z = key_load<W>(Zo.keys + j * W);
   const Key<W> hi3 = key_or_low<W>(key_shl<W>(key_shr<W>(z, 2), 2), 3);
-  const uint64_t p = j + sv_lower<W>(E, key_shl<W>(z, 2)) + sv_upper<W>(Zi, hi3);
+  uint64_t re, ri;
+  sv_bounds2<W, true>(E, key_shl<W>(z, 2), Zi, hi3, &re, &ri);
+  const uint64_t p = j + re + ri;
   Wb[p] = 0;
   mult[p] = 0;
   rf[p] = 1;
@@ -287,24 +290,52 @@ __global__ void k_place_zin(SortedView E, SortedView Zo, SortedView Zi, uint8_t*
   if (j >= Zi.n) return;
   const Key<W> y = key_load<W>(Zi.keys + j * W);
   const Key<W> hv = key_shr<W>(y, 2);
-  const uint64_t p = j + sv_lower<W>(E, key_shl<W>(hv, 4)) + sv_lower<W>(Zo, key_shl<W>(hv, 2));
+  uint64_t re, ro;
+  sv_bounds2<W, false>(E, key_shl<W>(hv, 4), Zo, key_shl<W>(hv, 2), &re, &ro);
+  const uint64_t p = j + re + ro;
   const bool last = j + 1 == Zi.n || !key_eq<W>(key_shr<W>(key_load<W>(Zi.keys + (j + 1) * W), 2), hv);
   Wb[p] = (uint8_t)((y.w[W - 1] & 3) + 1);
   mult[p] = 0;
   rf[p] = (uint8_t)(4 | (last ? 1 : 0));
 }
 
-// One wavefront ballot over 64 consecutive rows is one word of each vector.
+// Each thread takes 8 consecutive rows (one 8-byte load of their flags) and
+// makes one byte of each bit vector; the 8 threads of a group of 64 rows
+// OR their bytes together (3 shuffles), and the group's first thread
+// writes the word.
 __global__ __launch_bounds__(SDBG_BLOCK) void k_pack_bits(const uint8_t* __restrict__ rf, uint64_t m,
                                                           uint64_t* __restrict__ last, uint64_t* __restrict__ valid,
                                                           uint64_t* __restrict__ tip) {
-  uint64_t i = blockIdx.x * (uint64_t)SDBG_BLOCK + threadIdx.x;
-  uint8_t f = i < m ? rf[i] : 0;
-  uint64_t bl = __ballot(f & 1), bv = __ballot(f & 2), bt = __ballot(f & 4);
-  if ((threadIdx.x & 63) == 0 && i < m) {
-    last[i >> 6] = bl;
-    valid[i >> 6] = bv;
-    tip[i >> 6] = bt;
+  const uint64_t t = blockIdx.x * (uint64_t)SDBG_BLOCK + threadIdx.x;
+  const uint64_t r0 = t * 8;
+  uint64_t f = 0;
+  if (r0 + 8 <= m) {
+    f = *reinterpret_cast<const uint64_t*>(rf + r0);
+  } else {
+    for (uint64_t q = 0; r0 + q < m && q < 8; ++q) f |= (uint64_t)rf[r0 + q] << (8 * q);
+  }
+  uint64_t bl = 0, bv = 0, bt = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint64_t b = f >> (8 * q);
+    bl |= (b & 1) << q;
+    bv |= ((b >> 1) & 1) << q;
+    bt |= ((b >> 2) & 1) << q;
+  }
+  const int sh = 8 * (int)(threadIdx.x & 7);
+  bl <<= sh;
+  bv <<= sh;
+  bt <<= sh;
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) {
+    bl |= __shfl_xor(bl, o, 64);
+    bv |= __shfl_xor(bv, o, 64);
+    bt |= __shfl_xor(bt, o, 64);
+  }
+  if ((threadIdx.x & 7) == 0 && r0 < m) {
+    last[r0 >> 6] = bl;
+    valid[r0 >> 6] = bv;
+    tip[r0 >> 6] = bt;
   }
 }
 
@@ -460,7 +491,7 @@ struct Builder {
     DBuf<uint64_t> last = c.buf<uint64_t>(words), valid = c.buf<uint64_t>(words), tip = c.buf<uint64_t>(words);
     {
       Stage st_(c, "pack_bits", m + 3 * words * 8);
-      k_pack_bits<<<grid1(m), SDBG_BLOCK, 0, c.s>>>(rf.get(), m, last.get(), valid.get(), tip.get());
+      k_pack_bits<<<grid1(ceil_div(m, 8)), SDBG_BLOCK, 0, c.s>>>(rf.get(), m, last.get(), valid.get(), tip.get());
       c.check_launch("pack_bits");
     }
     DBuf<uint64_t> F = c.buf<uint64_t>(6);
