@@ -108,7 +108,7 @@ __global__ void k_row_flags(SortedView E, int k, uint8_t* __restrict__ fl) {
 // Split of the flagged edges into 4 classes, keeping edge order within a
 // class.  mode 0: '$' rows, class = label, value = target vertex P(z);
 // mode 1: dummy rows, class = last base of the source, value = dummy key.
-constexpr int SPLIT_IPT = 8;  // one 8-byte word of flags per thread
+constexpr int SPLIT_IPT = 32;  // four 8-byte words of flags per thread
 constexpr int SPLIT_TILE = SDBG_BLOCK * SPLIT_IPT;
 
 // The flag bytes of edges [base, base + 8) as one word (one load; byte by
@@ -142,10 +142,13 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_split_count(SortedView E, const 
   if (threadIdx.x < 4) h[threadIdx.x] = 0;
   __syncthreads();
   const uint64_t base = blockIdx.x * (uint64_t)SPLIT_TILE + threadIdx.x * SPLIT_IPT;
-  const uint64_t f8 = flags8(fl, E.n, base);
   const uint64_t bit = mode ? 4 : 2;
+  uint64_t f8[SPLIT_IPT / 8];
+#pragma unroll
+  for (int u = 0; u < SPLIT_IPT / 8; ++u) f8[u] = flags8(fl, E.n, base + 8 * u);
+#pragma unroll
   for (int q = 0; q < SPLIT_IPT; ++q) {
-    if (!((f8 >> (8 * q)) & bit)) continue;
+    if (!((f8[q >> 3] >> (8 * (q & 7))) & bit)) continue;
     uint32_t cl;
     Key<W> v;
     split_item<W>(E, mode, k, base + q, &cl, &v);
@@ -161,11 +164,14 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_split_write(SortedView E, const 
                                                             uint64_t* __restrict__ out) {
   __shared__ uint64_t sc[SDBG_WAVES + 1];
   const uint64_t base = blockIdx.x * (uint64_t)SPLIT_TILE + threadIdx.x * SPLIT_IPT;
-  const uint64_t f8 = flags8(fl, E.n, base);
   const uint64_t bit = mode ? 4 : 2;
+  uint64_t f8[SPLIT_IPT / 8];
+#pragma unroll
+  for (int u = 0; u < SPLIT_IPT / 8; ++u) f8[u] = flags8(fl, E.n, base + 8 * u);
   uint64_t packed = 0;  // 4 x 16-bit per-class counts of this thread
+#pragma unroll
   for (int q = 0; q < SPLIT_IPT; ++q) {
-    if (!((f8 >> (8 * q)) & bit)) continue;
+    if (!((f8[q >> 3] >> (8 * (q & 7))) & bit)) continue;
     uint32_t cl;
     Key<W> v;
     split_item<W>(E, mode, k, base + q, &cl, &v);
@@ -176,8 +182,9 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_split_write(SortedView E, const 
   uint64_t pos[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) pos[c] = tcs[c * ntiles + blockIdx.x] + ((ex >> (16 * c)) & 0xFFFF);
+#pragma unroll
   for (int q = 0; q < SPLIT_IPT; ++q) {
-    if (!((f8 >> (8 * q)) & bit)) continue;
+    if (!((f8[q >> 3] >> (8 * (q & 7))) & bit)) continue;
     uint32_t cl;
     Key<W> v;
     split_item<W>(E, mode, k, base + q, &cl, &v);
