@@ -31,8 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE counter runs scaled by a 1 GiB device copy (profiles/), valid
 # while the kernel sources hash to the value recorded there.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_metagenome_k31.md")
-KERNEL_SOURCES = ["paper_1409_7208_amd/csrc/count.hip", "paper_1409_7208_amd/csrc/device.h",
-                  "paper_1409_7208_amd/csrc/kernels.h"]
+KERNEL_SOURCES = ["paper_1409_7208_amd/csrc/" + f for f in
+                  ("count.hip", "build.hip", "prims.hip", "device.h", "kernels.h", "prims.h")]
 
 
 def kernel_source_hash() -> str:

@@ -203,7 +203,7 @@ int sdbg_autotune(const sdbg_reads *sets, uint64_t n_sets, const sdbg_params *pa
  * the single-call path (sdbg_count_solid, then sdbg_build if cfg->build),
  * so its results are identical to running it alone.  The device buffers of
  * finished jobs stay cached for the next ones (the memory-adaptive
- * construction of Section 2, third paragraph, under a shared budget). */
+ * construction reported in Section 3, under a shared budget). */
 typedef struct sdbg_server_cfg {
   uint32_t max_jobs;   /* jobs running at once, at most 64; 0 = 4 */
   uint32_t queue_cap;  /* waiting jobs before submit returns SDBG_E_BUSY; 0 = 4096 */

@@ -70,6 +70,8 @@ def _load():
             ctypes.c_void_p, ctypes.c_int,
         ]
         lib.oracle_count_keys.restype = ctypes.c_int
+        lib.oracle_narrow_count.argtypes = [ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32)]
+        lib.oracle_narrow_count.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -164,3 +166,12 @@ def count_keys(seq, offsets, k: int, qkeys: np.ndarray, threads: int | None = No
     if rc != 0:
         raise ValueError(f"oracle_count_keys failed ({rc})")
     return out
+
+
+def narrow_count(c: int) -> int:
+    """A count as the oracle reports it (32 bits); raises OverflowError for a
+    count of 2^32 or more (the oracle never clamps)."""
+    out = ctypes.c_uint32()
+    if _load().oracle_narrow_count(c, ctypes.byref(out)) != 0:
+        raise OverflowError(f"count {c} does not fit 32 bits")
+    return out.value

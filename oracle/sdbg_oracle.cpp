@@ -174,10 +174,19 @@ typedef struct oracle_graph {
 
 void oracle_free(void* p) { std::free(p); }
 
+// A (k+1)-mer count as reported (32 bits): 0 and *out = c if it fits, else
+// -3 (the input has a (k+1)-mer seen 2^32 times or more; not clamped).
+int oracle_narrow_count(uint64_t c, uint32_t* out) {
+  if (c > 0xffffffffull) return -3;
+  *out = (uint32_t)c;
+  return 0;
+}
+
 // Counts of every (k+1)-mer over both strands, solid filter (count >= d) and,
 // if mercy != 0, mercy-kmers.  Outputs the edge set E sorted by key with each
 // edge's count; n_mercy = number of edges added by the mercy rule; n_occ =
-// number of (k+1)-mer occurrences counted (both strands).
+// number of (k+1)-mer occurrences counted (both strands).  Returns -3 if an
+// output edge's count does not fit 32 bits.
 int oracle_count_solid(const uint8_t* seq, const uint64_t* offsets, uint64_t n_reads, uint32_t k, uint32_t d,
                        uint32_t mercy, uint64_t** keys_out, uint32_t** counts_out, uint64_t* n_out,
                        uint64_t* n_mercy_out, uint64_t* n_occ_out) {
@@ -233,17 +242,21 @@ int oracle_count_solid(const uint8_t* seq, const uint64_t* offsets, uint64_t n_r
     }
   }
 
-  // E = solid + mercy, sorted by key.
+  // E = solid + mercy, sorted by key.  Counts are reported in 32 bits; a
+  // count that does not fit is an error, never clamped.
   const int w = key_words(K);
   std::vector<std::pair<std::vector<uint64_t>, uint32_t>> edges;
+  bool too_many = false;
   auto add = [&](const std::string& x) {
     std::vector<uint64_t> key(w);
     edge_key(x, K, key.data());
-    uint64_t c = count[x];
-    edges.push_back({key, (uint32_t)(c > 0xffffffffull ? 0xffffffffull : c)});
+    uint32_t c32 = 0;
+    if (oracle_narrow_count(count[x], &c32) != 0) too_many = true;
+    edges.push_back({key, c32});
   };
   for (const std::string& x : solid) add(x);
   for (const std::string& x : mercy_set) add(x);
+  if (too_many) return -3;
   KeyLess less{w};
   std::sort(edges.begin(), edges.end(), [&](const auto& a, const auto& b) { return less(a.first, b.first); });
 

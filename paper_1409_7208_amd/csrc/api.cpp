@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "abi_common.h"
+#include "prims.h"
 
 namespace sdbg_abi {
 
@@ -137,6 +138,17 @@ uint64_t device_budget(const sdbg_params* p) {
   return (uint64_t)(0.8 * (double)(fr + sdbg::Pool::get().cached_bytes()));
 }
 
+// Every field of the caller's sdbg_tune, and nothing past it.
+void tune_to_abi(const sdbg::SortTune& x, sdbg_tune* t) {
+  t->digit_bits = (uint32_t)x.digit_bits;
+  t->tile_shift = (uint32_t)x.tile_shift;
+  t->leaf_wg_per_cu = (uint32_t)x.leaf_wg_per_cu;
+  t->leaf_cap_shift = (uint32_t)x.leaf_cap_shift;
+  t->first_bits = (uint32_t)x.first_bits;
+  t->mercy_shift = (uint32_t)x.mercy_shift;
+  t->reserved[0] = t->reserved[1] = 0;
+}
+
 }  // namespace sdbg_abi
 
 using namespace sdbg_abi;
@@ -196,6 +208,9 @@ int sdbg_count_solid(const sdbg_reads* reads, const sdbg_params* params, sdbg_ed
       uint64_t first = c.d2h_one(reads->offsets);
       R.n_bases = c.d2h_one(reads->offsets + reads->n_reads);
       SDBG_CHECK(first == 0, SDBG_E_INVAL, "offsets[0] must be 0");
+      // with offsets[0] = 0 and no decrease, every read lies in [0, n_bases)
+      SDBG_CHECK(sdbg::nondecreasing(reads->offsets, reads->n_reads, c), SDBG_E_INVAL,
+                 "offsets must be non-decreasing");
       SDBG_CHECK(R.n_bases == 0 || reads->seq, SDBG_E_INVAL, "null seq");
     } else {
       const uint64_t* o = reads->offsets;
@@ -413,14 +428,7 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
 int sdbg_tune_get(sdbg_tune* t) {
   return guarded([&]() -> int {
     SDBG_CHECK(t, SDBG_E_INVAL, "null argument");
-    const sdbg::SortTune x = sdbg::sort_tune();
-    t->digit_bits = (uint32_t)x.digit_bits;
-    t->tile_shift = (uint32_t)x.tile_shift;
-    t->leaf_wg_per_cu = (uint32_t)x.leaf_wg_per_cu;
-    t->leaf_cap_shift = (uint32_t)x.leaf_cap_shift;
-    t->first_bits = (uint32_t)x.first_bits;
-    t->mercy_shift = (uint32_t)x.mercy_shift;
-    t->reserved[0] = t->reserved[1] = 0;
+    tune_to_abi(sdbg::sort_tune(), t);
     return SDBG_OK;
   });
 }
@@ -489,14 +497,7 @@ int sdbg_autotune(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* pa
       throw;
     }
     sdbg::set_sort_tune(cur);
-    if (best) {
-      best->digit_bits = (uint32_t)cur.digit_bits;
-      best->tile_shift = (uint32_t)cur.tile_shift;
-      best->leaf_wg_per_cu = (uint32_t)cur.leaf_wg_per_cu;
-      best->leaf_cap_shift = (uint32_t)cur.leaf_cap_shift;
-      best->first_bits = (uint32_t)cur.first_bits;
-      best->reserved[0] = best->reserved[1] = best->reserved[2] = 0;
-    }
+    if (best) tune_to_abi(cur, best);
     return SDBG_OK;
   });
 }

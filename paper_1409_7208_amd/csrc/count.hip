@@ -386,18 +386,68 @@ struct SegView {
   uint64_t n;
 };
 
+// st[0] = oversized segments that still have key bits to cut, st[1] = their
+// keys, st[2] = how many of them came whole out of their parent's cut (D
+// flag set by k_seg_newwrite).
 __global__ void k_seg_stats(SegView v, uint64_t cap, unsigned long long* st) {
   uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  unsigned long long n = 0, sum = 0;
+  unsigned long long n = 0, sum = 0, whole = 0;
   if (s < v.n && v.len[s] > cap && v.bit[s] > 0) {
     n = 1;
     sum = v.len[s];
+    whole = v.D[s] != 0;
   }
   n = wave_sum(n);
   sum = wave_sum(sum);
+  whole = wave_sum(whole);
   if ((threadIdx.x & 63) == 0 && n) {
     atomicAdd(&st[0], n);
     atomicAdd(&st[1], sum);
+    if (whole) atomicAdd(&st[2], whole);
+  }
+}
+
+// An oversized segment that a cut left whole (all its keys fell into one
+// digit) may hold many copies of a few keys, for which cutting a few bits
+// per level would take as many levels as the key has bits.  Its keys share
+// every bit above the highest bit in which some key differs from the first
+// one, so `bit` drops to that bit + 1; all keys equal -> 0 (the leaf then
+// counts the run).  Workgroups stride over the segments.
+template <int W>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_seg_squeeze(SegView v, uint64_t* const* __restrict__ bufs,
+                                                            uint64_t cap) {
+  __shared__ uint64_t red[SDBG_WAVES][W];
+  for (uint64_t s = blockIdx.x; s < v.n; s += gridDim.x) {
+    if (!v.D[s] || v.len[s] <= cap || v.bit[s] == 0) continue;  // uniform over the workgroup
+    const uint64_t* src = bufs[v.buf[s]] + v.off[s] * W;
+    const uint64_t len = v.len[s];
+    const Key<W> k0 = key_load_g<W>(src);
+    uint64_t x[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) x[j] = 0;
+    for (uint64_t i = threadIdx.x; i < len; i += SDBG_BLOCK) {
+      const Key<W> ki = key_load_g<W>(src + i * W);
+#pragma unroll
+      for (int j = 0; j < W; ++j) x[j] |= ki.w[j] ^ k0.w[j];
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+      for (int o = 32; o > 0; o >>= 1) x[j] |= __shfl_xor(x[j], o, 64);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int j = 0; j < W; ++j) red[threadIdx.x >> 6][j] = x[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int nb = 0;  // highest differing bit + 1 (word 0 is the most significant)
+      for (int j = 0; j < W && !nb; ++j) {
+        uint64_t o = 0;
+        for (int q = 0; q < SDBG_WAVES; ++q) o |= red[q][j];
+        if (o) nb = 64 * (W - 1 - j) + 64 - __clzll(o);
+      }
+      if (nb < (int)v.bit[s]) v.bit[s] = (uint16_t)nb;
+      v.D[s] = 0;
+    }
+    __syncthreads();
   }
 }
 
@@ -555,6 +605,7 @@ __global__ void k_seg_newwrite(SegView v, int tk, const uint64_t* __restrict__ t
       nv.len[p] = v.len[s];
       nv.bit[p] = v.bit[s];
       nv.buf[p] = v.buf[s];
+      nv.D[p] = 0;
     }
     return;
   }
@@ -570,6 +621,7 @@ __global__ void k_seg_newwrite(SegView v, int tk, const uint64_t* __restrict__ t
       nv.len[q] = b - a;
       nv.bit[q] = (uint16_t)(v.bit[s] - D);
       nv.buf[q] = (uint8_t)(v.buf[s] ^ 1);
+      nv.D[q] = (uint8_t)(b - a == v.len[s]);  // the cut left it whole
     }
     p += __shfl(incl, 63, 64);
   }
@@ -651,7 +703,9 @@ __global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* con
     if (len > CAP) {
       fetch(s + G);
       if (threadIdx.x == 0) {
-        const uint32_t c = len > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)len;
+        // a partition group holds fewer than 2^32 keys (checked on the host
+        // before the keys are extracted), so a run's count fits 32 bits
+        const uint32_t c = (uint32_t)len;
         const bool solid = len >= dmin;
         if (solid || want_low) cn[0] = c;
         nsolid[s] = solid;
@@ -1814,15 +1868,24 @@ struct Counter {
   // Cut every segment longer than CAP (while it has key bits left) until
   // all fit a leaf; data ping-pongs between bufs[0] and bufs[1] at equal
   // offsets.
-  void refine(SegList& L, uint64_t* const* d_bufs) {
-    DBuf<unsigned long long> st = c.buf<unsigned long long>(2);
-    for (int level = 0; level < 64; ++level) {
+  // Every level takes at least one bit off each oversized segment, so
+  // kbits (the segments' largest `bit`) levels always suffice.
+  void refine(SegList& L, uint64_t* const* d_bufs, int kbits) {
+    DBuf<unsigned long long> st = c.buf<unsigned long long>(3);
+    for (int level = 0; level <= kbits; ++level) {
       if (L.n == 0) return;
-      fill<uint64_t>(reinterpret_cast<uint64_t*>(st.get()), 2, 0, c);
-      k_seg_stats<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), leaf_cap(), st.get());
-      c.check_launch("seg_stats");
-      unsigned long long hs[2];
-      c.d2h(hs, st.get(), 2);
+      unsigned long long hs[3];
+      for (int pass = 0; pass < 2; ++pass) {
+        fill<uint64_t>(reinterpret_cast<uint64_t*>(st.get()), 3, 0, c);
+        k_seg_stats<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), leaf_cap(), st.get());
+        c.check_launch("seg_stats");
+        c.d2h(hs, st.get(), 3);
+        if (hs[2] == 0 || pass == 1) break;
+        // segments a cut left whole: skip their common bits
+        k_seg_squeeze<W><<<(unsigned)std::min<uint64_t>(L.n, 4096), SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs,
+                                                                                          leaf_cap());
+        c.check_launch("seg_squeeze");
+      }
       if (hs[0] == 0) return;
       const uint64_t avg = hs[1] / hs[0];
       VLOG("refine level %d: %llu segments, %llu oversized holding %llu keys", level, (unsigned long long)L.n,
@@ -1926,7 +1989,7 @@ struct Counter {
     c.h2d(L.bit.get(), &bit, 1);
     c.h2d(L.buf.get(), &b0, 1);
     c.h2d(L.D.get(), &b0, 1);
-    refine(L, db.get());
+    refine(L, db.get(), kb);
     DBuf<uint32_t> ocnt;
     DBuf<uint64_t> lk;
     DBuf<uint32_t> lc;
@@ -2266,7 +2329,7 @@ struct Counter {
         L.alloc(c, nbins);
         k_seg_init<<<grid1(nbins), SDBG_BLOCK, 0, c.s>>>(tab.get(), ntiles, nbins, NG, kb - ea.dbits, L.view());
         c.check_launch("seg_init");
-        refine(L, db.get());
+        refine(L, db.get(), kb - ea.dbits);
         leaves(L, NG, db.get(), cnt.get(), P.d, want_low, s_keys[gi], s_cnt[gi], &s_n[gi], l_keys[gi], l_cnt[gi],
                &l_n[gi]);
       }
@@ -2371,23 +2434,6 @@ struct Counter {
       scan_excl<uint64_t, uint64_t>(mcount.get(), mpos.get(), R.n_reads, tot.get(), c);
       const uint64_t NC = c.d2h_one(tot.get());
       VLOG("mercy: %llu solid edges, %llu candidate keys", (unsigned long long)nS, (unsigned long long)NC);
-      if (const char* dd = std::getenv("SDBG_DUMP_DIR")) {  // debugging aid: intermediate arrays
-        std::vector<uint8_t> h1(sfl.get() ? nS : 0), h2(NW);
-        std::vector<uint64_t> h3(R.n_reads);
-        if (sfl.get()) c.d2h(h1.data(), sfl.get(), nS);
-        c.d2h(h2.data(), wf.get(), NW);
-        c.d2h(h3.data(), mcount.get(), R.n_reads);
-        auto dump = [&](const char* name, const void* p, size_t bytes) {
-          std::string path = std::string(dd) + "/" + name;
-          if (FILE* f = std::fopen(path.c_str(), "wb")) {
-            std::fwrite(p, 1, bytes, f);
-            std::fclose(f);
-          }
-        };
-        if (sfl.get()) dump("sfl.bin", h1.data(), nS);
-        dump("wf.bin", h2.data(), NW);
-        dump("mcount.bin", h3.data(), 8 * R.n_reads);
-      }
       if (NC) {
         DBuf<uint64_t> cand = c.buf<uint64_t>(NC * W);
         // reads with candidates, in read order
@@ -2503,7 +2549,7 @@ struct Counter {
     k_seg_init_sets<<<grid1(S * nbins), SDBG_BLOCK, 0, c.s>>>(tab.get(), std_.get(), S, ea.dbits, N, kb - ea.dbits,
                                                               L.view());
     c.check_launch("seg_init_sets");
-    refine(L, db.get());
+    refine(L, db.get(), kb - ea.dbits);
     DBuf<uint64_t> Sk, Lk, spos;
     DBuf<uint32_t> Sc, Lc;
     uint64_t nS = 0, nL = 0;

@@ -16,4 +16,7 @@ void fill(T* p, uint64_t n, T v, Ctx& c);
 template <typename Tin, typename Tout>
 void scan_excl(const Tin* in, Tout* out, uint64_t n, uint64_t* d_total, Ctx& c);
 
+// True iff off[0..n] never decreases (n + 1 entries; one read-back).
+bool nondecreasing(const uint64_t* off, uint64_t n, Ctx& c);
+
 }  // namespace sdbg

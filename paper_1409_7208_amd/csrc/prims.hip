@@ -106,6 +106,25 @@ void scan_excl(const Tin* in, Tout* out, uint64_t n, uint64_t* d_total, Ctx& c) 
   c.check_launch("scan_down");
 }
 
+__global__ void k_decreasing(const uint64_t* __restrict__ off, uint64_t n, uint32_t* __restrict__ flag) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (uint64_t j = i; j < n; j += stride) bad |= off[j + 1] < off[j];
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+bool nondecreasing(const uint64_t* off, uint64_t n, Ctx& c) {
+  if (n == 0) return true;
+  DBuf<uint32_t> flag = c.buf<uint32_t>(1);
+  fill<uint32_t>(flag.get(), 1, 0u, c);
+  uint64_t blocks = ceil_div(n, SDBG_BLOCK);
+  if (blocks > 65536) blocks = 65536;
+  k_decreasing<<<(unsigned)blocks, SDBG_BLOCK, 0, c.s>>>(off, n, flag.get());
+  c.check_launch("offsets check");
+  return c.d2h_one(flag.get()) == 0;
+}
+
 template void scan_excl<uint64_t, uint64_t>(const uint64_t*, uint64_t*, uint64_t, uint64_t*, Ctx&);
 template void scan_excl<uint32_t, uint32_t>(const uint32_t*, uint32_t*, uint64_t, uint64_t*, Ctx&);
 template void scan_excl<uint32_t, uint64_t>(const uint32_t*, uint64_t*, uint64_t, uint64_t*, Ctx&);

@@ -192,3 +192,33 @@ def test_autotune_keeps_results():
     finally:
         sdbg.tune_set(None)
     _close(ref)
+
+
+def test_autotune_writes_only_its_struct():
+    """sdbg_autotune fills every field of the caller's sdbg_tune (including
+    mercy_shift) and writes nothing past its end."""
+    import ctypes
+
+    lib = sdbg.load()
+    sdbg._tune_api(lib)
+    sets = [synth.batch_set(i, read_scale=0.002) for i in range(8)]
+    dev = [to_device(rs) for rs in sets]
+    arr = (sdbg._Reads * len(dev))()
+    keep = []
+    for i, (seq, off) in enumerate(dev):
+        r, kp = sdbg._reads_struct(seq, off)
+        arr[i] = r
+        keep += kp
+    size = ctypes.sizeof(sdbg._Tune)
+    raw = (ctypes.c_uint8 * (size + 64))(*([0xAB] * (size + 64)))
+    p = sdbg._Params(31, 2, 0, 8, 0, None)
+    try:
+        sdbg.tune_set({"mercy_shift": 3})
+        rc = lib.sdbg_autotune(arr, len(dev), ctypes.byref(p), 1, ctypes.cast(raw, ctypes.POINTER(sdbg._Tune)))
+        assert rc == 0, lib.sdbg_last_error()
+        assert bytes(raw[size:]) == b"\xab" * 64
+        t = ctypes.cast(raw, ctypes.POINTER(sdbg._Tune)).contents
+        assert sdbg._tune_dict(t) == sdbg.tune_get()
+        assert t.mercy_shift == 3 and list(t.reserved) == [0, 0]
+    finally:
+        sdbg.tune_set(None)

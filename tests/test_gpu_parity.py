@@ -212,3 +212,36 @@ def test_mercy_lookup_table_overfull_paths(k):
             assert np.array_equal(keys, o.keys) and np.array_equal(cnt, o.counts)
     finally:
         sdbg.tune_set(None)
+
+
+@pytest.mark.parametrize("k,copies", [(31, 2100), (81, 1100), (99, 1100)])
+@pytest.mark.parametrize("cap_shift", [0, 1])
+def test_many_copies_of_one_read(k, copies, cap_shift):
+    """One 150 bp read repeated a little more often than a leaf holds (an
+    amplicon or spike-in), plus random reads: every window of that read is a
+    key whose run is longer than a leaf, so the partition must isolate the
+    run without cutting one digit per level through all 2(k+1) key bits."""
+    rng = np.random.Generator(np.random.PCG64([0x14097208, 99, k, copies]))
+    read = "".join("ACGT"[c] for c in rng.integers(0, 4, 150))
+    rs_bg = synth.random_small(400, k + 1, k + 60, 3000, 0.02, 7 + k)
+    reads = [r.decode() for r in rs_bg.reads()] + [read] * copies
+    rs = synth.from_strings(reads, k, 2, True)
+    rs.name = f"{copies} copies of one read"
+    try:
+        sdbg.tune_set({"leaf_cap_shift": cap_shift})
+        _parity(rs, k, 2, True)
+    finally:
+        sdbg.tune_set(None)
+
+
+def test_device_offsets_must_not_decrease():
+    """Device-resident offsets are validated like host ones: a decreasing
+    pair is an argument error, before any read is touched."""
+    import torch
+
+    seq = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    for offs in ([0, 40, 10, 64], [0, 64, 63], [0, 1 << 40, 100]):
+        off = torch.tensor(offs, dtype=torch.int64, device="cuda")
+        with pytest.raises(sdbg.SdbgError) as ei:
+            sdbg.count_solid(seq, off, 5, 2, True)
+        assert ei.value.code == -1 and "non-decreasing" in str(ei.value)

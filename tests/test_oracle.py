@@ -193,3 +193,14 @@ def test_empty_and_short_inputs():
         assert e.keys.shape[0] == 0 and e.n_occ == 0
         g = oracle.build_graph(e.keys, e.counts, 3)
         assert g.m == 0 and g.t == 0 and g.F.tolist() == [0] * 6
+
+
+def test_count_width_is_checked_not_clamped():
+    # Counts are reported in 32 bits: a count of 2^32 or more is an error of
+    # the oracle (count_solid returns -3 for it), never a clamped value.
+    assert oracle.narrow_count(0) == 0
+    assert oracle.narrow_count(2**32 - 1) == 2**32 - 1
+    with pytest.raises(OverflowError):
+        oracle.narrow_count(2**32)
+    with pytest.raises(OverflowError):
+        oracle.narrow_count(2**63)
