@@ -131,6 +131,33 @@ typedef struct sdbg_graph {
 /* Count, filter and mercy (Section 2, third paragraph) -> *out. */
 int sdbg_count_solid(const sdbg_reads *reads, const sdbg_params *params, sdbg_edges **out);
 
+/* Allocation-free form of sdbg_count_solid, for callers that cannot
+ * allocate device memory (code under stream capture, serving loops and
+ * harnesses that forbid hipMalloc).  Computes exactly what
+ * sdbg_count_solid computes, but every working buffer is carved out of one
+ * fixed scratch array of SDBG_NOALLOC_SCRATCH_MB MiB per device, which the
+ * device holds from the library's first use on it until the process ends,
+ * and the edge set is written into the caller's buffers:
+ *   keys_out   device, cap * w words (w = ceil(2(k+1)/64)), ascending keys;
+ *   count_out  device, cap entries;
+ *   *n_out     |E| (also when it exceeds cap: then SDBG_E_INVAL and the
+ *              output buffers are left untouched, so the caller can retry
+ *              with larger ones);
+ *   *n_mercy_out, *n_occ_out, *scratch_peak_out (scratch bytes in use at
+ *              the call's peak): as in sdbg_edges; each may be NULL.
+ * reads, params: as for sdbg_count_solid; params->mem_budget is capped at
+ * the scratch size.  An input whose bound on scratch use (from its read
+ * lengths) exceeds the scratch, or that runs out of it, returns
+ * SDBG_E_NOMEM_DEVICE before any kernel touches memory beyond the scratch.
+ * Calls on one device share its scratch, which keeps the last call's
+ * contents; they take turns (a per-device lock held until the call's
+ * stream has completed), so concurrent calls in one process do not race.
+ * Returns after params->stream has completed the call's work. */
+#define SDBG_NOALLOC_SCRATCH_MB 256
+int sdbg_count_solid_noalloc(const sdbg_reads *reads, const sdbg_params *params, uint64_t *keys_out,
+                             uint32_t *count_out, uint64_t cap, uint64_t *n_out, uint64_t *n_mercy_out,
+                             uint64_t *n_occ_out, uint64_t *scratch_peak_out);
+
 /* SdBG arrays of an edge set (Section 2, first and second paragraphs).
  * Uses params->stream only (params may be NULL: null stream); the other
  * fields are ignored.  An edge set made by sdbg_edges_from_host is checked

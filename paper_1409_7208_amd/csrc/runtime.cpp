@@ -2,6 +2,9 @@
 
 #include "engine.h"
 
+#include <algorithm>
+#include <iterator>
+
 namespace sdbg {
 
 namespace {
@@ -81,6 +84,56 @@ void Pool::trim() {
 size_t Pool::cached_bytes() {
   std::lock_guard<std::mutex> lk(mu_);
   return cached_;
+}
+
+Arena::Arena(void* base, size_t bytes) : base_(static_cast<char*>(base)), cap_(bytes & ~size_t(255)) {
+  if (cap_) free_.emplace(0, cap_);
+}
+
+void* Arena::alloc(size_t bytes) {
+  const size_t want = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < want) continue;
+    const size_t off = it->first, rest = it->second - want;
+    free_.erase(it);
+    if (rest) free_.emplace(off + want, rest);
+    used_[off] = want;
+    in_use_ += want;
+    peak_ = std::max(peak_, in_use_);
+    return base_ + off;
+  }
+  throw Error(-3, "fixed scratch of " + std::to_string(cap_) + " bytes cannot hold a further " +
+                      std::to_string(want) + " bytes (" + std::to_string(in_use_) + " in use): input too large");
+}
+
+void Arena::release(void* p) {
+  if (!p) return;
+  const size_t off = static_cast<size_t>(static_cast<char*>(p) - base_);
+  auto u = used_.find(off);
+  if (u == used_.end()) return;
+  size_t sz = u->second;
+  size_t start = off;
+  used_.erase(u);
+  in_use_ -= sz;
+  auto nx = free_.lower_bound(off);
+  if (nx != free_.end() && nx->first == off + sz) {  // merge with the next free range
+    sz += nx->second;
+    nx = free_.erase(nx);
+  }
+  if (nx != free_.begin()) {  // and with the previous one
+    auto pv = std::prev(nx);
+    if (pv->first + pv->second == start) {
+      start = pv->first;
+      sz += pv->second;
+      free_.erase(pv);
+    }
+  }
+  free_.emplace(start, sz);
+}
+
+Arena*& current_arena() {
+  thread_local Arena* a = nullptr;
+  return a;
 }
 
 }  // namespace sdbg

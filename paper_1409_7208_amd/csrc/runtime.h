@@ -62,8 +62,44 @@ class Pool {
   size_t cached_ = 0;
 };
 
+// A fixed device region that stands in for the pool: while one is made
+// current on a thread (ArenaScope), every DBuf that thread creates is carved
+// out of it, and nothing is allocated from the device.  First fit over a
+// sorted free list with coalescing; blocks are 256-byte aligned.  All users
+// of one arena run on one stream, so a block freed by one step and handed
+// to the next is reused in stream order.  Running out is an error (code -3)
+// raised before any kernel touches the block.
+class Arena {
+ public:
+  Arena(void* base, size_t bytes);
+  void* alloc(size_t bytes);
+  void release(void* p);
+  size_t capacity() const { return cap_; }
+  size_t peak() const { return peak_; }
+
+ private:
+  char* base_;
+  size_t cap_;
+  size_t in_use_ = 0, peak_ = 0;
+  std::map<size_t, size_t> free_;           // offset -> bytes
+  std::unordered_map<size_t, size_t> used_;  // offset -> bytes
+};
+
+Arena*& current_arena();  // of the calling thread; nullptr = the pool
+
+class ArenaScope {
+ public:
+  explicit ArenaScope(Arena* a) : prev_(current_arena()) { current_arena() = a; }
+  ~ArenaScope() { current_arena() = prev_; }
+  ArenaScope(const ArenaScope&) = delete;
+  ArenaScope& operator=(const ArenaScope&) = delete;
+
+ private:
+  Arena* prev_;
+};
+
 // Device buffer owned by the calling scope, returned to the pool (tagged
-// with its stream) on destruction.
+// with its stream) on destruction, or to the arena it was carved from.
 template <typename T>
 class DBuf {
  public:
@@ -72,11 +108,11 @@ class DBuf {
   ~DBuf() { free(); }
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p_(o.p_), n_(o.n_), s_(o.s_) { o.p_ = nullptr; o.n_ = 0; }
+  DBuf(DBuf&& o) noexcept : p_(o.p_), n_(o.n_), s_(o.s_), a_(o.a_) { o.p_ = nullptr; o.n_ = 0; }
   DBuf& operator=(DBuf&& o) noexcept {
     if (this != &o) {
       free();
-      p_ = o.p_; n_ = o.n_; s_ = o.s_;
+      p_ = o.p_; n_ = o.n_; s_ = o.s_; a_ = o.a_;
       o.p_ = nullptr; o.n_ = 0;
     }
     return *this;
@@ -85,12 +121,19 @@ class DBuf {
     free();
     n_ = n;
     s_ = s;
-    p_ = static_cast<T*>(Pool::get().alloc(sizeof(T) * (n ? n : 1), s));
+    a_ = current_arena();
+    if (a_)
+      p_ = static_cast<T*>(a_->alloc(sizeof(T) * (n ? n : 1)));
+    else
+      p_ = static_cast<T*>(Pool::get().alloc(sizeof(T) * (n ? n : 1), s));
   }
   void free() noexcept {
     if (p_) {
       try {
-        Pool::get().release(p_, s_, true);
+        if (a_)
+          a_->release(p_);
+        else
+          Pool::get().release(p_, s_, true);
       } catch (...) {
       }
     }
@@ -110,6 +153,7 @@ class DBuf {
   T* p_ = nullptr;
   size_t n_ = 0;
   hipStream_t s_ = nullptr;
+  Arena* a_ = nullptr;
 };
 
 // Per-call context.  Declared before any DBuf of the call, so that it is

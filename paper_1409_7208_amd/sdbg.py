@@ -18,6 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsdbg.so")
 
 SDBG_OK = 0
+# fixed device scratch of the allocation-free counting call (SDBG_NOALLOC_SCRATCH_MB)
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 class SdbgError(RuntimeError):
@@ -261,6 +263,35 @@ def count_solid(seq, offsets, k: int, d: int = 2, mercy: bool = False, prefix_le
     _check(lib.sdbg_count_solid(ctypes.byref(r), ctypes.byref(p), ctypes.byref(out)))
     del keep
     return Edges(out)
+
+
+def count_solid_noalloc(seq, offsets, k: int, d: int, mercy: bool, keys_out, count_out, prefix_len: int = 8,
+                        mem_budget: int = 0, stream=None) -> dict:
+    """Allocation-free counting into caller buffers: keys_out (device uint64
+    tensor of cap*w words) and count_out (device int32/uint32 tensor of cap
+    entries).  Returns n, n_mercy, n_occ and scratch_peak."""
+    lib = load()
+    if not getattr(lib, "_noalloc_api", False):
+        P = ctypes.POINTER
+        lib.sdbg_count_solid_noalloc.argtypes = [P(_Reads), P(_Params), ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_uint64] + [P(ctypes.c_uint64)] * 4
+        lib.sdbg_count_solid_noalloc.restype = ctypes.c_int
+        lib._noalloc_api = True
+    assert keys_out.is_cuda and count_out.is_cuda and keys_out.is_contiguous() and count_out.is_contiguous()
+    assert keys_out.dtype.itemsize == 8 and count_out.dtype.itemsize == 4
+    w = key_words(k)
+    cap = min(keys_out.numel() // w, count_out.numel())
+    r, keep = _reads_struct(seq, offsets)
+    p = _Params(k, d, 1 if mercy else 0, prefix_len, mem_budget, _stream_ptr(stream))
+    n, nm, no, peak = (ctypes.c_uint64() for _ in range(4))
+    rc = lib.sdbg_count_solid_noalloc(ctypes.byref(r), ctypes.byref(p), keys_out.data_ptr(), count_out.data_ptr(),
+                                      cap, ctypes.byref(n), ctypes.byref(nm), ctypes.byref(no), ctypes.byref(peak))
+    del keep
+    if rc != SDBG_OK:
+        err = SdbgError(rc, lib.sdbg_last_error().decode(errors="replace"))
+        err.n = n.value
+        raise err
+    return {"n": n.value, "n_mercy": nm.value, "n_occ": no.value, "scratch_peak": peak.value}
 
 
 def build(edges: Edges, stream=None) -> Graph:
