@@ -675,7 +675,9 @@ __global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* con
   uint64_t* const buf1 = bufs[1];
   const uint64_t G = gridDim.x;
 
-  // next segment, prefetched
+  // next segment, prefetched (the first PF keys of each thread; the largest
+  // one-word leaf holds the rest back so that it needs no scratch memory)
+  constexpr int PF = (W == 1 && CAP > 1024) ? PER - 2 : PER;
   uint64_t n_len = 0, n_off = 0;
   int n_buf = 0, n_bit = 0;
   Key<W> nk[PER];
@@ -688,7 +690,7 @@ __global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* con
     if (n_len <= CAP) {
       const uint64_t* src = (n_buf ? buf1 : buf0) + n_off * W;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
+      for (int q = 0; q < PF; ++q) {
         const int i = q * SDBG_BLOCK + threadIdx.x;
         if (i < (int)n_len) nk[q] = key_load_g<W>(src + (uint64_t)i * W);
       }
@@ -724,7 +726,7 @@ __global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* con
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int i = q * SDBG_BLOCK + threadIdx.x;
-      if (i < n) key_store<W>(&A[i * W], nk[q]);
+      if (i < n) key_store<W>(&A[i * W], q < PF ? nk[q] : key_load_g<W>(keys + (uint64_t)i * W));
     }
     if (distinct) {
       // keys known to be distinct: each is its own slot, count 1
@@ -736,7 +738,6 @@ __global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* con
     lds_barrier();
     // 1. merge duplicates; the element that claims a slot represents its key
     uint32_t rep[PER];  // representative's hash slot (| digit << 16 once binned), else EMPTY
-    uint32_t rsl[PER];  // its place among the output keys of its bin
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       rep[q] = EMPTY;
@@ -784,7 +785,7 @@ __global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* con
     for (int q = 0; q < PER; ++q) {
       if (rep[q] != EMPTY) {
         const uint32_t dg = B ? key_bits<W>(key_load<W>(&A[(hs[rep[q]] >> 16) * W]), lo, B) : 0;
-        rsl[q] = atomicAdd(&bins[dg], 1u);
+        atomicAdd(&bins[dg], 1u);
         rep[q] |= dg << 16;
       }
     }
@@ -805,15 +806,16 @@ __global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* con
       if (threadIdx.x == 0) bins[nbins] = tot;
     }
     lds_barrier();
-    // output keys (as hash slots) in bin order
+    // output keys (as hash slots) grouped by bin, in any order within a bin
+    // (each bin is sorted next); bins[d] ends as the end of bin d
 #pragma unroll
     for (int q = 0; q < PER; ++q)
-      if (rep[q] != EMPTY) idx[bins[rep[q] >> 16] + rsl[q]] = (uint16_t)(rep[q] & 0xFFFFu);
+      if (rep[q] != EMPTY) idx[atomicAdd(&bins[rep[q] >> 16], 1u)] = (uint16_t)(rep[q] & 0xFFFFu);
     lds_barrier();
     // 4. finish each thread's bins: sort by key, count outputs, write
     const int b0 = (int)(((uint64_t)threadIdx.x * nbins) / SDBG_BLOCK);
     const int b1 = (int)(((uint64_t)(threadIdx.x + 1) * nbins) / SDBG_BLOCK);
-    const int r0 = bins[b0], r1 = bins[b1];
+    const int r0 = b0 ? (int)bins[b0 - 1] : 0, r1 = b1 ? (int)bins[b1 - 1] : 0;
     for (int i = r0 + 1; i < r1; ++i) {
       const uint16_t x = idx[i];
       const Key<W> kx = key_load<W>(&A[(hs[x] >> 16) * W]);
