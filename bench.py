@@ -180,27 +180,52 @@ def bench_serve(args):
     log(f"generated {len(pool)} jobs, {sum(r.n_reads for r in pool)} reads in {time.perf_counter() - t0:.1f} s")
 
     def replay(max_jobs, arrivals, jobs):
+        """One replay of the trace; every wait is bounded by a deadline, on
+        whose expiry the request loop's state is printed and the run ends."""
         res = [None] * len(jobs)
+        deadline = time.perf_counter() + args.serve_deadline
         with sdbg.Server(max_jobs=max_jobs) as srv:
             ids = [None] * len(jobs)
-            ready = threading.Event()
+            failed = []
 
             def submitter():
                 base = time.perf_counter()
-                for i, (a, rs) in enumerate(zip(arrivals, jobs)):
-                    dt = base + a - time.perf_counter()
-                    if dt > 0:
-                        time.sleep(dt)
-                    ids[i] = srv.submit(rs.seq, rs.offsets, rs.k, 2, True)
-                    ready.set()
+                try:
+                    for i, (a, rs) in enumerate(zip(arrivals, jobs)):
+                        dt = base + a - time.perf_counter()
+                        if dt > 0:
+                            time.sleep(dt)
+                        ids[i] = srv.submit(rs.seq, rs.offsets, rs.k, 2, True)
+                except Exception as e:  # reported by the main thread
+                    failed.append(e)
 
-            th = threading.Thread(target=submitter)
+            def stuck(what):
+                st = srv.state()
+                log(f"serve replay ({max_jobs} jobs at once) stuck {what}: {st}")
+                for i, jid in enumerate(ids):
+                    if jid is not None and res[i] is None:
+                        r = srv.poll(jid, wait=False)
+                        log(f"  job {i} (id {jid}, k={jobs[i].k}, {jobs[i].n_reads} reads): status {r.status}, "
+                            f"submit {r.submit_s:.3f} s start {r.start_s:.3f} s footprint {r.footprint}")
+                sys.stderr.flush()
+                os._exit(3)
+
+            th = threading.Thread(target=submitter, daemon=True)
             th.start()
             for i in range(len(jobs)):
                 while ids[i] is None:
-                    ready.wait(0.01)
-                    ready.clear()
-                r = srv.poll(ids[i])
+                    if failed:
+                        raise failed[0]
+                    if time.perf_counter() > deadline:
+                        stuck(f"waiting for submission of job {i}")
+                    time.sleep(0.002)
+                while True:
+                    r = srv.poll(ids[i], wait=False)
+                    if r.status <= 0:
+                        break
+                    if time.perf_counter() > deadline:
+                        stuck(f"waiting for job {i}")
+                    time.sleep(0.002)
                 assert r.status == 0, r.error
                 res[i] = (r.submit_s, r.start_s, r.end_s, r.n_occ)
                 r.edges.close()
@@ -267,6 +292,8 @@ def main():
     ap.add_argument("--read-scale", type=float, default=None, help="batch/serve: scale of the read counts")
     ap.add_argument("--rates", default="1,2,5,10,20,50", help="serve: arrival rates (jobs/s)")
     ap.add_argument("--pool", type=int, default=32, help="serve: distinct jobs in the pool")
+    ap.add_argument("--serve-deadline", type=float, default=120.0,
+                    help="serve: seconds one replay may take before the loop's state is printed and the run ends")
     ap.add_argument("--autotune", action="store_true", help="batch: pick launch parameters on a sample first")
     ap.add_argument("--tune", default="", help="launch parameters, e.g. leaf_cap_shift=1,leaf_wg_per_cu=8")
     ap.add_argument("--host-input", action="store_true",

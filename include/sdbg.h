@@ -252,6 +252,22 @@ typedef struct sdbg_job_stats {
 
 typedef struct sdbg_server sdbg_server;
 
+/* Device bytes the request loop reserves for a job of these reads and
+ * parameters (host reads only): a bound on the job's peak use of the
+ * library's device memory, used for admission. */
+int sdbg_job_footprint(const sdbg_reads *reads, const sdbg_params *params, uint64_t *bytes);
+
+/* Snapshot of the request loop: admission budget and the footprint bytes
+ * of running jobs, waiting and running job counts, jobs not yet collected
+ * by sdbg_server_poll, seconds since start. */
+typedef struct sdbg_server_info {
+  uint64_t budget, mem_in_use;
+  uint32_t queued, running;
+  uint64_t jobs;
+  double uptime_s;
+} sdbg_server_info;
+int sdbg_server_state(sdbg_server *srv, sdbg_server_info *info);
+
 /* Starts the workers (cfg may be NULL for defaults). */
 int sdbg_server_start(const sdbg_server_cfg *cfg, sdbg_server **out);
 

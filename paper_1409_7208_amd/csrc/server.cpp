@@ -26,6 +26,7 @@
 #include <unordered_map>
 
 #include "abi_common.h"
+#include "admission.h"
 
 namespace {
 
@@ -41,6 +42,8 @@ struct Job {
   sdbg_params params{};
   uint64_t footprint = 0;
   bool alone = false;  // retry after running out of device memory: run alone
+  uint64_t adm_seq = 0;     // admission bookkeeping (admission.h)
+  bool adm_shared = false;
   int status = kWaiting;
   std::string err;
   sdbg_job_stats stats{};
@@ -105,11 +108,9 @@ struct sdbg_server {
   Clock::time_point t0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<Job*> queue;
+  sdbg_sched::Admission<Job*> adm{0};  // guarded by mu
   std::unordered_map<uint64_t, Job*> jobs;
   uint64_t next_id = 1;
-  uint64_t mem_in_use = 0;
-  uint32_t running = 0;
   bool stopping = false;
   std::vector<std::thread> workers;
   PinnedPool pinned;
@@ -122,14 +123,6 @@ struct sdbg_server {
   }
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
-
-  // Called with mu held: may the head of the queue start now?
-  bool head_admissible() const {
-    if (queue.empty()) return false;
-    const Job* j = queue.front();
-    if (j->alone || j->footprint > budget) return running == 0;
-    return mem_in_use + j->footprint <= budget;
-  }
 
   void run_job(Job* j, hipStream_t s) {
     sdbg::EdgesOut eo;
@@ -170,15 +163,11 @@ struct sdbg_server {
       j->edges = nullptr;
     }
     std::lock_guard<std::mutex> lk(mu);
-    mem_in_use -= j->footprint;
-    --running;
-    if (rc == SDBG_E_NOMEM_DEVICE && !j->alone && running > 0) {
-      // Device memory ran out next to other jobs: queue it again at the
-      // head, to run when the device is otherwise idle.
-      j->alone = true;
+    if (adm.finish(j, rc == SDBG_E_NOMEM_DEVICE)) {
+      // Device memory ran out next to other jobs: queued again at the head,
+      // to run when the device is otherwise idle.
       j->status = kWaiting;
       j->err.clear();
-      queue.push_front(j);
     } else {
       j->stats.end_s = now();
       j->stats.n_occ = j->edges ? j->edges->n_occ : 0;
@@ -198,12 +187,9 @@ struct sdbg_server {
       Job* j = nullptr;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stopping || head_admissible(); });
+        cv_work.wait(lk, [&] { return stopping || adm.head_admissible(); });
         if (stopping) break;
-        j = queue.front();
-        queue.pop_front();
-        mem_in_use += j->footprint;
-        ++running;
+        j = adm.start_head();
         j->status = kRunning;
         j->stats.status = kRunning;
         j->stats.start_s = now();
@@ -216,6 +202,34 @@ struct sdbg_server {
 };
 
 extern "C" {
+
+int sdbg_job_footprint(const sdbg_reads* reads, const sdbg_params* params, uint64_t* bytes) {
+  return sdbg_abi::guarded([&]() -> int {
+    SDBG_CHECK(reads && params && bytes, SDBG_E_INVAL, "null argument");
+    SDBG_CHECK(!reads->on_device, SDBG_E_INVAL, "the request loop takes host reads");
+    sdbg_abi::check_params(params);
+    SDBG_CHECK(reads->n_reads == 0 || reads->offsets, SDBG_E_INVAL, "null offsets");
+    std::vector<uint64_t> o(reads->n_reads + 1, 0);
+    if (reads->n_reads) std::memcpy(o.data(), reads->offsets, sizeof(uint64_t) * (reads->n_reads + 1));
+    SDBG_CHECK(o[0] == 0, SDBG_E_INVAL, "offsets[0] must be 0");
+    *bytes = job_footprint(sdbg_abi::occ_bound(o, params->k), o.back(), params->k);
+    return SDBG_OK;
+  });
+}
+
+int sdbg_server_state(sdbg_server* sv, sdbg_server_info* info) {
+  return sdbg_abi::guarded([&]() -> int {
+    SDBG_CHECK(sv && info, SDBG_E_INVAL, "null argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    info->budget = sv->adm.budget();
+    info->mem_in_use = sv->adm.mem_in_use();
+    info->queued = (uint32_t)sv->adm.queued();
+    info->running = sv->adm.running();
+    info->jobs = sv->jobs.size();
+    info->uptime_s = sv->now();
+    return SDBG_OK;
+  });
+}
 
 int sdbg_server_start(const sdbg_server_cfg* cfg, sdbg_server** out) {
   return sdbg_abi::guarded([&]() -> int {
@@ -231,6 +245,7 @@ int sdbg_server_start(const sdbg_server_cfg* cfg, sdbg_server** out) {
       sdbg_params p{};
       p.mem_budget = sv->cfg.mem_budget;
       sv->budget = sdbg_abi::device_budget(&p);
+      sv->adm = sdbg_sched::Admission<Job*>(sv->budget);
       sv->t0 = Clock::now();
       for (uint32_t i = 0; i < sv->cfg.max_jobs; ++i) sv->workers.emplace_back([sv] { sv->worker(); });
     } catch (...) {
@@ -265,7 +280,7 @@ int sdbg_server_submit(sdbg_server* sv, const sdbg_reads* reads, const sdbg_para
     {
       std::lock_guard<std::mutex> lk(sv->mu);
       SDBG_CHECK(!sv->stopping, SDBG_E_INVAL, "server is stopping");
-      if (sv->queue.size() >= sv->cfg.queue_cap) throw sdbg::Error(SDBG_E_BUSY, "queue full");
+      if (sv->adm.queued() >= sv->cfg.queue_cap) throw sdbg::Error(SDBG_E_BUSY, "queue full");
     }
     Job* j = new Job();
     j->n_reads = reads->n_reads;
@@ -285,7 +300,7 @@ int sdbg_server_submit(sdbg_server* sv, const sdbg_reads* reads, const sdbg_para
     std::memcpy(j->off, o.data(), sizeof(uint64_t) * (j->n_reads + 1));
     {
       std::lock_guard<std::mutex> lk(sv->mu);
-      if (sv->stopping || sv->queue.size() >= sv->cfg.queue_cap) {
+      if (sv->stopping || sv->adm.queued() >= sv->cfg.queue_cap) {
         const bool stop = sv->stopping;
         sv->free_pinned(j);
         delete j;
@@ -296,7 +311,7 @@ int sdbg_server_submit(sdbg_server* sv, const sdbg_reads* reads, const sdbg_para
       j->stats.submit_s = sv->now();
       j->stats.footprint = j->footprint;
       sv->jobs[j->id] = j;
-      sv->queue.push_back(j);
+      sv->adm.push(j);
       *job_id = j->id;
     }
     sv->cv_work.notify_all();
@@ -342,8 +357,7 @@ int sdbg_server_cancel(sdbg_server* sv, uint64_t job_id) {
     auto it = sv->jobs.find(job_id);
     SDBG_CHECK(it != sv->jobs.end(), SDBG_E_INVAL, "unknown job id");
     Job* j = it->second;
-    if (j->status != kWaiting) return SDBG_E_BUSY;
-    sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), j));
+    if (j->status != kWaiting || !sv->adm.cancel(j)) return SDBG_E_BUSY;
     j->status = SDBG_E_CANCELLED;
     j->stats.status = SDBG_E_CANCELLED;
     j->stats.end_s = sv->now();
@@ -360,13 +374,12 @@ int sdbg_server_stop(sdbg_server* sv) {
     if (!sv) return SDBG_OK;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
-      for (Job* j : sv->queue) {
+      for (Job* j : sv->adm.drain()) {
         j->status = SDBG_E_CANCELLED;
         j->stats.status = SDBG_E_CANCELLED;
         sv->free_pinned(j);
       }
-      sv->queue.clear();
-      sv->cv_done.wait(lk, [&] { return sv->running == 0; });
+      sv->cv_done.wait(lk, [&] { return sv->adm.running() == 0; });
       sv->stopping = true;
     }
     sv->cv_work.notify_all();

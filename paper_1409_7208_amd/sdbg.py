@@ -480,7 +480,34 @@ def _server_api(lib):
     lib.sdbg_server_cancel.restype = ctypes.c_int
     lib.sdbg_server_stop.argtypes = [ctypes.c_void_p]
     lib.sdbg_server_stop.restype = ctypes.c_int
+    lib.sdbg_server_state.argtypes = [ctypes.c_void_p, P(_ServerInfo)]
+    lib.sdbg_server_state.restype = ctypes.c_int
+    lib.sdbg_job_footprint.argtypes = [P(_Reads), P(_Params), P(ctypes.c_uint64)]
+    lib.sdbg_job_footprint.restype = ctypes.c_int
     lib._server_api = True
+
+
+class _ServerInfo(ctypes.Structure):
+    _fields_ = [
+        ("budget", ctypes.c_uint64),
+        ("mem_in_use", ctypes.c_uint64),
+        ("queued", ctypes.c_uint32),
+        ("running", ctypes.c_uint32),
+        ("jobs", ctypes.c_uint64),
+        ("uptime_s", ctypes.c_double),
+    ]
+
+
+def job_footprint(seq, offsets, k: int, d: int = 2, mercy: bool = True, prefix_len: int = 8) -> int:
+    """Device bytes the request loop reserves for a job on these host reads."""
+    lib = load()
+    _server_api(lib)
+    r, keep = _reads_struct(seq, offsets)
+    p = _Params(k, d, 1 if mercy else 0, prefix_len, 0, None)
+    b = ctypes.c_uint64()
+    _check(lib.sdbg_job_footprint(ctypes.byref(r), ctypes.byref(p), ctypes.byref(b)))
+    del keep
+    return b.value
 
 
 class Server:
@@ -519,6 +546,12 @@ class Server:
         if rc < 0 and st.status != rc:
             raise SdbgError(rc, err)  # not a job's own result (e.g. unknown id)
         return JobResult(rc, None, None, st.submit_s, st.start_s, st.end_s, st.n_occ, st.footprint, err)
+
+    def state(self) -> dict:
+        """Admission budget, footprint bytes in use, queued and running jobs."""
+        info = _ServerInfo()
+        _check(load().sdbg_server_state(self._h, ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in _ServerInfo._fields_}
 
     def cancel(self, job_id: int) -> int:
         return load().sdbg_server_cancel(self._h, job_id)

@@ -262,15 +262,26 @@ def serving_trace(rate: float, n_jobs: int, seed_extra: int = 0, read_scale: flo
     t = np.cumsum(gaps)
     jobs = []
     for j in range(n_jobs):
-        jr = rng_for(5, 1000 + seed_extra * 100_000 + j)
-        ng = int(jr.integers(1, 51))
-        comm = make_community(ng, max(200, int(100_000 * genome_scale)), max(400, int(5_000_000 * genome_scale)), 1.5, jr)
-        n = max(1, int(round(float(log_uniform_int(10_000, 20_000_000, 1, jr)[0]) * read_scale)))
-        L = int(jr.integers(100, 151))
-        k = int(jr.choice([21, 41, 61]))
+        jr, comm, n, L, k = _serving_job(j, seed_extra, read_scale, genome_scale)
         seq, off = sample_reads(comm, n, L, 0.005, jr)
         jobs.append(Job(float(t[j]), ReadSet(seq, off, k=k, d=2, mercy=True, name=f"job[{j}]")))
     return jobs
+
+
+def _serving_job(j: int, seed_extra: int, read_scale: float, genome_scale: float):
+    jr = rng_for(5, 1000 + seed_extra * 100_000 + j)
+    ng = int(jr.integers(1, 51))
+    comm = make_community(ng, max(200, int(100_000 * genome_scale)), max(400, int(5_000_000 * genome_scale)), 1.5, jr)
+    n = max(1, int(round(float(log_uniform_int(10_000, 20_000_000, 1, jr)[0]) * read_scale)))
+    L = int(jr.integers(100, 151))
+    k = int(jr.choice([21, 41, 61]))
+    return jr, comm, n, L, k
+
+
+def serving_job_shapes(n_jobs: int, seed_extra: int = 0, read_scale: float = 1.0, genome_scale: float = 1.0) -> list[tuple[int, int, int]]:
+    """(reads, read length, k) of the first n_jobs jobs of serving_trace,
+    without sampling their reads."""
+    return [_serving_job(j, seed_extra, read_scale, genome_scale)[2:] for j in range(n_jobs)]
 
 
 def random_small(n_reads: int, min_len: int, max_len: int, genome_len: int, err: float, seed: int, n_rate: float = 0.0) -> ReadSet:
