@@ -7,7 +7,10 @@ never calls the device library.
 ``count_solid`` and ``build`` wrap the plain C++ implementation in
 ``sdbg_oracle.cpp`` (string-based, std::sort + std::unordered_map) which
 follows Section 2 of the paper step by step; ``count_keys`` counts chosen
-edges over all reads for sampled checks of large runs.
+edges over all reads for sampled checks of large runs.  ``part_count_solid``
+and ``part_build_graph`` (``sdbg_oracle_part.cpp``) compute the same outputs
+on packed keys, one block of the key space at a time on several threads, for
+read sets too large for the string form; the tests pin them to it.
 """
 
 from __future__ import annotations
@@ -20,7 +23,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "sdbg_oracle.cpp")
+_SRC = [os.path.join(_HERE, "sdbg_oracle.cpp"), os.path.join(_HERE, "sdbg_oracle_part.cpp")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -29,7 +32,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with the host compiler (no GPU code involved)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", tmp, _SRC])
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", tmp, *_SRC])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -70,6 +73,15 @@ def _load():
             ctypes.c_void_p, ctypes.c_int,
         ]
         lib.oracle_count_keys.restype = ctypes.c_int
+        lib.oracle_part_count_solid.argtypes = [
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+            ctypes.c_int, ctypes.c_uint64, p(p(ctypes.c_uint64)), p(p(ctypes.c_uint32)), p(ctypes.c_uint64),
+            p(ctypes.c_uint64), p(ctypes.c_uint64),
+        ]
+        lib.oracle_part_count_solid.restype = ctypes.c_int
+        lib.oracle_part_build.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                          ctypes.c_int, p(_Graph)]
+        lib.oracle_part_build.restype = ctypes.c_int
         lib.oracle_narrow_count.argtypes = [ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32)]
         lib.oracle_narrow_count.restype = ctypes.c_int
         _lib = lib
@@ -109,7 +121,22 @@ def _as_reads(seq, offsets):
     return seq, offsets
 
 
+def _threads(threads):
+    return min(16, os.cpu_count() or 1) if threads is None else threads
+
+
 def count_solid(seq, offsets, k: int, d: int = 2, mercy: bool = False) -> Edges:
+    return _count(seq, offsets, k, d, mercy, None)
+
+
+def part_count_solid(seq, offsets, k: int, d: int = 2, mercy: bool = False, threads: int | None = None,
+                     group_keys: int = 0) -> Edges:
+    """Same as count_solid, block by block (group_keys: most keys counted
+    together, 0 = all)."""
+    return _count(seq, offsets, k, d, mercy, (_threads(threads), group_keys))
+
+
+def _count(seq, offsets, k, d, mercy, part):
     lib = _load()
     seq, offsets = _as_reads(seq, offsets)
     n_reads = offsets.shape[0] - 1
@@ -118,10 +145,15 @@ def count_solid(seq, offsets, k: int, d: int = 2, mercy: bool = False) -> Edges:
     n = ctypes.c_uint64()
     nm = ctypes.c_uint64()
     nocc = ctypes.c_uint64()
-    rc = lib.oracle_count_solid(seq.ctypes.data if seq.size else None, offsets.ctypes.data, n_reads, k, d, int(bool(mercy)),
-                                ctypes.byref(kp), ctypes.byref(cp), ctypes.byref(n), ctypes.byref(nm), ctypes.byref(nocc))
+    outs = (ctypes.byref(kp), ctypes.byref(cp), ctypes.byref(n), ctypes.byref(nm), ctypes.byref(nocc))
+    sp = seq.ctypes.data if seq.size else None
+    if part is None:
+        rc = lib.oracle_count_solid(sp, offsets.ctypes.data, n_reads, k, d, int(bool(mercy)), *outs)
+    else:
+        rc = lib.oracle_part_count_solid(sp, offsets.ctypes.data, n_reads, k, d, int(bool(mercy)), part[0], part[1],
+                                         *outs)
     if rc != 0:
-        raise ValueError(f"oracle_count_solid failed ({rc})")
+        raise ValueError(f"oracle count failed ({rc})")
     w = key_words(k)
     try:
         keys = np.ctypeslib.as_array(kp, shape=(n.value * w + 1,))[: n.value * w].copy().reshape(n.value, w)
@@ -133,13 +165,26 @@ def count_solid(seq, offsets, k: int, d: int = 2, mercy: bool = False) -> Edges:
 
 
 def build_graph(keys: np.ndarray, counts: np.ndarray, k: int) -> Graph:
+    return _build(keys, counts, k, None)
+
+
+def part_build_graph(keys: np.ndarray, counts: np.ndarray, k: int, threads: int | None = None) -> Graph:
+    """Same as build_graph, block by block."""
+    return _build(keys, counts, k, _threads(threads))
+
+
+def _build(keys, counts, k, threads):
     lib = _load()
     w = key_words(k)
     keys = np.ascontiguousarray(keys, dtype=np.uint64).reshape(-1, w)
     counts = np.ascontiguousarray(counts, dtype=np.uint32)
     n = keys.shape[0]
     g = _Graph()
-    rc = lib.oracle_build(keys.ctypes.data if n else None, counts.ctypes.data if n else None, n, k, ctypes.byref(g))
+    kp, cp = (keys.ctypes.data if n else None), (counts.ctypes.data if n else None)
+    if threads is None:
+        rc = lib.oracle_build(kp, cp, n, k, ctypes.byref(g))
+    else:
+        rc = lib.oracle_part_build(kp, cp, n, k, threads, ctypes.byref(g))
     if rc != 0:
         raise ValueError(f"oracle_build failed ({rc})")
     try:
@@ -159,8 +204,7 @@ def count_keys(seq, offsets, k: int, qkeys: np.ndarray, threads: int | None = No
     w = key_words(k)
     q = np.ascontiguousarray(qkeys, dtype=np.uint64).reshape(-1, w)
     out = np.zeros(q.shape[0], dtype=np.uint64)
-    if threads is None:
-        threads = min(16, os.cpu_count() or 1)
+    threads = _threads(threads)
     rc = lib.oracle_count_keys(seq.ctypes.data if seq.size else None, offsets.ctypes.data, offsets.shape[0] - 1, k,
                                q.ctypes.data if q.size else None, q.shape[0], out.ctypes.data, threads)
     if rc != 0:

@@ -204,3 +204,40 @@ def test_count_width_is_checked_not_clamped():
         oracle.narrow_count(2**32)
     with pytest.raises(OverflowError):
         oracle.narrow_count(2**63)
+
+
+# ---- the partitioned oracle (packed keys, block by block, several threads)
+# is pinned to the string oracle above: identical outputs on the toys, on
+# random inputs over the whole k range (N bytes, lower case, d = 1..3, mercy
+# on and off), with one and several threads and with counting groups small
+# enough to split the blocks.
+
+def _same_as_string_oracle(rs, k, d, mercy, threads, group_keys):
+    o = oracle.count_solid(rs.seq, rs.offsets, k, d, mercy)
+    p = oracle.part_count_solid(rs.seq, rs.offsets, k, d, mercy, threads=threads, group_keys=group_keys)
+    assert p.n_occ == o.n_occ and p.n_mercy == o.n_mercy
+    assert np.array_equal(p.keys, o.keys) and np.array_equal(p.counts, o.counts)
+    g = oracle.build_graph(o.keys, o.counts, k)
+    h = oracle.part_build_graph(o.keys, o.counts, k, threads=threads)
+    assert h.m == g.m and h.t == g.t
+    for f in ("W", "last", "valid", "tip", "mult", "F", "tip_seq"):
+        assert np.array_equal(getattr(h, f), getattr(g, f)), f
+
+
+@pytest.mark.parametrize("toy", TOYS, ids=[t["name"] for t in TOYS])
+def test_partitioned_oracle_toys(toy):
+    rs = synth.from_strings(toy["reads"], toy["k"], toy["d"], toy["mercy"])
+    _same_as_string_oracle(rs, toy["k"], toy["d"], toy["mercy"], 2, 0)
+
+
+@pytest.mark.parametrize("k", [2, 3, 7, 8, 9, 15, 21, 31, 32, 33, 41, 61, 63, 64, 81, 95, 96, 99, 127])
+def test_partitioned_oracle_random(k):
+    for seed in range(3):
+        rs = synth.random_small(80, 20, 220, 500, 0.02, seed=seed * 1000 + k, n_rate=0.01)
+        _same_as_string_oracle(rs, k, 1 + seed % 3, seed != 1, 1 + 2 * seed, [0, 64, 700][seed])
+
+
+def test_partitioned_oracle_workload_sample():
+    rs = synth.tiny(scale=0.2)
+    for k in (21, 31, 41):
+        _same_as_string_oracle(rs, k, 2, True, 8, 200_000)
