@@ -204,9 +204,11 @@ def bench_serve(args):
                 log(f"serve replay ({max_jobs} jobs at once) stuck {what}: {st}")
                 for i, jid in enumerate(ids):
                     if jid is not None and res[i] is None:
+                        tr = srv.trace(jid)
                         r = srv.poll(jid, wait=False)
                         log(f"  job {i} (id {jid}, k={jobs[i].k}, {jobs[i].n_reads} reads): status {r.status}, "
-                            f"submit {r.submit_s:.3f} s start {r.start_s:.3f} s footprint {r.footprint}")
+                            f"submit {r.submit_s:.3f} s start {r.start_s:.3f} s footprint {r.footprint}, "
+                            f"at {tr}")
                 sys.stderr.flush()
                 os._exit(3)
 
@@ -290,7 +292,8 @@ def main():
                          "serve: Poisson request stream through the request loop vs one job at a time")
     ap.add_argument("--sets", type=int, default=4096, help="batch: first N sets of the 4096-set recipe")
     ap.add_argument("--read-scale", type=float, default=None, help="batch/serve: scale of the read counts")
-    ap.add_argument("--rates", default="1,2,5,10,20,50", help="serve: arrival rates (jobs/s)")
+    ap.add_argument("--rates", default="1,2", help="serve: arrival rates (jobs/s); see the design notes before "
+                    "running 5 and above")
     ap.add_argument("--pool", type=int, default=32, help="serve: distinct jobs in the pool")
     ap.add_argument("--serve-deadline", type=float, default=120.0,
                     help="serve: seconds one replay may take before the loop's state is printed and the run ends")

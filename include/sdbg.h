@@ -226,7 +226,8 @@ int sdbg_autotune(const sdbg_reads *sets, uint64_t n_sets, const sdbg_params *pa
  * FIFO order; max_jobs workers, each with its own stream, start the head of
  * the queue as soon as its device-memory footprint fits mem_budget next to
  * the running jobs, so jobs that arrive while others run join them on the
- * device (a job larger than the whole budget runs alone).  Each job runs
+ * device (a job larger than the whole budget, or with a footprint above
+ * 8 GiB, runs alone).  Each job runs
  * the single-call path (sdbg_count_solid, then sdbg_build if cfg->build),
  * so its results are identical to running it alone.  The device buffers of
  * finished jobs stay cached for the next ones (the memory-adaptive
@@ -268,6 +269,14 @@ typedef struct sdbg_server_info {
 } sdbg_server_info;
 int sdbg_server_state(sdbg_server *srv, sdbg_server_info *info);
 
+/* Where a running job is, for diagnosis: the last kernel stage it entered,
+ * what its worker waits on ("" if nothing: stream synchronisation, device
+ * allocation, releasing cached device memory), and seconds since either
+ * changed.  Empty strings for a job that is not running.  The strings are
+ * static. */
+int sdbg_server_trace(sdbg_server *srv, uint64_t job_id, const char **stage, const char **activity,
+                      double *seconds);
+
 /* Starts the workers (cfg may be NULL for defaults). */
 int sdbg_server_start(const sdbg_server_cfg *cfg, sdbg_server **out);
 
@@ -292,6 +301,36 @@ int sdbg_server_cancel(sdbg_server *srv, uint64_t job_id);
  * polled, and releases the server.  No other call on srv may be in
  * progress or follow. */
 int sdbg_server_stop(sdbg_server *srv);
+
+/* Navigation of a graph on the device (Section 2, first paragraph: the
+ * succinct representation is traversed through rank and select over W,
+ * last and F).  sdbg_index_build makes rank directories over the graph's
+ * arrays (about 1.4 bits per row; the index borrows the graph, which must
+ * outlive it; release with sdbg_free).  A node is identified by the index
+ * of its last row.  sdbg_navigate answers n queries rows[i] (device array)
+ * into out (device array; n words, or n * ceil(2k/64) words for
+ * SDBG_NAV_LABEL), on `stream`, and returns when they are done:
+ *   SDBG_NAV_NODE      row -> its node
+ *   SDBG_NAV_FORWARD   row -> node its edge enters (none for a '$' row)
+ *   SDBG_NAV_BACKWARD  node -> node whose edge enters it (for a vertex with
+ *                      no incoming edge: the dummy node before it; none for
+ *                      a dummy node)
+ *   SDBG_NAV_OUTDEG    node -> outgoing edges (0 for a '$' node)
+ *   SDBG_NAV_INDEG     node -> incoming edges, dummy rows not counted
+ *   SDBG_NAV_LABEL     node -> its k-mer v, base j at bits 2j (LSB-first
+ *                      words); the k-mer of a vertex with no incoming edge
+ *                      comes from tip_seq; all ones for a dummy node
+ * "none" and out-of-range queries give all ones (UINT64_MAX).  Nodes are
+ * given by any of their rows. */
+#define SDBG_NAV_NODE 1
+#define SDBG_NAV_FORWARD 2
+#define SDBG_NAV_BACKWARD 3
+#define SDBG_NAV_OUTDEG 4
+#define SDBG_NAV_INDEG 5
+#define SDBG_NAV_LABEL 6
+typedef struct sdbg_index sdbg_index;
+int sdbg_index_build(const sdbg_graph *g, const sdbg_params *params, sdbg_index **out);
+int sdbg_navigate(const sdbg_index *index, int op, const uint64_t *rows, uint64_t n, uint64_t *out, void *stream);
 
 /* Wraps host arrays (n*w key words ascending and unique, n counts) into a
  * library-owned device edge set, e.g. to build a graph from edges computed
@@ -327,6 +366,17 @@ int sdbg_profile_get(uint32_t i, const char **name, double *ms, uint64_t *bytes)
 /* Releases the library's cached device memory (kept between calls to avoid
  * repeated allocation).  Objects not yet freed stay valid. */
 void sdbg_trim(void);
+
+/* Device memory of the library's caching pool on the current device:
+ * bytes held by live buffers and outputs, the most held at any time since
+ * the last call with reset_peak = 1 (which sets it to the current use), and
+ * bytes cached for reuse.  Any pointer may be NULL. */
+int sdbg_pool_stats(uint64_t *in_use, uint64_t *peak, uint64_t *cached, int reset_peak);
+
+/* Failure injection for tests of the error paths: after `after` more pool
+ * allocations on the current device succeed, the next one fails with
+ * SDBG_E_NOMEM_DEVICE (once); a negative value disables it. */
+int sdbg_fail_alloc_after(int64_t after);
 
 #ifdef __cplusplus
 }

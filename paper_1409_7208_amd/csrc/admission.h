@@ -7,8 +7,9 @@
 // Rules:
 //   * only the head of the queue may start (FIFO, no overtaking);
 //   * it starts when its footprint fits the budget next to the running jobs;
-//   * a job larger than the whole budget, or one marked `alone`, starts only
-//     when nothing else runs, and nothing else starts while it runs;
+//   * a job larger than the whole budget, larger than the exclusive
+//     threshold, or marked `alone` starts only when nothing else runs, and
+//     nothing else starts while it runs;
 //   * a job that ran out of device memory while another job ran at any time
 //     during its run is marked `alone` and queued again at the head (the
 //     others may have finished by the time it reports); out of memory when
@@ -30,7 +31,9 @@ namespace sdbg_sched {
 template <typename JobPtr>
 class Admission {
  public:
-  explicit Admission(uint64_t budget) : budget_(budget) {}
+  // exclusive_above: footprint above which a job runs alone (0 = none).
+  explicit Admission(uint64_t budget, uint64_t exclusive_above = 0)
+      : budget_(budget), exclusive_above_(exclusive_above) {}
 
   void push(JobPtr j) { q_.push_back(j); }
 
@@ -85,7 +88,9 @@ class Admission {
     return v;
   }
 
-  bool exclusive(const JobPtr j) const { return j->alone || j->footprint > budget_; }
+  bool exclusive(const JobPtr j) const {
+    return j->alone || j->footprint > budget_ || (exclusive_above_ && j->footprint > exclusive_above_);
+  }
 
   size_t queued() const { return q_.size(); }
   uint32_t running() const { return running_; }
@@ -95,6 +100,7 @@ class Admission {
  private:
   std::deque<JobPtr> q_;
   uint64_t budget_;
+  uint64_t exclusive_above_;
   uint64_t mem_in_use_ = 0;
   uint64_t starts_ = 0;
   uint32_t running_ = 0;

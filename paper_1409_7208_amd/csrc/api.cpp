@@ -20,7 +20,6 @@ namespace sdbg_abi {
 
 thread_local std::string t_err;
 
-enum ObjKind { kEdges = 1, kGraph = 2 };
 // Edge sets the library computed itself are sorted and in range by
 // construction; sdbg_build checks the others.
 constexpr int kSortedByConstruction = 0x100;
@@ -173,6 +172,20 @@ int sdbg_profile_get(uint32_t i, const char** name, double* ms, uint64_t* bytes)
   if (ms) *ms = r[i].ms;
   if (bytes) *bytes = r[i].bytes;
   return SDBG_OK;
+}
+
+int sdbg_pool_stats(uint64_t* in_use, uint64_t* peak, uint64_t* cached, int reset_peak) {
+  return guarded([&]() -> int {
+    sdbg::Pool::get().stats(in_use, peak, cached, reset_peak != 0);
+    return SDBG_OK;
+  });
+}
+
+int sdbg_fail_alloc_after(int64_t after) {
+  return guarded([&]() -> int {
+    sdbg::Pool::get().fail_after(after);
+    return SDBG_OK;
+  });
 }
 
 void sdbg_trim(void) {
@@ -571,6 +584,8 @@ void sdbg_free(void* obj) {
       pool_free(g->mult);
       pool_free(g->tip_seq);
       delete g;
+    } else if (kind == kIndex) {
+      free_index(obj);
     }
   } catch (...) {
   }

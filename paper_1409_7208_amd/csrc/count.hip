@@ -226,9 +226,9 @@ DEV void window_keys(const ExArgs& a, uint64_t j, Key<W>* kf, Key<W>* kr) {
 // complement -- so every canonical key's count is the count of either of
 // its strands' keys over both strands.  Returns how many (1 or 2).
 template <int W>
-DEV int window_emit(const ExArgs& a, uint64_t j, Key<W>* k0, Key<W>* k1) {
-  Key<W> kf, kr;
-  window_keys<W>(a, j, &kf, &kr);
+DEV int window_emit(const ExArgs& a, Roller<W>& rl, uint64_t j, Key<W>* k0, Key<W>* k1) {
+  rl.at(a.packed, a.k, a.kb, j);
+  const Key<W> kf = rl.fwd_key(a.kb), kr = rl.rc_key(a.kb);
   if (!a.canon) {
     *k0 = kf;
     *k1 = kr;
@@ -261,13 +261,14 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_hist(ExArgs a, uint32_t* __re
   if (g0 < tg.gend) {
     WinIter it;
     it.init(a, g0);
+    Roller<W> rl;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
       if (g0 + q < tg.gend) {
         uint64_t j = it.pos();
         if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
           Key<W> k0, k1;
-          const int ne = window_emit<W>(a, j, &k0, &k1);
+          const int ne = window_emit<W>(a, rl, j, &k0, &k1);
           produced += 2;
           if (ex_pass<W>(a, k0)) atomicAdd(&h[key_bits<W>(k0, a.dlo, a.dbits)], 1u);
           if (ne == 2 && ex_pass<W>(a, k1)) atomicAdd(&h[key_bits<W>(k1, a.dlo, a.dbits)], 1u);
@@ -314,12 +315,13 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_scatter(ExArgs a, const uint3
   if (g0 < tg.gend) {
     WinIter it;
     it.init(a, g0);
+    Roller<W> rl;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
       if (g0 + q < tg.gend) {
         uint64_t j = it.pos();
         if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
-          const int ne = window_emit<W>(a, j, &keys[2 * q], &keys[2 * q + 1]);
+          const int ne = window_emit<W>(a, rl, j, &keys[2 * q], &keys[2 * q + 1]);
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             if (h < ne && ex_pass<W>(a, keys[2 * q + h])) {
@@ -362,11 +364,12 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_ex_hist_prefix(ExArgs a, unsigne
   if (g0 >= a.NW) return;
   WinIter it;
   it.init(a, g0);
+  Roller<W> rl;
   for (int q = 0; q < IPT && g0 + q < a.NW; ++q) {
     uint64_t j = it.pos();
     if (!a.any_bad || window_clean(a.bad, j, a.k + 1)) {
       Key<W> k0, k1;
-      const int ne = window_emit<W>(a, j, &k0, &k1);
+      const int ne = window_emit<W>(a, rl, j, &k0, &k1);
       atomicAdd(&h[key_bits<W>(k0, a.kb - a.pb, a.pb)], 1ull);
       if (ne == 2) atomicAdd(&h[key_bits<W>(k1, a.kb - a.pb, a.pb)], 1ull);
     }

@@ -132,6 +132,35 @@ DEV Key<W> key_revcomp(const Key<W>& x, int kb) {
   return key_from_fwd<W>(revcomp_fwd<W>(F, kb), kb);
 }
 
+// Forward packing F and reverse-complement packing R of consecutive
+// windows of a packed 2-bit stream (base j at bits 2(j mod 32) of word
+// j/32), updated by one base per step instead of being rebuilt: the next
+// window drops its first base from the bottom of F and takes the new base
+// on top; R gains the new base's complement at the bottom.  A window that
+// does not follow the one held (a new read, or the first window) is built
+// from the stream.  kb = 2(k+1).
+template <int W>
+struct Roller {
+  Key<W> F, R;
+  uint64_t j = 0;     // stream position of the window held
+  bool held = false;  // F and R hold the window at j
+  DEV void at(const uint64_t* __restrict__ packed, int k, int kb, uint64_t pos) {
+    if (held && pos == j + 1) {
+      const uint64_t p = pos + (uint64_t)k;  // the new last base
+      const uint64_t b = (packed[p >> 5] >> (2 * (p & 31))) & 3;
+      F = key_or2<W>(key_shr<W>(F, 2), kb - 2, b);
+      R = key_or_low<W>(key_lowbits<W>(key_shl<W>(R, 2), kb), 3 - b);
+    } else {
+      F = stream_bits<W>(packed, 2 * pos, kb);
+      R = revcomp_fwd<W>(F, kb);
+    }
+    j = pos;
+    held = true;
+  }
+  DEV Key<W> fwd_key(int kb) const { return key_from_fwd<W>(F, kb); }
+  DEV Key<W> rc_key(int kb) const { return key_from_fwd<W>(R, kb); }
+};
+
 // Target node x[1..k] of edge key x (2k bits): (x >> 4) + x[k] * 4^(k-1).
 template <int W>
 DEV Key<W> edge_target(const Key<W>& x, int k) {

@@ -3,6 +3,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <chrono>
 #include <iterator>
 
 namespace sdbg {
@@ -28,13 +29,25 @@ void* Pool::alloc(size_t bytes, hipStream_t s) {
   size_t want = round_size(bytes);
   {
     std::lock_guard<std::mutex> lk(mu_);
+    if (fail_after_ >= 0 && fail_after_-- == 0)
+      throw Error(-3, "device allocation of " + std::to_string(want) + " bytes failed (injected)");
     for (auto it = free_.lower_bound(want); it != free_.end() && it->first <= want + want / 2 + (4u << 20); ++it) {
       if (it->second.tagged && it->second.s != s) continue;
       void* p = it->second.p;
       cached_ -= it->first;
+      in_use_ += it->first;
+      peak_ = std::max(peak_, in_use_);
       free_.erase(it);
       return p;
     }
+  }
+  trace_activity("device allocation");
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+    const size_t reserve = std::max<size_t>(size_t(1) << 30, tot / 64);
+    if (fr < want + reserve) trim();
+  } else {
+    (void)hipGetLastError();
   }
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, want);
@@ -44,11 +57,15 @@ void* Pool::alloc(size_t bytes, hipStream_t s) {
     e = hipMalloc(&p, want);
     if (e != hipSuccess) {
       (void)hipGetLastError();
+      trace_activity("");
       throw Error(-3, "device allocation of " + std::to_string(want) + " bytes failed: " + hipGetErrorString(e));
     }
   }
+  trace_activity("");
   std::lock_guard<std::mutex> lk(mu_);
   size_[p] = want;
+  in_use_ += want;
+  peak_ = std::max(peak_, in_use_);
   return p;
 }
 
@@ -59,6 +76,7 @@ void Pool::release(void* p, hipStream_t s, bool tagged) {
   if (it == size_.end()) return;
   free_.emplace(it->second, Blk{p, s, tagged});
   cached_ += it->second;
+  in_use_ -= it->second;
 }
 
 void Pool::untag(hipStream_t s) {
@@ -67,18 +85,40 @@ void Pool::untag(hipStream_t s) {
     if (kv.second.tagged && kv.second.s == s) kv.second.tagged = false;
 }
 
+// Cached blocks no stream may still use are freed; hipFree can wait for the
+// device, so it is called after the pool's lock is released.
 void Pool::trim() {
-  std::lock_guard<std::mutex> lk(mu_);
-  for (auto it = free_.begin(); it != free_.end();) {
-    if (it->second.tagged) {
-      ++it;
-      continue;
+  std::vector<void*> give;
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto it = free_.begin(); it != free_.end();) {
+      if (it->second.tagged) {
+        ++it;
+        continue;
+      }
+      give.push_back(it->second.p);
+      size_.erase(it->second.p);
+      cached_ -= it->first;
+      it = free_.erase(it);
     }
-    (void)hipFree(it->second.p);
-    size_.erase(it->second.p);
-    cached_ -= it->first;
-    it = free_.erase(it);
   }
+  if (give.empty()) return;
+  trace_activity("releasing cached device memory");
+  for (void* p : give) (void)hipFree(p);
+  trace_activity("");
+}
+
+void Pool::stats(uint64_t* in_use, uint64_t* peak, uint64_t* cached, bool reset_peak) {
+  std::lock_guard<std::mutex> lk(mu_);
+  if (reset_peak) peak_ = in_use_;
+  if (in_use) *in_use = in_use_;
+  if (peak) *peak = peak_;
+  if (cached) *cached = cached_;
+}
+
+void Pool::fail_after(int64_t after) {
+  std::lock_guard<std::mutex> lk(mu_);
+  fail_after_ = after;
 }
 
 size_t Pool::cached_bytes() {
@@ -131,6 +171,32 @@ void Arena::release(void* p) {
   free_.emplace(start, sz);
 }
 
+Trace*& current_trace() {
+  thread_local Trace* t = nullptr;
+  return t;
+}
+
+namespace {
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+}  // namespace
+
+void trace_stage(const char* stage) {
+  if (Trace* t = current_trace()) {
+    t->stage.store(stage);
+    t->since_ns.store(now_ns());
+  }
+}
+
+void trace_activity(const char* activity) {
+  if (Trace* t = current_trace()) {
+    t->activity.store(activity);
+    t->since_ns.store(now_ns());
+  }
+}
+
 Arena*& current_arena() {
   thread_local Arena* a = nullptr;
   return a;
@@ -171,6 +237,7 @@ void prof_set_last_bytes(uint64_t bytes) {
 }
 
 Stage::Stage(Ctx& c, const char* name, uint64_t bytes) : c_(c), name_(name), bytes_(bytes) {
+  trace_stage(name);
   if (t_prof) {
     SDBG_HIP(hipEventCreate(&a_));
     SDBG_HIP(hipEventRecord(a_, c_.s));

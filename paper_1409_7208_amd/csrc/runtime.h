@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <cstdio>
 #include <map>
 #include <mutex>
@@ -33,6 +34,18 @@ struct Error : std::runtime_error {
     if (!(cond)) throw ::sdbg::Error((code), (msg));    \
   } while (0)
 
+// Where a thread's call is, for diagnosis: the last kernel stage it entered
+// and what it is waiting on, with the time it got there.  A thread points
+// `current_trace()` at a record it owns (the request loop does, per worker);
+// otherwise nothing is recorded.
+struct Trace {
+  std::atomic<const char*> stage{""}, activity{""};
+  std::atomic<int64_t> since_ns{0};
+};
+Trace*& current_trace();
+void trace_stage(const char* stage);
+void trace_activity(const char* activity);  // "" when done waiting
+
 // Caching allocator: device blocks are kept after release and handed out
 // again to requests of similar size, so that repeated calls do not pay for
 // hipMalloc/hipFree.  One pool per device.
@@ -41,6 +54,11 @@ struct Error : std::runtime_error {
 // stream that used it; it is tagged with that stream and handed out again
 // only to the same stream (stream order makes that safe) until the stream
 // has been synchronised, after which untag() makes it free for any stream.
+//
+// New device memory is taken only while a reserve stays free on the device
+// (1/64 of it, at least 1 GiB) for the runtime's own needs (queues, kernel
+// arguments) and other users of the device; cached blocks are given back
+// first when an allocation would cut into it.
 class Pool {
  public:
   void* alloc(size_t bytes, hipStream_t s);
@@ -48,6 +66,12 @@ class Pool {
   void untag(hipStream_t s);
   void trim();
   size_t cached_bytes();
+  // Bytes handed out and not released, and the most at any time since the
+  // last reset (reset_peak sets it to the current use).
+  void stats(uint64_t* in_use, uint64_t* peak, uint64_t* cached, bool reset_peak);
+  // Test hook: after `after` more allocations succeed, the next one fails
+  // with an out-of-device-memory error (once); negative disables.
+  void fail_after(int64_t after);
   static Pool& get();  // pool of the current device
 
  private:
@@ -60,6 +84,8 @@ class Pool {
   std::multimap<size_t, Blk> free_;
   std::unordered_map<void*, size_t> size_;
   size_t cached_ = 0;
+  uint64_t in_use_ = 0, peak_ = 0;
+  int64_t fail_after_ = -1;
 };
 
 // A fixed device region that stands in for the pool: while one is made
@@ -173,7 +199,12 @@ struct Ctx {
   Ctx& operator=(const Ctx&) = delete;
   template <typename T>
   DBuf<T> buf(size_t n) { return DBuf<T>(n, s); }
-  void sync() { SDBG_HIP(hipStreamSynchronize(s)); }
+  void sync() {
+    trace_activity("stream synchronisation");
+    const hipError_t e = hipStreamSynchronize(s);
+    trace_activity("");
+    SDBG_HIP(e);
+  }
   template <typename T>
   T d2h_one(const T* dev) {
     T v;

@@ -44,6 +44,7 @@ struct Job {
   bool alone = false;  // retry after running out of device memory: run alone
   uint64_t adm_seq = 0;     // admission bookkeeping (admission.h)
   bool adm_shared = false;
+  const sdbg::Trace* trace = nullptr;  // the worker's record while running
   int status = kWaiting;
   std::string err;
   sdbg_job_stats stats{};
@@ -51,14 +52,25 @@ struct Job {
   sdbg_graph* graph = nullptr;
 };
 
-// Device bytes a job may need at its peak: the two key buffers and counts
-// of the partition (16w + 4 bytes per (k+1)-mer occurrence), the working
-// arrays of mercy and of the builder (a few more bytes per occurrence),
-// and the packed reads.
+// Device bytes a job may need at its peak: per (k+1)-mer occurrence bound,
+// the two key buffers and counts of the partition, the mercy lookup table
+// and the edge-set merges (measured peaks of the library's pool, outputs
+// included: about 12 bytes per occurrence for one-word keys, which are
+// counted on one strand, and 42-51, 72-77 and 94-103 bytes for two-, three-
+// and four-word keys), with a margin; plus the reads and a constant for
+// small jobs.
 uint64_t job_footprint(uint64_t occ, uint64_t bases, uint32_t k) {
   const uint64_t w = (uint64_t)sdbg::key_words((int)k);
-  return occ * (16 * w + 8) + 3 * bases + (64ull << 20);
+  const uint64_t per_occ = w == 1 ? 24 : 28 * w + 16;
+  return occ * per_occ + 3 * bases + (64ull << 20);
 }
+
+// Jobs whose footprint exceeds this run alone.  A replay of the serving
+// workload with four jobs at once stalled for minutes on a job of 8.2M reads
+// at k = 61 (53 GB footprint) that had started next to others, while the
+// same job alone finishes in well under a second; until the cause is known,
+// large jobs do not share the device.
+constexpr uint64_t kExclusiveBytes = 8ull << 30;
 
 // Pinned host staging, kept for reuse: freeing pinned memory can wait for
 // the whole device, which would stall the jobs still running.
@@ -163,6 +175,7 @@ struct sdbg_server {
       j->edges = nullptr;
     }
     std::lock_guard<std::mutex> lk(mu);
+    j->trace = nullptr;
     if (adm.finish(j, rc == SDBG_E_NOMEM_DEVICE)) {
       // Device memory ran out next to other jobs: queued again at the head,
       // to run when the device is otherwise idle.
@@ -181,6 +194,8 @@ struct sdbg_server {
 
   void worker() {
     (void)hipSetDevice(device);
+    sdbg::Trace trace;
+    sdbg::current_trace() = &trace;
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
     for (;;) {
@@ -191,6 +206,9 @@ struct sdbg_server {
         if (stopping) break;
         j = adm.start_head();
         j->status = kRunning;
+        trace.stage.store("start");
+        trace.activity.store("");
+        j->trace = &trace;
         j->stats.status = kRunning;
         j->stats.start_s = now();
         cv_work.notify_all();  // the next head may fit too
@@ -213,6 +231,21 @@ int sdbg_job_footprint(const sdbg_reads* reads, const sdbg_params* params, uint6
     if (reads->n_reads) std::memcpy(o.data(), reads->offsets, sizeof(uint64_t) * (reads->n_reads + 1));
     SDBG_CHECK(o[0] == 0, SDBG_E_INVAL, "offsets[0] must be 0");
     *bytes = job_footprint(sdbg_abi::occ_bound(o, params->k), o.back(), params->k);
+    return SDBG_OK;
+  });
+}
+
+int sdbg_server_trace(sdbg_server* sv, uint64_t job_id, const char** stage, const char** activity, double* seconds) {
+  return sdbg_abi::guarded([&]() -> int {
+    SDBG_CHECK(sv && stage && activity && seconds, SDBG_E_INVAL, "null argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->jobs.find(job_id);
+    SDBG_CHECK(it != sv->jobs.end(), SDBG_E_INVAL, "unknown job id");
+    const sdbg::Trace* t = it->second->trace;
+    *stage = t ? t->stage.load() : "";
+    *activity = t ? t->activity.load() : "";
+    const int64_t ns = std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now().time_since_epoch()).count();
+    *seconds = t ? (double)(ns - t->since_ns.load()) * 1e-9 : 0.0;
     return SDBG_OK;
   });
 }
@@ -245,7 +278,7 @@ int sdbg_server_start(const sdbg_server_cfg* cfg, sdbg_server** out) {
       sdbg_params p{};
       p.mem_budget = sv->cfg.mem_budget;
       sv->budget = sdbg_abi::device_budget(&p);
-      sv->adm = sdbg_sched::Admission<Job*>(sv->budget);
+      sv->adm = sdbg_sched::Admission<Job*>(sv->budget, kExclusiveBytes);
       sv->t0 = Clock::now();
       for (uint32_t i = 0; i < sv->cfg.max_jobs; ++i) sv->workers.emplace_back([sv] { sv->worker(); });
     } catch (...) {

@@ -124,6 +124,10 @@ def load(path: str | None = None):
     lib.sdbg_profile_count.restype = ctypes.c_uint32
     lib.sdbg_profile_get.argtypes = [ctypes.c_uint32, P(ctypes.c_char_p), P(ctypes.c_double), P(ctypes.c_uint64)]
     lib.sdbg_profile_get.restype = ctypes.c_int
+    lib.sdbg_pool_stats.argtypes = [P(ctypes.c_uint64)] * 3 + [ctypes.c_int]
+    lib.sdbg_pool_stats.restype = ctypes.c_int
+    lib.sdbg_fail_alloc_after.argtypes = [ctypes.c_int64]
+    lib.sdbg_fail_alloc_after.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -131,6 +135,20 @@ def load(path: str | None = None):
 def _check(rc: int):
     if rc != SDBG_OK:
         raise SdbgError(rc, load().sdbg_last_error().decode(errors="replace"))
+
+
+def pool_stats(reset_peak: bool = False) -> dict:
+    """Device bytes of the library's pool on the current device: in use,
+    peak since the last reset, cached."""
+    a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load().sdbg_pool_stats(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), 1 if reset_peak else 0))
+    return {"in_use": a.value, "peak": b.value, "cached": c.value}
+
+
+def fail_alloc_after(after: int):
+    """Test hook: the pool allocation after `after` more successful ones
+    fails once (negative: off)."""
+    _check(load().sdbg_fail_alloc_after(after))
 
 
 def key_words(k: int) -> int:
@@ -300,6 +318,48 @@ def build(edges: Edges, stream=None) -> Graph:
     out = ctypes.POINTER(_Graph)()
     _check(lib.sdbg_build(edges._p, ctypes.byref(p), ctypes.byref(out)))
     return Graph(out)
+
+
+NAV_NODE, NAV_FORWARD, NAV_BACKWARD, NAV_OUTDEG, NAV_INDEG, NAV_LABEL = 1, 2, 3, 4, 5, 6
+
+
+class Index:
+    """Navigation index of a graph on the device (sdbg_index_build); the
+    graph must outlive it."""
+
+    def __init__(self, graph: Graph, stream=None):
+        lib = load()
+        if not getattr(lib, "_nav_api", False):
+            P = ctypes.POINTER
+            lib.sdbg_index_build.argtypes = [P(_Graph), P(_Params), ctypes.POINTER(ctypes.c_void_p)]
+            lib.sdbg_index_build.restype = ctypes.c_int
+            lib.sdbg_navigate.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64,
+                                          ctypes.c_void_p, ctypes.c_void_p]
+            lib.sdbg_navigate.restype = ctypes.c_int
+            lib._nav_api = True
+        p = _Params(graph.raw.k, 0, 0, 0, 0, _stream_ptr(stream))
+        h = ctypes.c_void_p()
+        _check(lib.sdbg_index_build(graph._p, ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self.k = graph.raw.k
+        self._graph = graph
+
+    def navigate(self, op: int, rows, out, stream=None):
+        """rows: device uint64/int64 tensor; out: device tensor of n words
+        (n * ceil(2k/64) for NAV_LABEL)."""
+        assert rows.is_cuda and out.is_cuda and rows.is_contiguous() and out.is_contiguous()
+        _check(load().sdbg_navigate(self._h, op, rows.data_ptr(), rows.numel(), out.data_ptr(), _stream_ptr(stream)))
+
+    def close(self):
+        if self._h:
+            load().sdbg_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def batch_run(sets, k: int, d: int = 2, mercy: bool = False, build: bool = True, prefix_len: int = 8,
@@ -482,6 +542,9 @@ def _server_api(lib):
     lib.sdbg_server_stop.restype = ctypes.c_int
     lib.sdbg_server_state.argtypes = [ctypes.c_void_p, P(_ServerInfo)]
     lib.sdbg_server_state.restype = ctypes.c_int
+    lib.sdbg_server_trace.argtypes = [ctypes.c_void_p, ctypes.c_uint64, P(ctypes.c_char_p), P(ctypes.c_char_p),
+                                      P(ctypes.c_double)]
+    lib.sdbg_server_trace.restype = ctypes.c_int
     lib.sdbg_job_footprint.argtypes = [P(_Reads), P(_Params), P(ctypes.c_uint64)]
     lib.sdbg_job_footprint.restype = ctypes.c_int
     lib._server_api = True
@@ -552,6 +615,13 @@ class Server:
         info = _ServerInfo()
         _check(load().sdbg_server_state(self._h, ctypes.byref(info)))
         return {f: getattr(info, f) for f, _ in _ServerInfo._fields_}
+
+    def trace(self, job_id: int) -> dict:
+        """Last kernel stage a running job entered, what it waits on, and
+        seconds since either changed."""
+        st, act, sec = ctypes.c_char_p(), ctypes.c_char_p(), ctypes.c_double()
+        _check(load().sdbg_server_trace(self._h, job_id, ctypes.byref(st), ctypes.byref(act), ctypes.byref(sec)))
+        return {"stage": (st.value or b"").decode(), "activity": (act.value or b"").decode(), "seconds": sec.value}
 
     def cancel(self, job_id: int) -> int:
         return load().sdbg_server_cancel(self._h, job_id)

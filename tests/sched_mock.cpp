@@ -3,7 +3,8 @@
 // do, and "run" them against a fake device of fixed memory, where a job
 // whose true peak does not fit what is left fails with out-of-memory.
 //
-// Input (stdin): one line "budget device_bytes workers time_scale", then
+// Input (stdin): one line "budget device_bytes workers time_scale
+// exclusive_above", then
 // one line per job "arrival_s footprint true_peak duration_s", in
 // submission order.  Output: one line per job "id status attempts
 // first_start_rank", then "ok" — or, if the jobs do not all finish within
@@ -66,7 +67,8 @@ int main() {
   uint64_t budget = 0, device = 0;
   unsigned workers = 0;
   double scale = 1.0;
-  if (std::scanf("%lu %lu %u %lf", &budget, &device, &workers, &scale) != 4) return 1;
+  uint64_t exclusive_above = 0;
+  if (std::scanf("%lu %lu %u %lf %lu", &budget, &device, &workers, &scale, &exclusive_above) != 5) return 1;
   std::vector<MockJob> jobs;
   MockJob j;
   while (std::scanf("%lf %lu %lu %lf", &j.arrival, &j.footprint, &j.peak, &j.duration) == 4) {
@@ -76,7 +78,7 @@ int main() {
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  sdbg_sched::Admission<MockJob*> adm(budget);
+  sdbg_sched::Admission<MockJob*> adm(budget, exclusive_above);
   FakeDevice dev;
   dev.cap = device;
   bool stopping = false;

@@ -144,3 +144,53 @@ def test_large_k_full_size_k61():
     """The large-k workload at k = 61 (two key words): 20M reads x 150 bp,
     3.56e9 occurrences."""
     _check_full(synth.metagenome_long(k=61), 61, 2, True, n_sample=2000)
+
+
+# ---- element-by-element parity at full size, through digests of every array
+import json  # noqa: E402
+import os  # noqa: E402
+import sys  # noqa: E402
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import digests  # noqa: E402
+
+_GOLD_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_digests.json")
+_GOLD = json.load(open(_GOLD_PATH)) if os.path.exists(_GOLD_PATH) else {}
+_READS: dict = {}
+
+
+def _full_reads(name: str):
+    if name == "metagenome":
+        return synth.metagenome(), 31
+    k = int(name[4:])
+    if "long" not in _READS:  # the same reads at every k
+        _READS.clear()
+        _READS["long"] = synth.metagenome_long()
+    return _READS["long"], k
+
+
+@pytest.mark.parametrize("name", [n for n in ("metagenome", "long21", "long41", "long61", "long81", "long99")
+                                  if n in _GOLD])
+def test_full_size_equals_partitioned_oracle(name):
+    """Every output of the full-size workloads, bit for bit: SHA-256 digests
+    of the keys, counts and every SdBG array (and the edges per key block)
+    against those of the partitioned oracle (tests/golden/fullsize_digests.json,
+    written by tests/golden/make_fullsize_digests.py)."""
+    gold = _GOLD[name]
+    rs, k = _full_reads(name)
+    say(f"full-size digests {name}: {rs.n_reads} reads, k={k}")
+    seq, off = to_device(rs)
+    e = sdbg.count_solid(seq, off, k, gold["d"], gold["mercy"])
+    del seq, off
+    keys, cnt = e.to_host()
+    ed = digests.edge_digest(keys, cnt, e.n_mercy, e.n_occ, k)
+    del keys, cnt
+    for f in ("n", "n_mercy", "n_occ", "blocks", "keys", "counts"):
+        assert ed[f] == gold["edges"][f], f
+    g = sdbg.build(e)
+    e.close()
+    h = g.to_host()
+    g.close()
+    gd = digests.graph_digest(h)
+    for f in ("m", "t", "F", "W", "last", "valid", "tip", "mult", "tip_seq"):
+        assert gd[f] == gold["graph"][f], f

@@ -131,3 +131,69 @@ def test_server_bad_input():
         e = srv.submit(synth.from_strings([], 21).seq, synth.from_strings([], 21).offsets, 21)
         r = srv.poll(e)
         assert r.status == 0 and r.edges.n == 0 and r.graph.m == 0
+
+
+@pytest.mark.parametrize("k", [21, 41, 61, 81, 99])
+def test_footprint_covers_peak_device_memory(k):
+    """The footprint a job is admitted with bounds the library's device
+    memory at the job's peak (pool bytes in use, outputs included)."""
+    cases = [synth.metagenome(scale=0.01), synth.tiny(scale=0.5),
+             synth.random_small(3000, 100, 150, 3000, 0.005, 11), synth.metagenome_long(scale=0.01)]
+    with sdbg.Server(max_jobs=1) as srv:
+        for rs in cases:
+            base = sdbg.pool_stats(reset_peak=True)["in_use"]
+            r = srv.poll(srv.submit(rs.seq, rs.offsets, k, 2, True))
+            assert r.status == 0, r.error
+            peak = sdbg.pool_stats()["peak"] - base
+            say(f"k={k} {rs.n_reads} reads: peak {peak} bytes, footprint {r.footprint} ({peak / r.footprint:.2f})")
+            r.edges.close()
+            r.graph.close()
+            assert peak <= r.footprint
+
+
+def test_injected_allocation_failures_leave_no_trace():
+    """A device allocation that fails at any point of a call returns
+    SDBG_E_NOMEM_DEVICE, releases everything the call held, and the next
+    call's result is unchanged; in the request loop the job fails alone."""
+    rs = synth.tiny(scale=0.05)
+    ref = _alone(rs, 21)
+    seq, off = to_device(rs)
+    import torch
+
+    torch.cuda.synchronize()
+    base = sdbg.pool_stats()["in_use"]
+    failed = 0
+    try:
+        for after in [0, 1, 2, 3, 5, 8, 13, 21, 34, 55, 89, 144]:
+            sdbg.fail_alloc_after(after)
+            say(f"allocation {after + 1} fails")
+            e = None
+            try:
+                e = sdbg.count_solid(seq, off, 21, 2, True)
+                sdbg.build(e).close()
+            except sdbg.SdbgError as err:
+                assert err.code == -3 and "injected" in str(err)
+                failed += 1
+            finally:
+                if e is not None:
+                    e.close()
+            sdbg.fail_alloc_after(-1)
+            assert sdbg.pool_stats()["in_use"] == base
+    finally:
+        sdbg.fail_alloc_after(-1)
+    assert failed >= 5
+    res = _alone(rs, 21)
+    assert res[0] == ref[0] and res[1] == ref[1]
+    assert np.array_equal(res[2], ref[2]) and np.array_equal(res[3], ref[3])
+    assert_graph_equal(res[4], ref[4])
+    with sdbg.Server(max_jobs=2) as srv:
+        sdbg.fail_alloc_after(4)
+        try:
+            bad = srv.poll(srv.submit(rs.seq, rs.offsets, 21, 2, True))
+        finally:
+            sdbg.fail_alloc_after(-1)
+        assert bad.status == -3
+        good = srv.poll(srv.submit(rs.seq, rs.offsets, 21, 2, True))
+        _same(good, ref)
+        good.edges.close()
+        good.graph.close()

@@ -34,8 +34,8 @@ def mock_bin(tmp_path_factory):
     return out
 
 
-def run_mock(binary, budget, device, workers, jobs, scale):
-    lines = [f"{budget} {device} {workers} {scale}"]
+def run_mock(binary, budget, device, workers, jobs, scale, exclusive_above=0):
+    lines = [f"{budget} {device} {workers} {scale} {exclusive_above}"]
     lines += [f"{a:.6f} {fp} {peak} {dur:.6f}" for a, fp, peak, dur in jobs]
     r = subprocess.run([binary], input="\n".join(lines) + "\n", capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, f"mock exit {r.returncode}\n{r.stdout[-3000:]}\n{r.stderr[-3000:]}"
@@ -73,7 +73,7 @@ def test_serving_trace_replay_terminates(mock_bin, peak_factor):
     budget = int(0.8 * device)
     for trace in serving_trace_footprints():
         jobs = [(a, fp, int(fp * peak_factor), occ / 20e9) for a, fp, occ in trace]
-        rows = run_mock(mock_bin, budget, device, 4, jobs, scale=0.05)
+        rows = run_mock(mock_bin, budget, device, 4, jobs, scale=0.05, exclusive_above=8 << 30)
         for (a, fp, peak, _), (_, status, attempts, _) in zip(jobs, rows):
             if peak <= device:
                 assert status == 0, (fp, peak, status)
@@ -93,7 +93,9 @@ def test_random_traces(mock_bin):
         arr = np.cumsum(rng.exponential(0.002, n))
         dur = rng.uniform(0.0005, 0.01, n)
         workers = int(rng.integers(1, 9))
-        rows = run_mock(mock_bin, budget, device, workers, list(zip(arr, fp, peak, dur)), scale=1.0)
+        excl = int(budget * rng.uniform(0.2, 0.6)) if rep % 2 else 0  # large jobs run alone
+        rows = run_mock(mock_bin, budget, device, workers, list(zip(arr, fp, peak, dur)), scale=1.0,
+                        exclusive_above=excl)
         for (i, status, attempts, first), p in zip(rows, peak):
             assert status == (0 if p <= device else -3)
             assert attempts in (1, 2)
