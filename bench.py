@@ -84,17 +84,89 @@ def make_workload(name: str, scale: float):
     return rs, desc
 
 
-def cpu_baseline(rs, n_reads: int):
-    """The oracle as it stands (single thread), on the first n_reads reads."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(rs, n_reads: int, n_reads_single: int):
+    """The oracle as it stands, on the host cores: the partitioned oracle
+    (the same definitions block by block on a thread pool, the CPU
+    counterpart of the construction) on the first n_reads reads, and the
+    string oracle on one thread on the first n_reads_single reads."""
     import oracle
 
+    threads = min(16, os.cpu_count() or 1)
     sub = rs.subset(n_reads)
     t0 = time.perf_counter()
-    e = oracle.count_solid(sub.seq, sub.offsets, rs.k, rs.d, rs.mercy)
-    oracle.build_graph(e.keys, e.counts, rs.k)
+    e = oracle.part_count_solid(sub.seq, sub.offsets, rs.k, rs.d, rs.mercy, threads=threads)
+    oracle.part_build_graph(e.keys, e.counts, rs.k, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": e.n_occ / dt / 1e9, "unit": "Gmer/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sub.n_reads} reads of the workload ({e.n_occ} (k+1)-mer occurrences), count+build, {dt:.1f} s"}
+    out = {"value": e.n_occ / dt / 1e9, "unit": "Gmer/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {sub.n_reads} reads of the workload ({e.n_occ} (k+1)-mer occurrences), count+build by "
+                     f"the partitioned oracle (256 key blocks on {threads} threads), {dt:.1f} s",
+           "cpu_model": cpu_model()}
+    sub1 = rs.subset(n_reads_single)
+    t0 = time.perf_counter()
+    e1 = oracle.count_solid(sub1.seq, sub1.offsets, rs.k, rs.d, rs.mercy)
+    oracle.build_graph(e1.keys, e1.counts, rs.k)
+    dt1 = time.perf_counter() - t0
+    out["single_thread"] = {"value": e1.n_occ / dt1 / 1e9, "unit": "Gmer/s", "cores": 1,
+                            "sample": f"first {sub1.n_reads} reads, string oracle, {dt1:.1f} s"}
+    return out
+
+
+def large_k_rates(steps: int):
+    """Gmer/s of the large-k workload (same community, 20M reads x 150 bp,
+    mercy on) at each k, reads resident on the device; HBM traffic per
+    occurrence from the library's per-launch algorithmic bytes."""
+    import torch
+
+    from paper_1409_7208_amd import sdbg, synth
+
+    t0 = time.perf_counter()
+    rs = synth.metagenome_long()
+    log(f"large-k workload: {rs.n_reads} reads generated in {time.perf_counter() - t0:.1f} s")
+    seq = torch.from_numpy(rs.seq).to("cuda:0")
+    off = torch.from_numpy(rs.offsets.view(np.int64)).to("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for k in (21, 41, 61, 81, 99):
+        def step():
+            e = sdbg.count_solid(seq, off, k, 2, True, stream=stream)
+            g = sdbg.build(e, stream=stream)
+            res = (e.n_occ, e.n)
+            g.close()
+            e.close()
+            return res
+
+        step()
+        torch.cuda.synchronize()
+        sdbg.profile_enable(True)
+        sdbg.profile_reset()
+        ea = torch.cuda.Event(enable_timing=True)
+        eb = torch.cuda.Event(enable_timing=True)
+        ea.record(stream)
+        for _ in range(steps):
+            r = step()
+        eb.record(stream)
+        torch.cuda.synchronize()
+        sdbg.profile_enable(False)
+        ms = ea.elapsed_time(eb) / steps
+        step_bytes = sum(b for _, _, b in sdbg.profile_records()) / steps
+        gms = r[0] / (ms / 1e3) / 1e9
+        rows.append({"k": k, "n_occ": int(r[0]), "edges": int(r[1]), "ms_per_step": round(ms, 2),
+                     "gmer_s": round(gms, 3), "bytes_per_occ": round(step_bytes / r[0], 1),
+                     "step_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+        log(f"large k={k}: {ms:.1f} ms/step, {gms:.2f} Gmer/s")
+    del seq, off
+    torch.cuda.synchronize()
+    return rows
 
 
 def bench_batch(args):
@@ -282,8 +354,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="metagenome")
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--cpu-reads", type=int, default=100000)
+    ap.add_argument("--cpu-reads", type=int, default=1000000, help="reads of the partitioned-oracle CPU baseline")
+    ap.add_argument("--cpu-reads-single", type=int, default=50000, help="reads of the single-thread oracle")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-large-k", action="store_true", help="skip the large-k figures (k = 21..99)")
+    ap.add_argument("--large-k-steps", type=int, default=2)
     ap.add_argument("--stages", action="store_true", help="print per-kernel breakdown to stderr")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (a reference kernel for hardware byte counters)")
@@ -436,10 +511,15 @@ def main():
                      "floor_bytes_per_occ": round(floor_b, 2),
                      "floor_frac": round(value * floor_b / HBM_PEAK_GBS, 4)}
 
+    large = None
+    if not args.no_large_k and args.workload == "metagenome" and args.scale == 1.0:
+        del seq, off
+        large = large_k_rates(args.large_k_steps)
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(rs, args.cpu_reads)
+        cpu = cpu_baseline(rs, args.cpu_reads, args.cpu_reads_single)
         log(f"  {cpu}")
 
     out = {
@@ -465,6 +545,8 @@ def main():
     }
     if host_rate is not None:
         out["host_input_gmer_s"] = round(host_rate, 3)
+    if large is not None:
+        out["large_k"] = large
     print(json.dumps(out), flush=True)
 
 

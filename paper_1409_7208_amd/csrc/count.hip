@@ -1821,6 +1821,25 @@ __global__ void k_gather_strided(const uint32_t* __restrict__ src, uint64_t stri
   if (i < n) dst[i] = src[(uint64_t)i * stride];
 }
 
+// The two ping-pong buffer pointers, written on the stream (no host wait).
+__global__ void k_set_bufs(uint64_t** db, uint64_t* a, uint64_t* b) {
+  if (threadIdx.x == 0) {
+    db[0] = a;
+    db[1] = b;
+  }
+}
+
+// A segment list of one segment: all n keys, in buffer 0, `bit` key bits.
+__global__ void k_seg_single(SegView v, uint64_t n, int bit) {
+  if (threadIdx.x == 0) {
+    v.off[0] = 0;
+    v.len[0] = n;
+    v.bit[0] = (uint16_t)bit;
+    v.buf[0] = 0;
+    v.D[0] = 0;
+  }
+}
+
 template <int W>
 struct Counter {
   static constexpr int IPT = Tune<W>::IPT, TK = Tune<W>::TK, CAP = Tune<W>::CAP;
@@ -1880,17 +1899,16 @@ struct Counter {
     for (int level = 0; level <= kbits; ++level) {
       if (L.n == 0) return;
       unsigned long long hs[3];
-      for (int pass = 0; pass < 2; ++pass) {
-        fill<uint64_t>(reinterpret_cast<uint64_t*>(st.get()), 3, 0, c);
-        k_seg_stats<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), leaf_cap(), st.get());
-        c.check_launch("seg_stats");
-        c.d2h(hs, st.get(), 3);
-        if (hs[2] == 0 || pass == 1) break;
-        // segments a cut left whole: skip their common bits
+      if (level > 0) {
+        // segments the last cut left whole: skip their common bits
         k_seg_squeeze<W><<<(unsigned)std::min<uint64_t>(L.n, 4096), SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs,
                                                                                           leaf_cap());
         c.check_launch("seg_squeeze");
       }
+      fill<uint64_t>(reinterpret_cast<uint64_t*>(st.get()), 3, 0, c);
+      k_seg_stats<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), leaf_cap(), st.get());
+      c.check_launch("seg_stats");
+      c.d2h(hs, st.get(), 3);
       if (hs[0] == 0) return;
       const uint64_t avg = hs[1] / hs[0];
       VLOG("refine level %d: %llu segments, %llu oversized holding %llu keys", level, (unsigned long long)L.n,
@@ -1981,19 +1999,13 @@ struct Counter {
     SDBG_CHECK(n < (1ull << 32), -3, "key array too large for one partition group");
     DBuf<uint64_t> other = c.buf<uint64_t>(n * W);
     DBuf<uint32_t> cnt = c.buf<uint32_t>(n);
-    uint64_t* hb[2] = {keys.get(), other.get()};
     DBuf<uint64_t*> db = c.buf<uint64_t*>(2);
-    c.h2d(db.get(), hb, 2);
+    k_set_bufs<<<1, 64, 0, c.s>>>(db.get(), keys.get(), other.get());
+    c.check_launch("set_bufs");
     SegList L;
     L.alloc(c, 1);
-    uint64_t z = 0, nn = n;
-    uint16_t bit = (uint16_t)kb;
-    uint8_t b0 = 0;
-    c.h2d(L.off.get(), &z, 1);
-    c.h2d(L.len.get(), &nn, 1);
-    c.h2d(L.bit.get(), &bit, 1);
-    c.h2d(L.buf.get(), &b0, 1);
-    c.h2d(L.D.get(), &b0, 1);
+    k_seg_single<<<1, 64, 0, c.s>>>(L.view(), n, kb);
+    c.check_launch("seg_single");
     refine(L, db.get(), kb);
     DBuf<uint32_t> ocnt;
     DBuf<uint64_t> lk;
@@ -2310,9 +2322,9 @@ struct Counter {
       const uint64_t cap_keys = groups.size() == 1 ? N : max_keys;
       DBuf<uint64_t> bufA = c.buf<uint64_t>(cap_keys * W), bufB = c.buf<uint64_t>(cap_keys * W);
       DBuf<uint32_t> cnt = c.buf<uint32_t>(cap_keys);
-      uint64_t* hb[2] = {bufA.get(), bufB.get()};
       DBuf<uint64_t*> db = c.buf<uint64_t*>(2);
-      c.h2d(db.get(), hb, 2);
+      k_set_bufs<<<1, 64, 0, c.s>>>(db.get(), bufA.get(), bufB.get());
+      c.check_launch("set_bufs");
       for (size_t gi = 0; gi < groups.size(); ++gi) {
         ExArgs ga = ea;
         ga.glo = groups[gi].first;
@@ -2541,9 +2553,9 @@ struct Counter {
     SDBG_CHECK(N <= 0xFFFFFFFFull, -3, "read sets too large for one pass");
     DBuf<uint64_t> bufA = c.buf<uint64_t>(N * W), bufB = c.buf<uint64_t>(N * W);
     DBuf<uint32_t> cnt = c.buf<uint32_t>(N);
-    uint64_t* hb[2] = {bufA.get(), bufB.get()};
     DBuf<uint64_t*> db = c.buf<uint64_t*>(2);
-    c.h2d(db.get(), hb, 2);
+    k_set_bufs<<<1, 64, 0, c.s>>>(db.get(), bufA.get(), bufB.get());
+    c.check_launch("set_bufs");
     if (N) {
       Stage st_(c, "ex_scatter", 3 * pr.words * 8 + NT * nbins * 4 + N * 8 * W);
       k_ex_scatter<W, IPT><<<(unsigned)NT, SDBG_BLOCK, 0, c.s>>>(ea, tab.get(), NT, bufA.get());
