@@ -33,76 +33,165 @@ inline unsigned grid1(uint64_t n) {
   return (unsigned)(g ? g : 1);
 }
 
-// Per edge: bit0 minus, bit1 '$' row for its target (target has no
-// out-edge, and this is the first edge into it), bit2 dummy row for its
-// source (first edge of the source, source has no in-edge), bit3 last.
-// Lower bounds of two queries in one sorted view, searched in lockstep so
-// that the loads of the two searches overlap (v.n >= 1).
+// First index in [lo, hi) whose key is >= q.
 template <int W>
-DEV void sv_lower2(const SortedView& v, const Key<W>& q1, const Key<W>& q2, uint64_t* r1, uint64_t* r2) {
-  const uint32_t b1 = key_bits<W>(q1, v.kbits - v.db, v.db), b2 = key_bits<W>(q2, v.kbits - v.db, v.db);
-  uint64_t lo1 = v.dir[b1], hi1 = v.dir[b1 + 1], lo2 = v.dir[b2], hi2 = v.dir[b2 + 1];
-  while (lo1 < hi1 || lo2 < hi2) {
-    const bool a1 = lo1 < hi1, a2 = lo2 < hi2;
-    const uint64_t m1 = (lo1 + hi1) >> 1, m2 = (lo2 + hi2) >> 1;
-    const Key<W> k1 = key_load<W>(v.keys + (a1 ? m1 : 0) * W);
-    const Key<W> k2 = key_load<W>(v.keys + (a2 ? m2 : 0) * W);
-    if (a1) {
-      if (key_less<W>(k1, q1))
-        lo1 = m1 + 1;
-      else
-        hi1 = m1;
-    }
-    if (a2) {
-      if (key_less<W>(k2, q2))
-        lo2 = m2 + 1;
-      else
-        hi2 = m2;
-    }
+DEV uint64_t lower_in(const uint64_t* keys, uint64_t lo, uint64_t hi, const Key<W>& q) {
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (key_less<W>(key_load<W>(keys + mid * W), q))
+      lo = mid + 1;
+    else
+      hi = mid;
   }
-  *r1 = lo1;
-  *r2 = lo2;
+  return lo;
+}
+
+// Row flags in two passes over tiles of consecutive edges.  The target of
+// an edge with label c and source v is the node c*4^(k-1) + (v div 4), so
+// over a tile (sources ascending) the targets of its label-c edges ascend
+// within one range, and the out-edges of those targets form one stretch of
+// E per label.  A tile finds its four stretches (8 searches), stages them
+// in LDS and answers every edge's "has my target an out-edge" there (in the
+// stretch in global memory when they do not fit).  The same answer says
+// that the found target has an in-edge: its first out-edge is marked in
+// hin, and the second pass gives the dummy-row bit to every first edge of
+// a source that no edge marked.  Final flags per edge: bit0 minus, bit1
+// '$' row for its target (the target has no out-edge and this is the first
+// edge into it), bit2 dummy row for its source (first edge of the source,
+// and the source has no in-edge), bit3 last; the first pass keeps "first
+// edge of its source" in bit4, which the second replaces by bit2.
+template <int W>
+struct RowTile {
+  static constexpr int IPT = W == 1 ? 8 : (W == 2 ? 4 : 2);
+  static constexpr int TILE = SDBG_BLOCK * IPT;
+  static constexpr int RCAP = 2 * TILE;  // staged stretch keys (about TILE expected)
+};
+
+template <int W>
+DEV uint64_t lds_lower(const uint64_t* R, uint32_t lo, uint32_t hi, const Key<W>& q) {
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (key_less<W>(key_load<W>(R + (uint64_t)mid * W), q))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
 }
 
 template <int W>
-__global__ void k_row_flags(SortedView E, int k, uint8_t* __restrict__ fl) {
-  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (i >= E.n) return;
-  const Key<W> x = key_load<W>(E.keys + i * W);
-  const uint64_t c = x.w[W - 1] & 3;
-  const Key<W> grp = key_shr<W>(x, 4), src = key_shr<W>(x, 2);
-  bool minus = false;
-  for (uint64_t j = i; j-- > 0;) {
-    Key<W> y = key_load<W>(E.keys + j * W);
-    if (!key_eq<W>(key_shr<W>(y, 4), grp)) break;
-    if ((y.w[W - 1] & 3) == c) {
-      minus = true;
-      break;
+__global__ __launch_bounds__(SDBG_BLOCK) void k_row_out(SortedView E, int k, uint8_t* __restrict__ fl,
+                                                        uint8_t* __restrict__ hin) {
+  constexpr int IPT = RowTile<W>::IPT, TILE = RowTile<W>::TILE, RCAP = RowTile<W>::RCAP;
+  __shared__ uint64_t R[RCAP * W];
+  __shared__ uint64_t rg[8];
+  const uint64_t i0 = blockIdx.x * (uint64_t)TILE;
+  const uint64_t i1 = i0 + TILE < E.n ? i0 + TILE : E.n;
+  if (threadIdx.x < 8) {
+    // stretch of label c = threadIdx.x / 2: from the first key >= T(first
+    // edge) * 4 (even threads) to the first key > T(last edge) * 4 + 3
+    const uint32_t c = threadIdx.x >> 1;
+    const bool hi = threadIdx.x & 1;
+    const Key<W> xs = key_load<W>(E.keys + (hi ? i1 - 1 : i0) * W);
+    const Key<W> T4 = key_shl<W>(key_or2<W>(key_shr<W>(xs, 4), 2 * k - 2, c), 2);
+    rg[threadIdx.x] = hi ? sv_upper<W>(E, key_or_low<W>(T4, 3)) : sv_lower<W>(E, T4);
+  }
+  __syncthreads();
+  uint64_t lo[4];
+  uint32_t off[5];
+  off[0] = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    lo[c] = rg[2 * c];
+    const uint64_t len = rg[2 * c + 1] - rg[2 * c];
+    off[c + 1] = off[c] + (uint32_t)(len < (uint64_t)RCAP ? len : (uint64_t)RCAP + 1);
+  }
+  const bool staged = off[4] <= (uint32_t)RCAP;
+  if (staged) {
+    for (uint32_t j = threadIdx.x; j < off[4]; j += SDBG_BLOCK) {
+      int c = 0;
+#pragma unroll
+      for (int u = 1; u < 4; ++u)
+        if (j >= off[u]) c = u;
+      key_store<W>(R + (uint64_t)j * W, key_load_g<W>(E.keys + (lo[c] + (j - off[c])) * W));
     }
   }
-  const bool first = i == 0 || !key_eq<W>(key_shr<W>(key_load<W>(E.keys + (i - 1) * W), 2), src);
-  const bool last = i + 1 == E.n || !key_eq<W>(key_shr<W>(key_load<W>(E.keys + (i + 1) * W), 2), src);
-  // out-edges of the target: keys T*4 + c'; in-edges of the source: keys
-  // (c' + 4*src[0..k-2])*4 + src[k-1], among the keys sharing key div 16
-  const Key<W> T = edge_target<W>(x, k);
-  const uint64_t top = key_bits<W>(src, 2 * k - 2, 2);
-  const Key<W> base = key_or_low<W>(key_shl<W>(key_lowbits<W>(src, 2 * k - 2), 4), top);
-  uint64_t io, ii;
-  sv_lower2<W>(E, key_shl<W>(T, 2), base, &io, &ii);
-  const bool has_out = io < E.n && key_eq<W>(key_shr<W>(key_load<W>(E.keys + io * W), 2), T);
-  bool has_in = false;
-  const Key<W> hi4 = key_shr<W>(base, 4);
-  for (; ii < E.n; ++ii) {
-    const Key<W> y = key_load<W>(E.keys + ii * W);
-    if (!key_eq<W>(key_shr<W>(y, 4), hi4)) break;
-    if ((y.w[W - 1] & 3) == top) {
-      has_in = true;
-      break;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) {
+    const uint64_t i = i0 + (uint64_t)q * SDBG_BLOCK + threadIdx.x;
+    if (i >= i1) continue;
+    const Key<W> x = key_load<W>(E.keys + i * W);
+    const uint32_t c = (uint32_t)(x.w[W - 1] & 3);
+    const Key<W> T = edge_target<W>(x, k);
+    const Key<W> T4 = key_shl<W>(T, 2);
+    bool has_out;
+    uint64_t io;
+    if (staged) {
+      uint32_t end = off[0], beg = off[0];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if ((uint32_t)u == c) {
+          beg = off[u];
+          end = off[u + 1];
+        }
+      const uint32_t j = (uint32_t)lds_lower<W>(R, beg, end, T4);
+      has_out = j < end && key_eq<W>(key_shr<W>(key_load<W>(R + (uint64_t)j * W), 2), T);
+      io = j - beg;
+    } else {
+      uint64_t l = 0, h = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if ((uint32_t)u == c) {
+          l = rg[2 * u];
+          h = rg[2 * u + 1];
+        }
+      const uint64_t j = lower_in<W>(E.keys, l, h, T4);
+      has_out = j < h && key_eq<W>(key_shr<W>(key_load<W>(E.keys + j * W), 2), T);
+      io = j - l;
+    }
+    if (has_out) {
+      uint64_t l = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if ((uint32_t)u == c) l = lo[u];
+      hin[l + io] = 1;
+    }
+    const Key<W> grp = key_shr<W>(x, 4), src = key_shr<W>(x, 2);
+    bool minus = false;
+    for (uint64_t j = i; j-- > 0;) {
+      const Key<W> y = key_load<W>(E.keys + j * W);
+      if (!key_eq<W>(key_shr<W>(y, 4), grp)) break;
+      if ((y.w[W - 1] & 3) == c) {
+        minus = true;
+        break;
+      }
+    }
+    const bool first = i == 0 || !key_eq<W>(key_shr<W>(key_load<W>(E.keys + (i - 1) * W), 2), src);
+    const bool last = i + 1 == E.n || !key_eq<W>(key_shr<W>(key_load<W>(E.keys + (i + 1) * W), 2), src);
+    fl[i] = (uint8_t)((minus ? 1 : 0) | (!minus && !has_out ? 2 : 0) | (last ? 8 : 0) | (first ? 16 : 0));
+  }
+}
+
+// Second pass: eight edges per thread.
+__global__ __launch_bounds__(SDBG_BLOCK) void k_row_in(uint8_t* __restrict__ fl, const uint8_t* __restrict__ hin,
+                                                       uint64_t n) {
+  const uint64_t b = (blockIdx.x * (uint64_t)SDBG_BLOCK + threadIdx.x) * 8;
+  if (b >= n) return;
+  if (b + 8 <= n) {
+    uint64_t f = *reinterpret_cast<const uint64_t*>(fl + b);
+    const uint64_t h = *reinterpret_cast<const uint64_t*>(hin + b);
+    const uint64_t first = f & 0x1010101010101010ull;
+    // a byte of h is 0 or 1: (h * 16) marks the bytes whose edge was found
+    const uint64_t zin = first & ~(h << 4);
+    f = (f & ~0x1010101010101010ull) | (zin >> 2);
+    *reinterpret_cast<uint64_t*>(fl + b) = f;
+  } else {
+    for (uint64_t i = b; i < n; ++i) {
+      const uint8_t f = fl[i];
+      fl[i] = (uint8_t)((f & ~16) | ((f & 16) && !hin[i] ? 4 : 0));
     }
   }
-  const bool zout = !minus && !has_out;
-  const bool zin = first && !has_in;
-  fl[i] = (uint8_t)((minus ? 1 : 0) | (zout ? 2 : 0) | (zin ? 4 : 0) | (last ? 8 : 0));
 }
 
 // Split of the flagged edges into 4 classes, keeping edge order within a
@@ -196,18 +285,6 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_split_write(SortedView E, const 
       key_store<W>(out + p * W, v);
     }
   }
-}
-
-template <int W>
-DEV uint64_t lower_in(const uint64_t* keys, uint64_t lo, uint64_t hi, const Key<W>& q) {
-  while (lo < hi) {
-    uint64_t mid = (lo + hi) >> 1;
-    if (key_less<W>(key_load<W>(keys + mid * W), q))
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
 }
 
 // The dummy rows arrive as 4 runs (by the source's last base), each sorted
@@ -457,9 +534,20 @@ struct Builder {
     SortedView E = view(keys, n, kb, edir);
     DBuf<uint8_t> fl = c.buf<uint8_t>(n);
     {
-      Stage st_(c, "row_flags", n * (8 * W + 1));
-      k_row_flags<W><<<grid1(n), SDBG_BLOCK, 0, c.s>>>(E, k, fl.get());
-      c.check_launch("row_flags");
+      DBuf<uint8_t> hin = c.buf<uint8_t>(n);
+      fill<uint8_t>(hin.get(), n, 0, c);
+      {
+        // every edge key once, each stretch of targets once (about as many
+        // keys), flags and marks
+        Stage st_(c, "row_flags", n * (16 * W + 2));
+        k_row_out<W><<<(unsigned)ceil_div(n, RowTile<W>::TILE), SDBG_BLOCK, 0, c.s>>>(E, k, fl.get(), hin.get());
+        c.check_launch("row_flags");
+      }
+      {
+        Stage st_(c, "row_in", n * 3);
+        k_row_in<<<grid1(ceil_div(n, 8)), SDBG_BLOCK, 0, c.s>>>(fl.get(), hin.get(), n);
+        c.check_launch("row_in");
+      }
     }
     DBuf<uint64_t> zo, zi_runs, zi;
     uint64_t bo[5], bi[5];
