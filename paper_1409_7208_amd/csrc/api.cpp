@@ -298,11 +298,13 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
       off[s] = host_offsets(c, &sets[s]);
       occ[s] = occ_bound(off[s], k);
     }
-    const uint64_t max_keys = std::min<uint64_t>(device_budget(params) / batch_bytes_per_key(w), 0xFFFFFFFFull);
     const bool shared = !(params->mercy && params->d >= 2);
     sdbg::CountParams P{(int)k, params->d, params->mercy != 0, (int)params->prefix_len, params->mem_budget};
     uint64_t s0 = 0;
     while (s0 < n_sets) {
+      // the budget is taken again for every pass: the outputs of the
+      // earlier passes stay on the device
+      const uint64_t max_keys = std::min<uint64_t>(device_budget(params) / batch_bytes_per_key(w), 0xFFFFFFFFull);
       if (!shared || occ[s0] > max_keys) {
         // one set alone on the single-set path (mercy, or larger than a pass)
         sdbg::EdgesOut eo;

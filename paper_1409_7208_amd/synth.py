@@ -247,6 +247,41 @@ def batch_set(i: int, n_sets: int = 4096, read_scale: float = 1.0) -> ReadSet:
     return ReadSet(seq, off, k=31, d=2, mercy=False, name=f"batch[{i}]")
 
 
+def batch_set_device(i: int, n_sets: int = 4096, read_scale: float = 1.0, device: str = "cuda:0"):
+    """Set i of the batch recipe drawn on the device with torch's generator
+    (seeded per set): the same genome length, read count, read length,
+    strand mix and error rate as batch_set(i), other random numbers.  For
+    runs at full read scale, which are too large to draw on the host in a
+    reasonable time (4096 sets hold about 590M reads).  Returns (ASCII reads,
+    int64 offsets), both on the device."""
+    import torch
+
+    meta = rng_for(4, 0)
+    glen = meta.integers(20_000, 500_001, size=n_sets)
+    nreads = log_uniform_int(1_000, 1_000_000, n_sets, meta)
+    seed = int(rng_for(4, 1 + i).integers(0, 2**62))
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    L, G = 100, int(glen[i])
+    n = max(1, int(round(nreads[i] * read_scale)))
+    genome = torch.randint(0, 4, (G,), generator=gen, device=device, dtype=torch.uint8)
+    ascii = torch.tensor(list(b"ACGT"), dtype=torch.uint8, device=device)
+    seq = torch.empty(n * L, dtype=torch.uint8, device=device)
+    cols = torch.arange(L, device=device)
+    for r0 in range(0, n, 1 << 18):
+        c = min(1 << 18, n - r0)
+        start = torch.randint(0, G - L + 1, (c,), generator=gen, device=device)
+        codes = genome[start[:, None] + cols[None, :]]
+        rc = torch.rand(c, generator=gen, device=device) < 0.5
+        codes = torch.where(rc[:, None], 3 - codes.flip(1), codes)
+        err = torch.rand((c, L), generator=gen, device=device) < 0.01
+        shift = torch.randint(1, 4, (c, L), generator=gen, device=device, dtype=torch.uint8)
+        codes = torch.where(err, (codes + shift) & 3, codes)
+        seq[r0 * L : (r0 + c) * L] = ascii[codes.long()].reshape(-1)
+    offsets = torch.arange(n + 1, device=device, dtype=torch.int64) * L
+    return seq, offsets
+
+
 @dataclasses.dataclass
 class Job:
     arrival: float  # seconds from trace start
