@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # while the kernel sources hash to the value recorded there.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_metagenome_k31.md")
 KERNEL_SOURCES = ["paper_1409_7208_amd/csrc/" + f for f in
-                  ("count.hip", "build.hip", "prims.hip", "device.h", "kernels.h", "prims.h")]
+                  ("count.hip", "build.hip", "prims.hip", "device.h", "kernels.h", "prims.h", "windows.h", "wslots.h")]
 
 
 def kernel_source_hash() -> str:
@@ -224,11 +224,26 @@ def bench_batch(args):
         fn()  # warm-up (device memory pool)
         torch.cuda.synchronize()
         times = []
+        if args.stages:
+            sdbg.profile_enable(True)
+            sdbg.profile_reset()
         for _ in range(max(1, args.steps)):
             w0 = time.perf_counter()
             occ = fn()
             torch.cuda.synchronize()
             times.append(time.perf_counter() - w0)
+        if args.stages:
+            sdbg.profile_enable(False)
+            agg: dict[str, list] = {}
+            for kname, kt, kb in sdbg.profile_records():
+                a = agg.setdefault(kname, [0, 0.0, 0])
+                a[0] += 1
+                a[1] += kt
+                a[2] += kb
+            steps = max(1, args.steps)
+            for kname, (n, kt, kb) in sorted(agg.items(), key=lambda x: -x[1][1])[:14]:
+                log(f"  {name} {kname:14s} launches={n // steps:6d}  {kt / steps:9.2f} ms  "
+                    f"{kb / (kt * 1e-3) / 1e9 if kt > 0 else 0:8.1f} GB/s")
         t = float(np.median(times))
         out[name] = {"seconds": round(t, 4), "gmer_s": round(occ / t / 1e9, 3)}
         log(f"{name}: {t * 1e3:.1f} ms, {occ / t / 1e9:.3f} Gmer/s over {len(dev)} sets")

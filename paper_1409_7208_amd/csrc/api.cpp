@@ -4,9 +4,12 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <cstdlib>
 #include <cstring>
 #include <thread>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -129,6 +132,9 @@ uint64_t batch_bytes_per_key(uint32_t w) { return 32ull * w + 16; }
 
 // Host threads (and streams) building the graphs of a batch.
 constexpr unsigned kBuildThreads = 4;
+// Device memory a counting pass of a batch leaves to the graph builds that
+// run next to it, beyond their estimated needs.
+constexpr uint64_t kBuildReserve = 8ull << 30;
 
 uint64_t device_budget(const sdbg_params* p) {
   if (p->mem_budget) return p->mem_budget;
@@ -280,6 +286,156 @@ int sdbg_build(const sdbg_edges* edges, const sdbg_params* params, sdbg_graph** 
   });
 }
 
+// Graph builders of a batch: a few host threads, each on a stream of its
+// own, take the sets whose edge sets are ready (pushed after each counting
+// pass) and build their graphs while the next pass counts, so that the
+// builds -- and one set's size read-backs -- overlap the counting and the
+// other builds.  The destructor stops and joins the threads (also when the
+// counting throws); errors are collected for rethrow().
+class BatchBuilders {
+ public:
+  BatchBuilders(sdbg_edges** edges, sdbg_graph** graphs, uint64_t n_sets, uint32_t k) : edges_(edges), graphs_(graphs),
+                                                                                        k_(k) {
+    int dev = 0;
+    SDBG_HIP(hipGetDevice(&dev));
+    const unsigned nth = (unsigned)std::min<uint64_t>(kBuildThreads, n_sets);
+    for (unsigned t = 0; t < nth; ++t) th_.emplace_back([this, dev] { work(dev); });
+  }
+  ~BatchBuilders() { finish(/*stop=*/true); }
+  void push(uint64_t s0, uint64_t s1) {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      for (uint64_t s = s0; s < s1; ++s) {
+        q_.push_back(s);
+        pending_ += build_bytes(s);
+      }
+    }
+    cv_.notify_all();
+  }
+  // Device memory the queued and running builds may still take (an upper
+  // estimate); the counting passes leave it out of their budget.
+  uint64_t pending() {
+    std::lock_guard<std::mutex> g(mu_);
+    return pending_;
+  }
+  // A counting pass starts / has ended (builds that run out of device
+  // memory during a pass wait for its end and try again).
+  void pass(bool running) {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      counting_ = running;
+      if (!running) ++epoch_;
+    }
+    done_.notify_all();
+  }
+  // Waits until the pending estimate is at most `limit` (or a build failed).
+  void wait_below(uint64_t limit) {
+    std::unique_lock<std::mutex> g(mu_);
+    done_.wait(g, [&] { return pending_ <= limit || failed_; });
+  }
+  // All sets pushed: wait for the builds, rethrow the first error.
+  void finish_and_check() {
+    finish(false);
+    if (!err_.empty()) throw sdbg::Error(err_rc_, err_);
+  }
+
+ private:
+  void finish(bool stop) {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      closed_ = true;
+      if (stop) failed_ = true;
+    }
+    cv_.notify_all();
+    done_.notify_all();
+    for (auto& t : th_)
+      if (t.joinable()) t.join();
+  }
+  void work(int dev) {
+    const int rc = guarded([&]() -> int {
+      SDBG_HIP(hipSetDevice(dev));
+      hipStream_t st = nullptr;
+      SDBG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      try {
+        sdbg::Ctx c2(st);
+        for (;;) {
+          uint64_t i;
+          {
+            std::unique_lock<std::mutex> g(mu_);
+            cv_.wait(g, [&] { return failed_ || closed_ || !q_.empty(); });
+            if (failed_ || q_.empty()) break;
+            i = q_.front();
+            q_.pop_front();
+          }
+          sdbg::GraphOut go;
+          for (;;) {
+            uint64_t epoch;
+            {
+              std::lock_guard<std::mutex> g(mu_);
+              epoch = epoch_;
+            }
+            try {
+              sdbg::build_graph(edges_[i]->keys, edges_[i]->count, edges_[i]->n, (int)k_, c2, &go, false);
+              c2.sync();
+              break;
+            } catch (const sdbg::Error& e) {
+              // out of device memory while a counting pass runs: wait for
+              // the pass to end, give back cached memory, and try again
+              if (e.code != -3) throw;
+              c2.sync();
+              std::unique_lock<std::mutex> g(mu_);
+              if (!counting_ && epoch_ == epoch) throw;
+              done_.wait(g, [&] { return failed_ || epoch_ != epoch; });
+              if (failed_) throw;
+              g.unlock();
+              sdbg::Pool::get().trim();
+            }
+          }
+          graphs_[i] = wrap_graph(go, k_);
+          {
+            std::lock_guard<std::mutex> g(mu_);
+            pending_ -= build_bytes(i);
+          }
+          done_.notify_all();
+        }
+      } catch (...) {
+        (void)hipStreamDestroy(st);
+        throw;
+      }
+      (void)hipStreamDestroy(st);
+      return SDBG_OK;
+    });
+    if (rc != SDBG_OK) {
+      std::lock_guard<std::mutex> g(mu_);
+      if (err_.empty()) {
+        err_ = t_err.empty() ? "graph build failed" : t_err;
+        err_rc_ = rc;
+      }
+      failed_ = true;
+      cv_.notify_all();
+      done_.notify_all();
+    }
+  }
+
+  // Working buffers and outputs of one build: per edge the row flags and
+  // marks, the '$' and dummy lists (at most one key each), their
+  // directories, and per row the label, multiplicity and bit-vector bytes.
+  uint64_t build_bytes(uint64_t s) const { return edges_[s]->n * (48ull * edges_[s]->w + 16) + (1ull << 20); }
+
+  sdbg_edges** edges_;
+  sdbg_graph** graphs_;
+  uint32_t k_;
+  uint64_t pending_ = 0, epoch_ = 0;
+  bool counting_ = false;
+  std::mutex mu_;
+  std::condition_variable cv_, done_;
+  std::deque<uint64_t> q_;
+  bool closed_ = false, failed_ = false;
+  std::string err_;
+  int err_rc_ = SDBG_OK;
+  std::vector<std::thread> th_;
+};
+
 int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* params, sdbg_edges** edges_out,
                    sdbg_graph** graphs_out) {
   std::vector<void*> made;
@@ -300,11 +456,33 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
     }
     const bool shared = !(params->mercy && params->d >= 2);
     sdbg::CountParams P{(int)k, params->d, params->mercy != 0, (int)params->prefix_len, params->mem_budget};
+    std::unique_ptr<BatchBuilders> builders;
+    if (graphs_out && n_sets) builders.reset(new BatchBuilders(edges_out, graphs_out, n_sets, k));
     uint64_t s0 = 0;
     while (s0 < n_sets) {
       // the budget is taken again for every pass: the outputs of the
       // earlier passes stay on the device
-      const uint64_t max_keys = std::min<uint64_t>(device_budget(params) / batch_bytes_per_key(w), 0xFFFFFFFFull);
+      uint64_t budget = device_budget(params);
+      if (builders && !params->mem_budget) {
+        // at most a third of the memory goes to builds still to come
+        if (builders->pending() > budget / 3) {
+          builders->wait_below(budget / 3);
+          budget = device_budget(params);
+        }
+        budget -= std::min(budget, builders->pending() + kBuildReserve);
+      }
+      const uint64_t max_keys = std::min<uint64_t>(budget / batch_bytes_per_key(w), 0xFFFFFFFFull);
+      if (std::getenv("SDBG_VERBOSE")) {
+        size_t fr = 0, tot = 0;
+        (void)hipMemGetInfo(&fr, &tot);
+        uint64_t iu = 0, pk = 0, ca = 0;
+        sdbg::Pool::get().stats(&iu, &pk, &ca, false);
+        std::fprintf(stderr, "[sdbg] batch pass from set %llu: budget %.2f GB, pending builds %.2f GB, free %.2f GB, "
+                             "pool in use %.2f GB cached %.2f GB\n",
+                     (unsigned long long)s0, budget / 1e9, builders ? builders->pending() / 1e9 : 0.0, fr / 1e9,
+                     iu / 1e9, ca / 1e9);
+      }
+      if (builders) builders->pass(true);
       if (!shared || occ[s0] > max_keys) {
         // one set alone on the single-set path (mercy, or larger than a pass)
         sdbg::EdgesOut eo;
@@ -328,6 +506,10 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
         }
         edges_out[s0] = wrap_edges(eo, k);
         made.push_back(edges_out[s0]);
+        if (builders) {
+          builders->pass(false);
+          builders->push(s0, s0 + 1);
+        }
         ++s0;
         continue;
       }
@@ -377,64 +559,25 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
         edges_out[s] = wrap_edges(outs[s - s0], k);
         made.push_back(edges_out[s]);
       }
+      if (builders) {
+        builders->pass(false);
+        builders->push(s0, s1);
+      }
       s0 = s1;
     }
-    if (graphs_out) {
-      // The sets' graphs are built by a few host threads, each on a stream
-      // of its own, so that one set's size read-backs overlap with the
-      // kernels of the others.
-      c.sync();
-      const unsigned nth = (unsigned)std::min<uint64_t>(kBuildThreads, n_sets);
-      int dev = 0;
-      SDBG_HIP(hipGetDevice(&dev));
-      std::atomic<uint64_t> next{0};
-      std::atomic<bool> failed{false};
-      std::vector<int> rcs(nth, SDBG_OK);
-      std::vector<std::string> errs(nth);
-      std::vector<std::thread> th;
-      for (unsigned t = 0; t < nth; ++t) {
-        th.emplace_back([&, t] {
-          rcs[t] = guarded([&]() -> int {
-            SDBG_HIP(hipSetDevice(dev));
-            hipStream_t st = nullptr;
-            SDBG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-            try {
-              sdbg::Ctx c2(st);
-              for (;;) {
-                const uint64_t i = next.fetch_add(1);
-                if (i >= n_sets || failed.load()) break;
-                sdbg::GraphOut go;
-                sdbg::build_graph(edges_out[i]->keys, edges_out[i]->count, edges_out[i]->n, (int)k, c2, &go, false);
-                c2.sync();
-                graphs_out[i] = wrap_graph(go, k);
-              }
-            } catch (...) {
-              (void)hipStreamDestroy(st);
-              throw;
-            }
-            (void)hipStreamDestroy(st);
-            return SDBG_OK;
-          });
-          if (rcs[t] != SDBG_OK) {
-            errs[t] = t_err;
-            failed.store(true);
-          }
-        });
-      }
-      for (auto& x : th) x.join();
-      for (uint64_t s = 0; s < n_sets; ++s)
-        if (graphs_out[s]) made.push_back(graphs_out[s]);
-      for (unsigned t = 0; t < nth; ++t)
-        if (rcs[t] != SDBG_OK) throw sdbg::Error(rcs[t], errs[t]);
-    }
+    if (builders) builders->finish_and_check();
     sdbg::prof_flush();
     return SDBG_OK;
   });
   if (rc != SDBG_OK) {
+    // (the builders are joined by now: the guarded lambda has returned)
     for (void* p : made) sdbg_free(p);
     for (uint64_t s = 0; edges_out && s < n_sets; ++s) {
       edges_out[s] = nullptr;
-      if (graphs_out) graphs_out[s] = nullptr;
+      if (graphs_out && graphs_out[s]) {
+        sdbg_free(graphs_out[s]);
+        graphs_out[s] = nullptr;
+      }
     }
   }
   return rc;

@@ -1727,6 +1727,22 @@ struct Counter {
               DBuf<uint32_t>& lcnt, uint64_t* nl_out, DBuf<uint64_t>* spos_keep = nullptr) {
     DBuf<uint64_t> nsolid = c.buf<uint64_t>(L.n), nlow = c.buf<uint64_t>(L.n);
     DBuf<uint64_t> spos = c.buf<uint64_t>(L.n + 1), lpos = c.buf<uint64_t>(L.n), tot = c.buf<uint64_t>(2);
+    if (verbose() && L.n) {
+      // leaf sizes: segments and keys up to 256, 512, 1024, 2048 keys, longer (runs of one key)
+      std::vector<uint64_t> len(L.n);
+      c.d2h(len.data(), L.len.get(), L.n);
+      uint64_t ns[5] = {}, nk[5] = {};
+      for (uint64_t x : len) {
+        const int b = x <= 256 ? 0 : x <= 512 ? 1 : x <= 1024 ? 2 : x <= 2048 ? 3 : 4;
+        ++ns[b];
+        nk[b] += x;
+      }
+      VLOG("leaves: %llu segments, %llu keys; by size <=256/512/1024/2048/longer: segments %llu %llu %llu %llu %llu, "
+           "keys %llu %llu %llu %llu %llu",
+           (unsigned long long)L.n, (unsigned long long)nkeys, (unsigned long long)ns[0], (unsigned long long)ns[1],
+           (unsigned long long)ns[2], (unsigned long long)ns[3], (unsigned long long)ns[4], (unsigned long long)nk[0],
+           (unsigned long long)nk[1], (unsigned long long)nk[2], (unsigned long long)nk[3], (unsigned long long)nk[4]);
+    }
     if (L.n) {
       Stage st_(c, "leaf", nkeys * 8 * W);
       if (tune.leaf_cap_shift == 0)

@@ -1,5 +1,7 @@
 #include "runtime.h"
 
+#include <unordered_set>
+
 #include "engine.h"
 
 #include <algorithm>
@@ -57,6 +59,11 @@ void* Pool::alloc(size_t bytes, hipStream_t s) {
     e = hipMalloc(&p, want);
     if (e != hipSuccess) {
       (void)hipGetLastError();
+      trim_all();
+      e = hipMalloc(&p, want);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
       trace_activity("");
       throw Error(-3, "device allocation of " + std::to_string(want) + " bytes failed: " + hipGetErrorString(e));
     }
@@ -74,15 +81,20 @@ void Pool::release(void* p, hipStream_t s, bool tagged) {
   std::lock_guard<std::mutex> lk(mu_);
   auto it = size_.find(p);
   if (it == size_.end()) return;
-  free_.emplace(it->second, Blk{p, s, tagged});
+  free_.emplace(it->second, Blk{p, s, tagged, ++releases_});
   cached_ += it->second;
   in_use_ -= it->second;
 }
 
-void Pool::untag(hipStream_t s) {
+void Pool::untag(hipStream_t s, uint64_t upto) {
   std::lock_guard<std::mutex> lk(mu_);
   for (auto& kv : free_)
-    if (kv.second.tagged && kv.second.s == s) kv.second.tagged = false;
+    if (kv.second.tagged && kv.second.s == s && kv.second.id <= upto) kv.second.tagged = false;
+}
+
+uint64_t Pool::release_mark() {
+  std::lock_guard<std::mutex> lk(mu_);
+  return releases_;
 }
 
 // Cached blocks no stream may still use are freed; hipFree can wait for the
@@ -104,6 +116,36 @@ void Pool::trim() {
   }
   if (give.empty()) return;
   trace_activity("releasing cached device memory");
+  for (void* p : give) (void)hipFree(p);
+  trace_activity("");
+}
+
+void Pool::trim_all() {
+  std::unordered_set<uint64_t> snap;  // release numbers of the blocks cached now
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto& kv : free_) snap.insert(kv.second.id);
+  }
+  if (snap.empty()) return;
+  trace_activity("device synchronisation to release cached memory");
+  // work queued before this point is all the work that can use the blocks
+  // released before it; a block handed out and released again since has a
+  // new release number and is kept
+  (void)hipDeviceSynchronize();
+  std::vector<void*> give;
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto it = free_.begin(); it != free_.end();) {
+      if (!snap.count(it->second.id)) {
+        ++it;
+        continue;
+      }
+      give.push_back(it->second.p);
+      size_.erase(it->second.p);
+      cached_ -= it->first;
+      it = free_.erase(it);
+    }
+  }
   for (void* p : give) (void)hipFree(p);
   trace_activity("");
 }

@@ -63,8 +63,17 @@ class Pool {
  public:
   void* alloc(size_t bytes, hipStream_t s);
   void release(void* p, hipStream_t s, bool tagged);
-  void untag(hipStream_t s);
+  // Makes the blocks released on s up to release number `upto` free for any
+  // stream (call after s has been synchronised; release_mark() taken before
+  // the synchronisation bounds what it covers).
+  void untag(hipStream_t s, uint64_t upto = ~0ull);
+  uint64_t release_mark();
   void trim();
+  // Gives back every cached block, tagged ones included: the blocks cached
+  // now are collected, the device is synchronised (so no stream still uses
+  // them), and those still cached are freed.  The last resort before an
+  // allocation fails.
+  void trim_all();
   size_t cached_bytes();
   // Bytes handed out and not released, and the most at any time since the
   // last reset (reset_peak sets it to the current use).
@@ -79,12 +88,13 @@ class Pool {
     void* p;
     hipStream_t s;
     bool tagged;
+    uint64_t id;  // release number (a block released again gets a new one)
   };
   std::mutex mu_;
   std::multimap<size_t, Blk> free_;
   std::unordered_map<void*, size_t> size_;
   size_t cached_ = 0;
-  uint64_t in_use_ = 0, peak_ = 0;
+  uint64_t in_use_ = 0, peak_ = 0, releases_ = 0;
   int64_t fail_after_ = -1;
 };
 
@@ -201,9 +211,12 @@ struct Ctx {
   DBuf<T> buf(size_t n) { return DBuf<T>(n, s); }
   void sync() {
     trace_activity("stream synchronisation");
+    Pool& pool = Pool::get();
+    const uint64_t mark = pool.release_mark();
     const hipError_t e = hipStreamSynchronize(s);
     trace_activity("");
     SDBG_HIP(e);
+    pool.untag(s, mark);  // what the stream released so far is idle now
   }
   template <typename T>
   T d2h_one(const T* dev) {
