@@ -332,6 +332,24 @@ typedef struct sdbg_index sdbg_index;
 int sdbg_index_build(const sdbg_graph *g, const sdbg_params *params, sdbg_index **out);
 int sdbg_navigate(const sdbg_index *index, int op, const uint64_t *rows, uint64_t n, uint64_t *out, void *stream);
 
+/* Tip removal (Section 2, fourth paragraph, lists it among the cleaning
+ * steps applied to each graph, without a definition; this is the reading
+ * implemented).  On the graph as built (validity is not read, so the
+ * result does not depend on earlier removals), a tip is
+ *   forward:  a path v0 -> ... -> vj of 1 <= j <= max_len edges from a node
+ *             with no incoming edge, through nodes of in- and out-degree 1
+ *             (v0: out-degree 1), to a node vj with in-degree >= 2 (it joins
+ *             the graph) or out-degree 0 (an isolated path);
+ *   backward: the mirror image, from a node with no outgoing edge back
+ *             through nodes of in- and out-degree 1 to a node with
+ *             out-degree >= 2 or in-degree 0.
+ * Every edge of every tip is removed at once by clearing its bit in
+ * g->valid (in place, on `stream`; the call returns when it is done).
+ * index must have been built on g (SDBG_E_INVAL otherwise).  *n_removed
+ * (may be NULL) = valid bits cleared by this call.  max_len = 0 removes
+ * nothing. */
+int sdbg_remove_tips(sdbg_graph *g, const sdbg_index *index, uint32_t max_len, uint64_t *n_removed, void *stream);
+
 /* Wraps host arrays (n*w key words ascending and unique, n counts) into a
  * library-owned device edge set, e.g. to build a graph from edges computed
  * elsewhere. */

@@ -161,6 +161,39 @@ __global__ void k_counts(const uint8_t* __restrict__ W, const uint64_t* __restri
   for (int s = 0; s < 8; ++s) p_cls[(uint64_t)s * (nb + 1) + b] = cnt[s];
 }
 
+// Node entered by the edge of row x (NONE for a '$' row): unflagged c-rows
+// before x; a flagged row enters the node of the nearest earlier unflagged one.
+DEV uint64_t nav_forward(const Nav& v, uint64_t x) {
+  const int c = v.W[x] & 7;
+  if (c == 0) return NONE;
+  uint64_t r = rank_cls(v, c - 1, x);
+  if ((v.W[x] >> 3) & 1) --r;
+  const Bits N = node_bits(v);
+  return N.select(N.rank(v.F[c]) + r);
+}
+
+// Outgoing edges of node u (its last row): the rows of the node, 0 for a
+// node whose only row is a '$' row.
+DEV uint64_t nav_outdeg(const Nav& v, uint64_t u) {
+  const Bits L = last_bits(v);
+  const uint64_t rk = L.rank(u);
+  const uint64_t start = rk ? L.select(rk - 1) + 1 : 0;
+  return (v.W[u] & 7) == 0 ? 0 : u - start + 1;
+}
+
+// Incoming edges of node u (dummy rows not counted): its unflagged entering
+// row and the flagged rows of the same label up to the next unflagged one.
+DEV uint64_t nav_indeg(const Nav& v, uint64_t u) {
+  if (bit(v.tip, u)) return 0;
+  const int c = block_of(v, u);
+  const uint64_t j = in_row(v, u, c);
+  if (bit(v.tip, j)) return 0;  // entered only by its dummy row
+  const uint64_t r = rank_cls(v, c - 1, j);
+  uint64_t j2 = select_cls(v, c - 1, r + 1);
+  if (j2 == NONE) j2 = v.m;
+  return 1 + rank_cls(v, 4 + c - 1, j2) - rank_cls(v, 4 + c - 1, j);
+}
+
 constexpr int OP_NODE = 1, OP_FORWARD = 2, OP_BACKWARD = 3, OP_OUTDEG = 4, OP_INDEG = 5, OP_LABEL = 6;
 
 __global__ void k_nav(Nav v, int op, const uint64_t* __restrict__ q, uint64_t n, uint64_t* __restrict__ out) {
@@ -178,42 +211,16 @@ __global__ void k_nav(Nav v, int op, const uint64_t* __restrict__ q, uint64_t n,
   if (op == OP_NODE) {
     out[t] = node_of(v, x);
   } else if (op == OP_FORWARD) {
-    const int c = v.W[x] & 7;
-    if (c == 0) {
-      out[t] = NONE;
-      return;
-    }
-    // unflagged c-rows before x; a flagged row enters the node of the
-    // nearest earlier unflagged one
-    uint64_t r = rank_cls(v, c - 1, x);
-    if ((v.W[x] >> 3) & 1) --r;
-    const Bits N = node_bits(v);
-    out[t] = N.select(N.rank(v.F[c]) + r);
+    out[t] = nav_forward(v, x);
   } else if (op == OP_OUTDEG) {
-    const uint64_t u = node_of(v, x);
-    const Bits L = last_bits(v);
-    const uint64_t rk = L.rank(u);
-    const uint64_t start = rk ? L.select(rk - 1) + 1 : 0;
-    out[t] = (v.W[u] & 7) == 0 ? 0 : u - start + 1;
+    out[t] = nav_outdeg(v, node_of(v, x));
   } else {
     const uint64_t u = node_of(v, x);
     const int c = block_of(v, u);
     if (op == OP_BACKWARD) {
       out[t] = bit(v.tip, u) ? NONE : node_of(v, in_row(v, u, c));
     } else if (op == OP_INDEG) {
-      if (bit(v.tip, u)) {
-        out[t] = 0;
-        return;
-      }
-      const uint64_t j = in_row(v, u, c);
-      if (bit(v.tip, j)) {
-        out[t] = 0;  // entered only by its dummy row: no incoming edge
-        return;
-      }
-      const uint64_t r = rank_cls(v, c - 1, j);
-      uint64_t j2 = select_cls(v, c - 1, r + 1);
-      if (j2 == NONE) j2 = v.m;
-      out[t] = 1 + rank_cls(v, 4 + c - 1, j2) - rank_cls(v, 4 + c - 1, j);
+      out[t] = nav_indeg(v, u);
     } else {  // OP_LABEL: walk back, one base per step, until k bases or a dummy row
       uint64_t w[4] = {0, 0, 0, 0};
       auto put = [&](int pos, uint64_t b) { w[(2 * pos) >> 6] |= b << ((2 * pos) & 63); };
@@ -240,6 +247,65 @@ __global__ void k_nav(Nav v, int op, const uint64_t* __restrict__ q, uint64_t n,
       for (int j = 0; j < lw; ++j) out[t * lw + j] = w[j];
     }
   }
+}
+
+// Tip removal (Section 2, fourth paragraph, names it among the cleaning
+// steps and gives no definition; the reading used here): on the graph as
+// built, a forward tip is a path v0 -> ... -> vj (1 <= j <= max_len edges)
+// from a node with no incoming edge through nodes of in- and out-degree 1
+// (v0: out-degree 1) to a node vj with in-degree >= 2 or out-degree 0; a
+// backward tip is its mirror image, from a node with no outgoing edge back
+// to a node with out-degree >= 2 or in-degree 0.  One thread per row: a
+// dummy row starts a forward walk at the node it enters, a '$' row a
+// backward walk at its node.  The walk is taken once to decide and, for a
+// tip, again to clear the valid bits of its edges; validity is not read,
+// so every tip is found on the graph as built and all are removed at once.
+// n_removed counts the valid bits cleared.
+__global__ void k_remove_tips(Nav v, uint64_t* __restrict__ valid, uint32_t max_len,
+                              unsigned long long* __restrict__ n_removed) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= v.m) return;
+  const bool fwd = bit(v.tip, i), bwd = (v.W[i] & 7) == 0;
+  if (!fwd && !bwd) return;
+  uint32_t len = 0;
+  bool tip = false;
+  if (fwd) {
+    // a node of out-degree 1 has one row, its last row, which is its edge
+    uint64_t cur = nav_forward(v, i);
+    while (len < max_len && nav_outdeg(v, cur) == 1) {
+      cur = nav_forward(v, cur);
+      ++len;
+      const uint64_t in = nav_indeg(v, cur);
+      if (in >= 2 || nav_outdeg(v, cur) == 0) {
+        tip = true;
+        break;
+      }
+      if (in != 1) break;
+    }
+  } else {
+    uint64_t cur = i;  // a node of out-degree 0 has one row, its '$' row
+    while (len < max_len && nav_indeg(v, cur) == 1) {
+      cur = node_of(v, in_row(v, cur, block_of(v, cur)));
+      ++len;
+      const uint64_t out = nav_outdeg(v, cur);
+      if (out >= 2 || nav_indeg(v, cur) == 0) {
+        tip = true;
+        break;
+      }
+      if (out != 1) break;
+    }
+  }
+  if (!tip) return;
+  unsigned long long cleared = 0;
+  uint64_t cur = fwd ? nav_forward(v, i) : i;
+  for (uint32_t s = 0; s < len; ++s) {
+    const uint64_t row = fwd ? cur : in_row(v, cur, block_of(v, cur));
+    const unsigned long long bitm = 1ull << (row & 63);
+    const unsigned long long old = atomicAnd(reinterpret_cast<unsigned long long*>(valid + (row >> 6)), ~bitm);
+    cleared += (old & bitm) ? 1 : 0;
+    cur = fwd ? nav_forward(v, cur) : node_of(v, row);
+  }
+  if (cleared) atomicAdd(n_removed, cleared);
 }
 
 }  // namespace
@@ -325,6 +391,30 @@ int sdbg_navigate(const sdbg_index* index, int op, const uint64_t* rows, uint64_
       c.check_launch("navigate");
     }
     c.sync();
+    return SDBG_OK;
+  });
+}
+
+int sdbg_remove_tips(sdbg_graph* g, const sdbg_index* index, uint32_t max_len, uint64_t* n_removed, void* stream) {
+  using namespace sdbg;
+  return sdbg_abi::guarded([&]() -> int {
+    SDBG_CHECK(g && index, SDBG_E_INVAL, "null argument");
+    SDBG_CHECK(sdbg_abi::reg_kind(g) == sdbg_abi::kGraph, SDBG_E_INVAL, "not a graph returned by this library");
+    SDBG_CHECK(sdbg_abi::reg_kind(index) == sdbg_abi::kIndex, SDBG_E_INVAL, "not an index returned by this library");
+    const NavIndex* ix = reinterpret_cast<const NavIndex*>(index);
+    SDBG_CHECK(ix->v.W == g->W && ix->v.m == g->m, SDBG_E_INVAL, "the index was not built on this graph");
+    Ctx c(stream);
+    DBuf<unsigned long long> cnt = c.buf<unsigned long long>(1);
+    fill<uint64_t>(reinterpret_cast<uint64_t*>(cnt.get()), 1, 0, c);
+    if (g->m && max_len) {
+      SDBG_CHECK(ceil_div(g->m, SDBG_BLOCK) < (1ull << 31), SDBG_E_INVAL, "graph too large");
+      k_remove_tips<<<(unsigned)ceil_div(g->m, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(ix->v, g->valid, max_len,
+                                                                                  cnt.get());
+      c.check_launch("remove_tips");
+    }
+    unsigned long long h = 0;
+    c.d2h(&h, cnt.get(), 1);
+    if (n_removed) *n_removed = h;
     return SDBG_OK;
   });
 }

@@ -350,6 +350,19 @@ class Index:
         assert rows.is_cuda and out.is_cuda and rows.is_contiguous() and out.is_contiguous()
         _check(load().sdbg_navigate(self._h, op, rows.data_ptr(), rows.numel(), out.data_ptr(), _stream_ptr(stream)))
 
+    def remove_tips(self, max_len: int, stream=None) -> int:
+        """Clears the valid bits of the tips of the indexed graph (paths of
+        at most max_len edges, sdbg_remove_tips); returns how many."""
+        lib = load()
+        if not getattr(lib, "_tips_api", False):
+            lib.sdbg_remove_tips.argtypes = [ctypes.POINTER(_Graph), ctypes.c_void_p, ctypes.c_uint32,
+                                             ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]
+            lib.sdbg_remove_tips.restype = ctypes.c_int
+            lib._tips_api = True
+        n = ctypes.c_uint64()
+        _check(lib.sdbg_remove_tips(self._graph._p, self._h, max_len, ctypes.byref(n), _stream_ptr(stream)))
+        return n.value
+
     def close(self):
         if self._h:
             load().sdbg_free(self._h)
