@@ -39,6 +39,7 @@ void* Pool::alloc(size_t bytes, hipStream_t s) {
       cached_ -= it->first;
       in_use_ += it->first;
       peak_ = std::max(peak_, in_use_);
+      if (it->second.tagged) tagged_at_.erase(p);
       free_.erase(it);
       return p;
     }
@@ -81,15 +82,29 @@ void Pool::release(void* p, hipStream_t s, bool tagged) {
   std::lock_guard<std::mutex> lk(mu_);
   auto it = size_.find(p);
   if (it == size_.end()) return;
-  free_.emplace(it->second, Blk{p, s, tagged, ++releases_});
+  auto at = free_.emplace(it->second, Blk{p, s, tagged, ++releases_});
+  if (tagged) {
+    tags_[s].push_back(Tag{releases_, p});
+    tagged_at_[p] = at;
+  }
   cached_ += it->second;
   in_use_ -= it->second;
 }
 
 void Pool::untag(hipStream_t s, uint64_t upto) {
   std::lock_guard<std::mutex> lk(mu_);
-  for (auto& kv : free_)
-    if (kv.second.tagged && kv.second.s == s && kv.second.id <= upto) kv.second.tagged = false;
+  auto t = tags_.find(s);
+  if (t == tags_.end()) return;
+  std::vector<Tag>& L = t->second;
+  size_t n = 0;  // release numbers grow along the list: untag a prefix
+  for (; n < L.size() && L[n].id <= upto; ++n) {
+    auto a = tagged_at_.find(L[n].p);
+    if (a == tagged_at_.end() || a->second->second.id != L[n].id) continue;
+    a->second->second.tagged = false;
+    tagged_at_.erase(a);
+  }
+  L.erase(L.begin(), L.begin() + n);
+  if (L.empty()) tags_.erase(t);
 }
 
 uint64_t Pool::release_mark() {
@@ -142,6 +157,7 @@ void Pool::trim_all() {
       }
       give.push_back(it->second.p);
       size_.erase(it->second.p);
+      tagged_at_.erase(it->second.p);
       cached_ -= it->first;
       it = free_.erase(it);
     }

@@ -90,8 +90,17 @@ class Pool {
     bool tagged;
     uint64_t id;  // release number (a block released again gets a new one)
   };
+  struct Tag {
+    uint64_t id;
+    void* p;
+  };
   std::mutex mu_;
   std::multimap<size_t, Blk> free_;
+  // per stream, the blocks released tagged, in release order, and where
+  // each tagged block sits in free_ (untag() walks only these; entries of
+  // blocks handed out or given back since are skipped)
+  std::unordered_map<hipStream_t, std::vector<Tag>> tags_;
+  std::unordered_map<void*, std::multimap<size_t, Blk>::iterator> tagged_at_;
   std::unordered_map<void*, size_t> size_;
   size_t cached_ = 0;
   uint64_t in_use_ = 0, peak_ = 0, releases_ = 0;
