@@ -132,9 +132,6 @@ uint64_t batch_bytes_per_key(uint32_t w) { return 32ull * w + 16; }
 
 // Host threads (and streams) building the graphs of a batch.
 constexpr unsigned kBuildThreads = 4;
-// Device memory a counting pass of a batch leaves to the graph builds that
-// run next to it, beyond their estimated needs.
-constexpr uint64_t kBuildReserve = 8ull << 30;
 
 uint64_t device_budget(const sdbg_params* p) {
   if (p->mem_budget) return p->mem_budget;
@@ -287,11 +284,11 @@ int sdbg_build(const sdbg_edges* edges, const sdbg_params* params, sdbg_graph** 
 }
 
 // Graph builders of a batch: a few host threads, each on a stream of its
-// own, take the sets whose edge sets are ready (pushed after each counting
-// pass) and build their graphs while the next pass counts, so that the
-// builds -- and one set's size read-backs -- overlap the counting and the
-// other builds.  The destructor stops and joins the threads (also when the
-// counting throws); errors are collected for rethrow().
+// own, build the sets' graphs once every pass has counted, so that one
+// set's size read-backs overlap the other sets' kernels.  (Building next to
+// the counting passes was measured slower: the two compete for the device.)
+// The destructor stops and joins the threads (also when the caller throws);
+// errors are collected for finish_and_check().
 class BatchBuilders {
  public:
   BatchBuilders(sdbg_edges** edges, sdbg_graph** graphs, uint64_t n_sets, uint32_t k) : edges_(edges), graphs_(graphs),
@@ -305,33 +302,9 @@ class BatchBuilders {
   void push(uint64_t s0, uint64_t s1) {
     {
       std::lock_guard<std::mutex> g(mu_);
-      for (uint64_t s = s0; s < s1; ++s) {
-        q_.push_back(s);
-        pending_ += build_bytes(s);
-      }
+      for (uint64_t s = s0; s < s1; ++s) q_.push_back(s);
     }
     cv_.notify_all();
-  }
-  // Device memory the queued and running builds may still take (an upper
-  // estimate); the counting passes leave it out of their budget.
-  uint64_t pending() {
-    std::lock_guard<std::mutex> g(mu_);
-    return pending_;
-  }
-  // A counting pass starts / has ended (builds that run out of device
-  // memory during a pass wait for its end and try again).
-  void pass(bool running) {
-    {
-      std::lock_guard<std::mutex> g(mu_);
-      counting_ = running;
-      if (!running) ++epoch_;
-    }
-    done_.notify_all();
-  }
-  // Waits until the pending estimate is at most `limit` (or a build failed).
-  void wait_below(uint64_t limit) {
-    std::unique_lock<std::mutex> g(mu_);
-    done_.wait(g, [&] { return pending_ <= limit || failed_; });
   }
   // All sets pushed: wait for the builds, rethrow the first error.
   void finish_and_check() {
@@ -347,7 +320,6 @@ class BatchBuilders {
       if (stop) failed_ = true;
     }
     cv_.notify_all();
-    done_.notify_all();
     for (auto& t : th_)
       if (t.joinable()) t.join();
   }
@@ -368,35 +340,9 @@ class BatchBuilders {
             q_.pop_front();
           }
           sdbg::GraphOut go;
-          for (;;) {
-            uint64_t epoch;
-            {
-              std::lock_guard<std::mutex> g(mu_);
-              epoch = epoch_;
-            }
-            try {
-              sdbg::build_graph(edges_[i]->keys, edges_[i]->count, edges_[i]->n, (int)k_, c2, &go, false);
-              c2.sync();
-              break;
-            } catch (const sdbg::Error& e) {
-              // out of device memory while a counting pass runs: wait for
-              // the pass to end, give back cached memory, and try again
-              if (e.code != -3) throw;
-              c2.sync();
-              std::unique_lock<std::mutex> g(mu_);
-              if (!counting_ && epoch_ == epoch) throw;
-              done_.wait(g, [&] { return failed_ || epoch_ != epoch; });
-              if (failed_) throw;
-              g.unlock();
-              sdbg::Pool::get().trim();
-            }
-          }
+          sdbg::build_graph(edges_[i]->keys, edges_[i]->count, edges_[i]->n, (int)k_, c2, &go, false);
+          c2.sync();
           graphs_[i] = wrap_graph(go, k_);
-          {
-            std::lock_guard<std::mutex> g(mu_);
-            pending_ -= build_bytes(i);
-          }
-          done_.notify_all();
         }
       } catch (...) {
         (void)hipStreamDestroy(st);
@@ -413,22 +359,14 @@ class BatchBuilders {
       }
       failed_ = true;
       cv_.notify_all();
-      done_.notify_all();
     }
   }
-
-  // Working buffers and outputs of one build: per edge the row flags and
-  // marks, the '$' and dummy lists (at most one key each), their
-  // directories, and per row the label, multiplicity and bit-vector bytes.
-  uint64_t build_bytes(uint64_t s) const { return edges_[s]->n * (48ull * edges_[s]->w + 16) + (1ull << 20); }
 
   sdbg_edges** edges_;
   sdbg_graph** graphs_;
   uint32_t k_;
-  uint64_t pending_ = 0, epoch_ = 0;
-  bool counting_ = false;
   std::mutex mu_;
-  std::condition_variable cv_, done_;
+  std::condition_variable cv_;
   std::deque<uint64_t> q_;
   bool closed_ = false, failed_ = false;
   std::string err_;
@@ -456,33 +394,21 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
     }
     const bool shared = !(params->mercy && params->d >= 2);
     sdbg::CountParams P{(int)k, params->d, params->mercy != 0, (int)params->prefix_len, params->mem_budget};
-    std::unique_ptr<BatchBuilders> builders;
-    if (graphs_out && n_sets) builders.reset(new BatchBuilders(edges_out, graphs_out, n_sets, k));
     uint64_t s0 = 0;
     while (s0 < n_sets) {
       // the budget is taken again for every pass: the outputs of the
       // earlier passes stay on the device
-      uint64_t budget = device_budget(params);
-      if (builders && !params->mem_budget) {
-        // at most a third of the memory goes to builds still to come
-        if (builders->pending() > budget / 3) {
-          builders->wait_below(budget / 3);
-          budget = device_budget(params);
-        }
-        budget -= std::min(budget, builders->pending() + kBuildReserve);
-      }
+      const uint64_t budget = device_budget(params);
       const uint64_t max_keys = std::min<uint64_t>(budget / batch_bytes_per_key(w), 0xFFFFFFFFull);
       if (std::getenv("SDBG_VERBOSE")) {
         size_t fr = 0, tot = 0;
         (void)hipMemGetInfo(&fr, &tot);
         uint64_t iu = 0, pk = 0, ca = 0;
         sdbg::Pool::get().stats(&iu, &pk, &ca, false);
-        std::fprintf(stderr, "[sdbg] batch pass from set %llu: budget %.2f GB, pending builds %.2f GB, free %.2f GB, "
-                             "pool in use %.2f GB cached %.2f GB\n",
-                     (unsigned long long)s0, budget / 1e9, builders ? builders->pending() / 1e9 : 0.0, fr / 1e9,
-                     iu / 1e9, ca / 1e9);
+        std::fprintf(stderr, "[sdbg] batch pass from set %llu: budget %.2f GB, free %.2f GB, pool in use %.2f GB "
+                             "cached %.2f GB\n",
+                     (unsigned long long)s0, budget / 1e9, fr / 1e9, iu / 1e9, ca / 1e9);
       }
-      if (builders) builders->pass(true);
       if (!shared || occ[s0] > max_keys) {
         // one set alone on the single-set path (mercy, or larger than a pass)
         sdbg::EdgesOut eo;
@@ -506,10 +432,6 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
         }
         edges_out[s0] = wrap_edges(eo, k);
         made.push_back(edges_out[s0]);
-        if (builders) {
-          builders->pass(false);
-          builders->push(s0, s0 + 1);
-        }
         ++s0;
         continue;
       }
@@ -559,13 +481,14 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
         edges_out[s] = wrap_edges(outs[s - s0], k);
         made.push_back(edges_out[s]);
       }
-      if (builders) {
-        builders->pass(false);
-        builders->push(s0, s1);
-      }
       s0 = s1;
     }
-    if (builders) builders->finish_and_check();
+    if (graphs_out && n_sets) {
+      c.sync();
+      BatchBuilders builders(edges_out, graphs_out, n_sets, k);
+      builders.push(0, n_sets);
+      builders.finish_and_check();
+    }
     sdbg::prof_flush();
     return SDBG_OK;
   });
