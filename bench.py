@@ -169,6 +169,40 @@ def large_k_rates(steps: int):
     return rows
 
 
+def navigation_rates(sdbg, torch, seq, off, rs, stream):
+    """Navigation index build, tip removal (paths of at most 2k edges) and
+    random forward queries on one graph of the workload, outside the timed
+    steps (HIP events on the call stream)."""
+    e = sdbg.count_solid(seq, off, rs.k, rs.d, rs.mercy, stream=stream)
+    g = sdbg.build(e, stream=stream)
+    e.close()
+    torch.cuda.synchronize()
+    ea, eb, ec = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    ea.record(stream)
+    ix = sdbg.Index(g, stream=stream)
+    eb.record(stream)
+    removed = ix.remove_tips(2 * rs.k, stream=stream)
+    ec.record(stream)
+    torch.cuda.synchronize()
+    rows = torch.randint(0, int(g.raw.m), (1 << 24,), device="cuda:0", dtype=torch.int64)
+    outq = torch.empty_like(rows)
+    ed, ee = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ix.navigate(sdbg.NAV_FORWARD, rows, outq, stream=stream)
+    ed.record(stream)
+    ix.navigate(sdbg.NAV_FORWARD, rows, outq, stream=stream)
+    ee.record(stream)
+    torch.cuda.synchronize()
+    clean = {"index_ms": round(ea.elapsed_time(eb), 3), "remove_tips_ms": round(eb.elapsed_time(ec), 3),
+             "tip_max_len": 2 * rs.k, "tip_edges_removed": int(removed),
+             "forward_queries_per_s": round((1 << 24) / (ed.elapsed_time(ee) * 1e-3), 1)}
+    log(f"index {clean['index_ms']} ms, tip removal {clean['remove_tips_ms']} ms ({removed} edges), "
+        f"{clean['forward_queries_per_s'] / 1e9:.2f} G forward queries/s")
+    ix.close()
+    g.close()
+    del rows, outq
+    return clean
+
+
 def bench_batch(args):
     """Batched form against one plain call per set, on the same device-resident
     sets; both build the SdBG of every set."""
@@ -382,6 +416,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-large-k", action="store_true", help="skip the large-k figures (k = 21..99)")
     ap.add_argument("--large-k-steps", type=int, default=2)
+    ap.add_argument("--no-nav", action="store_true", help="skip the navigation index and tip removal figures")
     ap.add_argument("--stages", action="store_true", help="print per-kernel breakdown to stderr")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (a reference kernel for hardware byte counters)")
@@ -535,35 +570,9 @@ def main():
                      "floor_bytes_per_occ": round(floor_b, 2),
                      "floor_frac": round(value * floor_b / HBM_PEAK_GBS, 4)}
 
-    # navigation index and tip removal on this step's graph (outside the
-    # timed steps; HIP events on the call stream)
-    e = sdbg.count_solid(seq, off, rs.k, rs.d, rs.mercy, stream=stream)
-    g = sdbg.build(e, stream=stream)
-    e.close()
-    torch.cuda.synchronize()
-    ea, eb, ec = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    ea.record(stream)
-    ix = sdbg.Index(g, stream=stream)
-    eb.record(stream)
-    removed = ix.remove_tips(2 * rs.k, stream=stream)
-    ec.record(stream)
-    torch.cuda.synchronize()
-    rows = torch.randint(0, int(g.raw.m), (1 << 24,), device="cuda:0", dtype=torch.int64)
-    outq = torch.empty_like(rows)
-    ed, ee = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ix.navigate(sdbg.NAV_FORWARD, rows, outq, stream=stream)
-    ed.record(stream)
-    ix.navigate(sdbg.NAV_FORWARD, rows, outq, stream=stream)
-    ee.record(stream)
-    torch.cuda.synchronize()
-    clean = {"index_ms": round(ea.elapsed_time(eb), 3), "remove_tips_ms": round(eb.elapsed_time(ec), 3),
-             "tip_max_len": 2 * rs.k, "tip_edges_removed": int(removed),
-             "forward_queries_per_s": round((1 << 24) / (ed.elapsed_time(ee) * 1e-3), 1)}
-    log(f"index {clean['index_ms']} ms, tip removal {clean['remove_tips_ms']} ms ({removed} edges), "
-        f"{clean['forward_queries_per_s'] / 1e9:.2f} G forward queries/s")
-    ix.close()
-    g.close()
-    del rows, outq
+    clean = None
+    if not args.no_nav:
+        clean = navigation_rates(sdbg, torch, seq, off, rs, stream)
 
     large = None
     if not args.no_large_k and args.workload == "metagenome" and args.scale == 1.0:
@@ -601,7 +610,8 @@ def main():
         out["host_input_gmer_s"] = round(host_rate, 3)
     if large is not None:
         out["large_k"] = large
-    out["navigation"] = clean
+    if clean is not None:
+        out["navigation"] = clean
     print(json.dumps(out), flush=True)
 
 

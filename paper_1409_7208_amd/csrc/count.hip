@@ -573,8 +573,8 @@ struct LeafShape {
 template <int W, int CAP>
 __global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* const* __restrict__ bufs,
                                                      uint32_t* __restrict__ cnt, uint32_t dmin, int want_low,
-                                                     int distinct, uint64_t* __restrict__ nsolid,
-                                                     uint64_t* __restrict__ nlow) {
+                                                     int distinct, const uint32_t* __restrict__ ids,
+                                                     uint64_t* __restrict__ nsolid, uint64_t* __restrict__ nlow) {
   constexpr int PER = LeafShape<CAP>::PER, H = LeafShape<CAP>::H, MAXB = LeafShape<CAP>::MAXB;
   constexpr uint32_t EMPTY = 0xFFFFFFFFu;
   static_assert(CAP <= 4096 && H <= 65536, "leaf sizes");
@@ -622,8 +622,9 @@ __global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* con
         const uint32_t c = (uint32_t)len;
         const bool solid = len >= dmin;
         if (solid || want_low) cn[0] = c;
-        nsolid[s] = solid;
-        nlow[s] = !solid && want_low;
+        const uint64_t id = ids ? ids[s] : s;
+        nsolid[id] = solid;
+        nlow[id] = !solid && want_low;
       }
       continue;
     }
@@ -766,8 +767,9 @@ __global__ __launch_bounds__(SDBG_BLOCK, 4) void k_leaf(SegView v, uint64_t* con
       }
     }
     if (threadIdx.x == 0) {
-      nsolid[s] = NS;
-      nlow[s] = NL;
+      const uint64_t id = ids ? ids[s] : s;
+      nsolid[id] = NS;
+      nlow[id] = NL;
     }
   }
 }
@@ -1523,6 +1525,32 @@ struct SegList {
   SegView view() const { return SegView{off.get(), len.get(), bit.get(), buf.get(), D.get(), n}; }
 };
 
+// Leaf launches with at least this many segments are split by segment size.
+constexpr uint64_t kLeafSplitMin = 16384;
+
+// Segment list split by size: flags (1 = at most cap keys), then the
+// entries copied to the small or the large list with their positions in
+// the original one (pos = exclusive scan of the flags).
+__global__ void k_seg_small(SegView v, uint64_t cap, uint64_t* __restrict__ f) {
+  const uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (s < v.n) f[s] = v.len[s] <= cap;
+}
+
+__global__ void k_seg_split(SegView v, uint64_t cap, const uint64_t* __restrict__ pos, SegView a, uint32_t* __restrict__ ida,
+                            SegView b, uint32_t* __restrict__ idb) {
+  const uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (s >= v.n) return;
+  const bool small = v.len[s] <= cap;
+  const uint64_t p = small ? pos[s] : s - pos[s];
+  const SegView& o = small ? a : b;
+  o.off[p] = v.off[s];
+  o.len[p] = v.len[s];
+  o.bit[p] = v.bit[s];
+  o.buf[p] = v.buf[s];
+  o.D[p] = v.D[s];
+  (small ? ida : idb)[p] = (uint32_t)s;
+}
+
 // Initial segments from the first cut: digit d covers [start_d, start_d+len_d).
 __global__ void k_seg_init(const uint32_t* __restrict__ tabscan, uint64_t ntiles, uint32_t nbins, uint64_t total,
                            int bit, SegView v) {
@@ -1623,8 +1651,8 @@ struct Counter {
   // Persistent leaf launch: as many workgroups as can be resident (at most
   // leaf_wg_per_cu per compute unit), so that none waits for another.
   template <int CAPX>
-  void launch_leaf(SegList& L, uint64_t* const* d_bufs, uint32_t* cnt, uint32_t dmin, bool want_low, uint64_t* ns,
-                   uint64_t* nl) {
+  void launch_leaf(const SegList& L, uint64_t* const* d_bufs, uint32_t* cnt, uint32_t dmin, bool want_low,
+                   uint64_t* ns, uint64_t* nl, const uint32_t* ids = nullptr) {
     static int resident = 0;
     if (!resident) {
       int r = 0;
@@ -1635,7 +1663,7 @@ struct Counter {
     const int per_cu = std::max(1, std::min(resident, tune.leaf_wg_per_cu));
     const unsigned lgrid = (unsigned)std::min<uint64_t>(L.n, (uint64_t)cu_count() * per_cu);
     k_leaf<W, CAPX><<<lgrid, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, cnt, dmin, want_low ? 1 : 0,
-                                                   distinct_keys ? 1 : 0, ns, nl);
+                                                   distinct_keys ? 1 : 0, ids, ns, nl);
     c.check_launch("leaf");
   }
 
@@ -1745,10 +1773,27 @@ struct Counter {
     }
     if (L.n) {
       Stage st_(c, "leaf", nkeys * 8 * W);
-      if (tune.leaf_cap_shift == 0)
+      if (tune.leaf_cap_shift == 0 && L.n >= kLeafSplitMin) {
+        // segments of at most CAP/2 keys go to the half-size leaf, which
+        // keeps more workgroups on a CU; the others to the full-size one
+        DBuf<uint64_t> pos = c.buf<uint64_t>(L.n + 1);
+        k_seg_small<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), (uint64_t)CAP / 2, pos.get());
+        scan_excl<uint64_t, uint64_t>(pos.get(), pos.get(), L.n, pos.get() + L.n, c);
+        const uint64_t ns_small = c.d2h_one(pos.get() + L.n);
+        SegList A, B;
+        A.alloc(c, ns_small);
+        B.alloc(c, L.n - ns_small);
+        DBuf<uint32_t> ida = c.buf<uint32_t>(A.n), idb = c.buf<uint32_t>(B.n);
+        k_seg_split<<<grid1(L.n), SDBG_BLOCK, 0, c.s>>>(L.view(), (uint64_t)CAP / 2, pos.get(), A.view(), ida.get(),
+                                                        B.view(), idb.get());
+        c.check_launch("seg_split");
+        if (A.n) launch_leaf<CAP / 2>(A, d_bufs, cnt, dmin, want_low, nsolid.get(), nlow.get(), ida.get());
+        if (B.n) launch_leaf<CAP>(B, d_bufs, cnt, dmin, want_low, nsolid.get(), nlow.get(), idb.get());
+      } else if (tune.leaf_cap_shift == 0) {
         launch_leaf<CAP>(L, d_bufs, cnt, dmin, want_low, nsolid.get(), nlow.get());
-      else
+      } else {
         launch_leaf<CAP / 2>(L, d_bufs, cnt, dmin, want_low, nsolid.get(), nlow.get());
+      }
     }
     scan_excl<uint64_t, uint64_t>(nsolid.get(), spos.get(), L.n, spos.get() + L.n, c);
     scan_excl<uint64_t, uint64_t>(nlow.get(), lpos.get(), L.n, tot.get() + 1, c);
