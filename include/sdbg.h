@@ -305,7 +305,7 @@ int sdbg_server_stop(sdbg_server *srv);
 /* Navigation of a graph on the device (Section 2, first paragraph: the
  * succinct representation is traversed through rank and select over W,
  * last and F).  sdbg_index_build makes rank directories over the graph's
- * arrays (about 1.4 bits per row; the index borrows the graph, which must
+ * arrays (about 2 bits per row; the index borrows the graph, which must
  * outlive it; release with sdbg_free).  A node is identified by the index
  * of its last row.  sdbg_navigate answers n queries rows[i] (device array)
  * into out (device array; n words, or n * ceil(2k/64) words for

@@ -13,9 +13,12 @@
 //
 // Index: per 64 rows, cumulative counts of last bits, of last bits of
 // non-dummy nodes, of tip bits, and of each of the 8 row classes (label
-// 1..4, minus 0/1).  rank is one cumulative count plus a popcount over at
-// most 64 rows; select is a binary search over the cumulative counts
-// followed by a scan of one 64-row block.
+// 1..4, minus 0/1), and select directories (the block of every 256th one)
+// for the non-dummy node ends and the four unflagged classes.  rank is one
+// cumulative count plus a popcount over at most 64 rows; select is a
+// binary search over the cumulative counts between two directory samples,
+// then a scan of one 64-row block; a row's node end and the previous node
+// end are found by scanning the last bits word by word.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -29,6 +32,10 @@ namespace {
 
 constexpr uint64_t NONE = ~0ull;
 
+// Select directories: the 64-row block that holds every SEL_S-th one, so a
+// select searches the cumulative counts between two samples only.
+constexpr uint64_t SEL_S = 256;
+
 struct Nav {
   uint64_t m, nb;  // rows, 64-row blocks
   int k;
@@ -37,6 +44,9 @@ struct Nav {
   const uint64_t *last, *tip, *tip_seq;
   const uint64_t *c_last, *c_nt, *c_tip;  // nb + 1 cumulative counts each
   const uint64_t* c_cls;                  // class-major: c_cls[s * (nb + 1) + b]
+  const uint32_t* sel_nt;                 // select directory of non-dummy node ends
+  const uint32_t* sel_cls;                // of the unflagged classes 0..3, sel_stride entries each
+  uint64_t sel_stride;
 };
 
 // Row class of a W byte: label c in 1..4 and minus f -> f * 4 + c - 1; -1 for '$'.
@@ -57,6 +67,7 @@ DEV int count_bytes_eq(uint64_t x, uint8_t v) {
 struct Bits {
   const uint64_t *b, *nb, *cum;
   uint64_t nw;
+  const uint32_t* sel;  // select directory, or null
   DEV uint64_t word(uint64_t w) const { return nb ? (b[w] & ~nb[w]) : b[w]; }
   DEV uint64_t rank(uint64_t i) const {  // ones in [0, i)
     const uint64_t w = i >> 6, r = i & 63;
@@ -64,6 +75,11 @@ struct Bits {
   }
   DEV uint64_t select(uint64_t r) const {  // position of the one of 0-based rank r (r < total)
     uint64_t lo = 0, hi = nw;  // last word w with cum[w] <= r
+    if (sel) {
+      const uint64_t j = r / SEL_S;
+      lo = sel[j];
+      if ((j + 1) * SEL_S < cum[nw]) hi = (uint64_t)sel[j + 1] + 1;
+    }
     while (hi - lo > 1) {
       const uint64_t mid = (lo + hi) >> 1;
       if (cum[mid] <= r)
@@ -77,9 +93,28 @@ struct Bits {
   }
 };
 
-DEV Bits last_bits(const Nav& v) { return Bits{v.last, nullptr, v.c_last, v.nb}; }
-DEV Bits node_bits(const Nav& v) { return Bits{v.last, v.tip, v.c_nt, v.nb}; }  // ends of non-dummy nodes
-DEV Bits tip_bits(const Nav& v) { return Bits{v.tip, nullptr, v.c_tip, v.nb}; }
+DEV Bits node_bits(const Nav& v) { return Bits{v.last, v.tip, v.c_nt, v.nb, v.sel_nt}; }  // ends of non-dummy nodes
+DEV Bits tip_bits(const Nav& v) { return Bits{v.tip, nullptr, v.c_tip, v.nb, nullptr}; }
+
+// Smallest set position >= i of b (one exists), by a scan of its words.
+DEV uint64_t next_one(const uint64_t* b, uint64_t i) {
+  uint64_t w = i >> 6;
+  uint64_t x = b[w] & (~0ull << (i & 63));
+  while (!x) x = b[++w];
+  return (w << 6) + (uint64_t)__builtin_ctzll(x);
+}
+
+// Largest set position < i of b, or NONE.
+DEV uint64_t prev_one(const uint64_t* b, uint64_t i) {
+  if (i == 0) return NONE;
+  uint64_t w = (i - 1) >> 6;
+  uint64_t x = b[w] & (~0ull >> (63 - ((i - 1) & 63)));
+  while (!x) {
+    if (w == 0) return NONE;
+    x = b[--w];
+  }
+  return (w << 6) + 63 - (uint64_t)__builtin_clzll(x);
+}
 
 // Eight bytes of W from row p on; rows past m read as 0xFF (no class).
 DEV uint64_t w8(const Nav& v, uint64_t p) {
@@ -109,6 +144,12 @@ DEV uint64_t select_cls(const Nav& v, int s, uint64_t r) {
   const uint64_t* c = v.c_cls + (uint64_t)s * (v.nb + 1);
   if (r >= c[v.nb]) return NONE;
   uint64_t lo = 0, hi = v.nb;
+  if (s < 4) {  // unflagged classes have select directories
+    const uint32_t* sel = v.sel_cls + (uint64_t)s * v.sel_stride;
+    const uint64_t j = r / SEL_S;
+    lo = sel[j];
+    if ((j + 1) * SEL_S < c[v.nb]) hi = (uint64_t)sel[j + 1] + 1;
+  }
   while (hi - lo > 1) {
     const uint64_t mid = (lo + hi) >> 1;
     if (c[mid] <= r)
@@ -130,11 +171,8 @@ DEV int block_of(const Nav& v, uint64_t row) {
 
 DEV bool bit(const uint64_t* b, uint64_t i) { return (b[i >> 6] >> (i & 63)) & 1; }
 
-// Last row of the node that holds row i.
-DEV uint64_t node_of(const Nav& v, uint64_t i) {
-  const Bits L = last_bits(v);
-  return L.select(L.rank(i));
-}
+// Last row of the node that holds row i (the next last bit).
+DEV uint64_t node_of(const Nav& v, uint64_t i) { return next_one(v.last, i); }
 
 // Unflagged row entering non-dummy node u (its last row), block c.
 DEV uint64_t in_row(const Nav& v, uint64_t u, int c) {
@@ -175,10 +213,9 @@ DEV uint64_t nav_forward(const Nav& v, uint64_t x) {
 // Outgoing edges of node u (its last row): the rows of the node, 0 for a
 // node whose only row is a '$' row.
 DEV uint64_t nav_outdeg(const Nav& v, uint64_t u) {
-  const Bits L = last_bits(v);
-  const uint64_t rk = L.rank(u);
-  const uint64_t start = rk ? L.select(rk - 1) + 1 : 0;
-  return (v.W[u] & 7) == 0 ? 0 : u - start + 1;
+  if ((v.W[u] & 7) == 0) return 0;
+  const uint64_t p = prev_one(v.last, u);  // last row of the previous node
+  return u - (p == NONE ? 0 : p + 1) + 1;
 }
 
 // Incoming edges of node u (dummy rows not counted): its unflagged entering
@@ -188,10 +225,22 @@ DEV uint64_t nav_indeg(const Nav& v, uint64_t u) {
   const int c = block_of(v, u);
   const uint64_t j = in_row(v, u, c);
   if (bit(v.tip, j)) return 0;  // entered only by its dummy row
-  const uint64_t r = rank_cls(v, c - 1, j);
-  uint64_t j2 = select_cls(v, c - 1, r + 1);
-  if (j2 == NONE) j2 = v.m;
-  return 1 + rank_cls(v, 4 + c - 1, j2) - rank_cls(v, 4 + c - 1, j);
+  // flagged c-rows after j up to the next unflagged c-row
+  uint64_t n = 1;
+  for (uint64_t p = j + 1; p < v.m; ++p) {
+    const uint8_t w = v.W[p];
+    if (w == (uint8_t)c) break;
+    n += w == (uint8_t)(c | 8);
+  }
+  return n;
+}
+
+// sel[j] = block holding the one of rank j * SEL_S, from the cumulative
+// counts cum[0..nb] (one thread per block).
+__global__ void k_select_dir(const uint64_t* __restrict__ cum, uint64_t nb, uint32_t* __restrict__ sel) {
+  const uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  for (uint64_t j = (cum[b] + SEL_S - 1) / SEL_S; j * SEL_S < cum[b + 1]; ++j) sel[j] = (uint32_t)b;
 }
 
 constexpr int OP_NODE = 1, OP_FORWARD = 2, OP_BACKWARD = 3, OP_OUTDEG = 4, OP_INDEG = 5, OP_LABEL = 6;
@@ -314,6 +363,7 @@ __global__ void k_remove_tips(Nav v, uint64_t* __restrict__ valid, uint32_t max_
 struct NavIndex {
   Nav v;
   uint64_t* counts = nullptr;  // c_last, c_nt, c_tip, then c_cls
+  uint32_t* sel = nullptr;     // select directories: node ends, then classes 0..3
 };
 
 }  // namespace sdbg
@@ -322,6 +372,7 @@ namespace sdbg_abi {
 void free_index(void* p) {
   auto* ix = static_cast<sdbg::NavIndex*>(p);
   pool_free(ix->counts);
+  pool_free(ix->sel);
   delete ix;
 }
 }  // namespace sdbg_abi
@@ -365,8 +416,21 @@ int sdbg_index_build(const sdbg_graph* g, const sdbg_params* params, sdbg_index*
       v.c_nt = cn;
       v.c_tip = ct;
       v.c_cls = cc;
+      // select directories (at most m / SEL_S + 1 samples each)
+      v.sel_stride = v.m / SEL_S + 2;
+      DBuf<uint32_t> sel = c.buf<uint32_t>(5 * v.sel_stride);
+      if (nb) {
+        k_select_dir<<<(unsigned)ceil_div(nb, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(cn, nb, sel.get());
+        for (int q = 0; q < 4; ++q)
+          k_select_dir<<<(unsigned)ceil_div(nb, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(
+              cc + (uint64_t)q * (nb + 1), nb, sel.get() + (uint64_t)(q + 1) * v.sel_stride);
+        c.check_launch("nav select directories");
+      }
+      v.sel_nt = sel.get();
+      v.sel_cls = sel.get() + v.sel_stride;
       c.sync();
       ix->counts = cnt.release_ownership();
+      ix->sel = sel.release_ownership();
     } catch (...) {
       delete ix;
       throw;
