@@ -2252,9 +2252,9 @@ struct Counter {
           // one bucket per pair of windows
           Stage st_(c, "window_flags", 3 * words * 8 + NW + ceil_div(NW, 2) * 8 * ns.bw);
           if (ns.bw == 4)
-            k_node_window_flags<4, 8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, nt, wf.get());
+            k_node_window_flags<4, 12><<<grid1(ceil_div(NW, 12)), SDBG_BLOCK, 0, c.s>>>(ea, nt, wf.get());
           else
-            k_node_window_flags<2, 8><<<grid1(ceil_div(NW, 8)), SDBG_BLOCK, 0, c.s>>>(ea, nt, wf.get());
+            k_node_window_flags<2, 12><<<grid1(ceil_div(NW, 12)), SDBG_BLOCK, 0, c.s>>>(ea, nt, wf.get());
           c.check_launch("window_flags");
         }
       } else {
