@@ -1007,7 +1007,7 @@ DEV void put_slot(uint64_t* w, uint64_t slot, int pos, int sb) {
 // A bucket with more nodes than its list marks itself and the spill line
 // overfull.  The
 // barriers order LDS only: no thread reads another's global data.
-constexpr int NODE_LIST = 8;
+constexpr int NODE_LIST = 6;
 
 DEV uint64_t node_stretch_bound(const SortedView& S, const NodeShape& p, uint64_t B, int r) {
   const uint64_t nblk = 1ull << (p.bb - p.s);
