@@ -1,9 +1,9 @@
 // Counting path (Section 2, third paragraph): reads -> 2-bit packing ->
 // both-strand (k+1)-mer keys -> MSD radix partition in HBM -> per-leaf LDS
 // sort + run-length count + solid filter -> mercy-kmers -> sorted edge set.
-// One-word keys are counted as canonical keys (one per window, see
-// window_emit) and the counted set is expanded to both strands before the
-// mercy step (expand_rc).
+// Keys of up to three words are counted as canonical keys (one per window,
+// see window_emit) and the counted set is expanded to both strands before
+// the mercy step (expand_rc).
 //
 // Keys are the colex edge keys (Section 2, second paragraph): digits
 // e[k-1], ..., e[0], e[k] of the (k+1)-mer e.  The partition cuts the key
@@ -1314,23 +1314,24 @@ __global__ void k_lookup_counts(const uint64_t* __restrict__ keys, uint64_t n, S
   out[i] = sv_find<W>(L, q, &ix) ? lcnt[ix] : 0;
 }
 
-// Counted canonical one-word keys -> the other strand's keys.  Every key
-// that is not its own reverse complement gives its reverse complement with
-// the same count, packed as a two-word key (key << 32 | count) so that the
-// partition engine sorts the pairs by key.  Pass 0 counts such keys per
-// block of SDBG_BLOCK, pass 1 writes them at the scanned block offsets.
+// Counted canonical keys (one to three words) -> the other strand's keys.
+// Every key that is not its own reverse complement gives its reverse
+// complement with the same count, packed as a (W+1)-word key (key << 32 |
+// count) so that the partition engine sorts the pairs by key.  Pass 0
+// counts such keys per block of SDBG_BLOCK, pass 1 writes them at the
+// scanned block offsets.
+template <int W>
 __global__ __launch_bounds__(SDBG_BLOCK) void k_rc_pack(const uint64_t* __restrict__ S,
                                                         const uint32_t* __restrict__ Sc, uint64_t n, int kb, int pass,
                                                         uint64_t* __restrict__ bpos, uint64_t* __restrict__ R2) {
   __shared__ uint32_t wc[SDBG_WAVES];
   const uint64_t i = blockIdx.x * (uint64_t)SDBG_BLOCK + threadIdx.x;
-  uint64_t r = 0;
+  Key<W> r = key_zero<W>();
   bool emit = false;
   if (i < n) {
-    Key<1> x;
-    x.w[0] = S[i];
-    r = key_revcomp<1>(x, kb).w[0];
-    emit = r != x.w[0];
+    const Key<W> x = key_load<W>(S + i * W);
+    r = key_revcomp<W>(x, kb);
+    emit = !key_eq<W>(r, x);
   }
   const uint64_t m = __ballot(emit);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1348,17 +1349,27 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_rc_pack(const uint64_t* __restri
   if (!emit) return;
   uint64_t pos = bpos[blockIdx.x] + (uint64_t)__popcll(m & ((1ull << lane) - 1));
   for (int w = 0; w < wid; ++w) pos += wc[w];
-  R2[2 * pos] = r >> 32;
-  R2[2 * pos + 1] = (r << 32) | Sc[i];
+  Key<W + 1> t;
+  t.w[0] = 0;
+#pragma unroll
+  for (int j = 0; j < W; ++j) t.w[j + 1] = r.w[j];
+  t = key_shl<W + 1>(t, 32);
+  t.w[W] |= Sc[i];
+  key_store<W + 1>(R2 + pos * (W + 1), t);
 }
 
+template <int W>
 __global__ void k_rc_unpack(const uint64_t* __restrict__ R2, uint64_t n, uint64_t* __restrict__ keys,
                             uint32_t* __restrict__ cnt) {
   const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const uint64_t hi = R2[2 * i], lo = R2[2 * i + 1];
-  keys[i] = (hi << 32) | (lo >> 32);
-  cnt[i] = (uint32_t)lo;
+  const Key<W + 1> t = key_load<W + 1>(R2 + i * (W + 1));
+  cnt[i] = (uint32_t)t.w[W];
+  const Key<W + 1> k = key_shr<W + 1>(t, 32);
+  Key<W> out;
+#pragma unroll
+  for (int j = 0; j < W; ++j) out.w[j] = k.w[j + 1];
+  key_store<W>(keys + i * W, out);
 }
 
 // Merge of two disjoint sorted key sets (with their counts) along the merge
@@ -1524,6 +1535,10 @@ struct SegList {
   }
   SegView view() const { return SegView{off.get(), len.get(), bit.get(), buf.get(), D.get(), n}; }
 };
+
+// Keys of at most this many words are counted as canonical keys (a key and
+// its count then fit kCanonWords + 1 words for the reverse-complement sort).
+constexpr int kCanonWords = 3;
 
 // Leaf launches with at least this many segments are split by segment size.
 constexpr uint64_t kLeafSplitMin = 16384;
@@ -1869,34 +1884,34 @@ struct Counter {
   // (with the same counts) are sorted as two-word (key, count) keys and
   // merged in.  One-word keys only.
   void expand_rc(DBuf<uint64_t>& S, DBuf<uint32_t>& Sc, uint64_t* nS, int kb) {
-    if constexpr (W == 1) {
+    if constexpr (W <= kCanonWords) {
       const uint64_t n = *nS;
       const uint64_t nblk = ceil_div(n, SDBG_BLOCK);
       DBuf<uint64_t> bpos = c.buf<uint64_t>(nblk), tot = c.buf<uint64_t>(1);
-      k_rc_pack<<<(unsigned)nblk, SDBG_BLOCK, 0, c.s>>>(S.get(), Sc.get(), n, kb, 0, bpos.get(), nullptr);
+      k_rc_pack<W><<<(unsigned)nblk, SDBG_BLOCK, 0, c.s>>>(S.get(), Sc.get(), n, kb, 0, bpos.get(), nullptr);
       c.check_launch("rc_count");
       scan_excl<uint64_t, uint64_t>(bpos.get(), bpos.get(), nblk, tot.get(), c);
       const uint64_t nR = c.d2h_one(tot.get());
-      DBuf<uint64_t> R2 = c.buf<uint64_t>(2 * nR);
+      DBuf<uint64_t> R2 = c.buf<uint64_t>((W + 1) * nR);
       {
-        Stage st_(c, "rc_pack", n * 12 + nR * 16);
-        k_rc_pack<<<(unsigned)nblk, SDBG_BLOCK, 0, c.s>>>(S.get(), Sc.get(), n, kb, 1, bpos.get(), R2.get());
+        Stage st_(c, "rc_pack", n * (8 * W + 4) + nR * 8 * (W + 1));
+        k_rc_pack<W><<<(unsigned)nblk, SDBG_BLOCK, 0, c.s>>>(S.get(), Sc.get(), n, kb, 1, bpos.get(), R2.get());
         c.check_launch("rc_pack");
       }
       if (nR == 0) return;
       DBuf<uint64_t> R2s;
       uint64_t nR2 = 0;
       {
-        Counter<2> c2(c);
+        Counter<W + 1> c2(c);
         c2.sort_unique(R2, nR, kb + 32, R2s, &nR2, true);
       }
       SDBG_CHECK(nR2 == nR, -4, "reverse complement keys are not distinct");
       R2.free();
-      DBuf<uint64_t> Rk = c.buf<uint64_t>(nR);
+      DBuf<uint64_t> Rk = c.buf<uint64_t>(nR * W);
       DBuf<uint32_t> Rc = c.buf<uint32_t>(nR);
       {
-        Stage st_(c, "rc_unpack", nR * 16 + nR * 12);
-        k_rc_unpack<<<grid1(nR), SDBG_BLOCK, 0, c.s>>>(R2s.get(), nR, Rk.get(), Rc.get());
+        Stage st_(c, "rc_unpack", nR * 8 * (W + 1) + nR * (8 * W + 4));
+        k_rc_unpack<W><<<grid1(nR), SDBG_BLOCK, 0, c.s>>>(R2s.get(), nR, Rk.get(), Rc.get());
         c.check_launch("rc_unpack");
       }
       R2s.free();
@@ -1911,7 +1926,7 @@ struct Counter {
       (void)Sc;
       (void)nS;
       (void)kb;
-      throw Error(-4, "canonical counting is for one-word keys");
+      throw Error(-4, "canonical counting is for keys of at most three words");
     }
   }
 
@@ -2038,9 +2053,10 @@ struct Counter {
     if (pr.NW == 0) return;
     const uint64_t NW = pr.NW, words = pr.words;
     ExArgs ea = pr.ea;
-    // One-word keys are counted on one strand (canonical keys) and expanded
-    // to both strands afterwards: half the keys pass the partition.
-    ea.canon = W == 1 ? 1 : 0;
+    // Keys of up to three words are counted on one strand (canonical keys)
+    // and expanded to both strands afterwards: half the keys pass the
+    // partition.
+    ea.canon = W <= kCanonWords ? 1 : 0;
     const uint32_t nbins = 1u << ea.dbits;
     const uint64_t win_per_tile = (uint64_t)SDBG_BLOCK * IPT;
     const uint64_t ntiles = ceil_div(NW, win_per_tile);
