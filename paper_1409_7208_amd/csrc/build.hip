@@ -334,22 +334,104 @@ DEV void sv_bounds2(const SortedView& v1, const Key<W>& q1, const SortedView& v2
   *r2 = lo2;
 }
 
-// Row placement.  rf: bit0 last, bit1 valid, bit2 tip.
+// Row placement.  rf: bit0 last, bit1 valid, bit2 tip.  A real row's
+// index is its edge index plus the '$' rows before it (Zo keys below its
+// source) and the dummy rows before it (Zi keys up to its source's top
+// k-1 symbols, then 3): both counts grow with the edge index, so a tile of
+// consecutive edges needs only the stretches of Zo and Zi between the
+// counts of its first and last edges.  Those are staged in LDS (a search
+// in global memory when they do not fit) and each edge's counts are found
+// there.
 template <int W>
-__global__ void k_place_real(SortedView E, const uint32_t* __restrict__ cnt, const uint8_t* __restrict__ fl,
-                             SortedView Zo, SortedView Zi, uint8_t* __restrict__ Wb, uint32_t* __restrict__ mult,
-                             uint8_t* __restrict__ rf) {
-  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (i >= E.n) return;
-  const Key<W> x = key_load<W>(E.keys + i * W);
-  const Key<W> hi3 = key_or_low<W>(key_shl<W>(key_shr<W>(x, 4), 2), 3);
-  uint64_t ro, ri;
-  sv_bounds2<W, true>(Zo, key_shr<W>(x, 2), Zi, hi3, &ro, &ri);
-  const uint64_t p = i + ro + ri;
-  const uint8_t f = fl[i];
-  Wb[p] = (uint8_t)(((x.w[W - 1] & 3) + 1) | ((f & 1) ? 8 : 0));
-  mult[p] = cnt[i];
-  rf[p] = (uint8_t)(((f & 8) ? 1 : 0) | 2);
+struct PlaceTile {
+  static constexpr int IPT = W == 1 ? 8 : (W == 2 ? 4 : 2);
+  static constexpr int TILE = SDBG_BLOCK * IPT;
+  static constexpr int RCAP = 1024 / W;  // staged keys of each list (a few per tile expected)
+};
+
+template <int W, bool UPPER>
+DEV uint64_t lds_bound(const uint64_t* R, uint32_t lo, uint32_t hi, const Key<W>& q) {
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    const Key<W> k = key_load<W>(R + (uint64_t)mid * W);
+    if (UPPER ? !key_less<W>(q, k) : key_less<W>(k, q))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <int W, bool UPPER>
+DEV uint64_t glob_bound(const uint64_t* keys, uint64_t lo, uint64_t hi, const Key<W>& q) {
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    const Key<W> k = key_load<W>(keys + mid * W);
+    if (UPPER ? !key_less<W>(q, k) : key_less<W>(k, q))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <int W>
+DEV Key<W> place_hi3(const Key<W>& x) {
+  return key_or_low<W>(key_shl<W>(key_shr<W>(x, 4), 2), 3);
+}
+
+template <int W>
+__global__ __launch_bounds__(SDBG_BLOCK) void k_place_real(SortedView E, const uint32_t* __restrict__ cnt,
+                                                           const uint8_t* __restrict__ fl, SortedView Zo,
+                                                           SortedView Zi, uint8_t* __restrict__ Wb,
+                                                           uint32_t* __restrict__ mult, uint8_t* __restrict__ rf) {
+  constexpr int IPT = PlaceTile<W>::IPT, TILE = PlaceTile<W>::TILE, RCAP = PlaceTile<W>::RCAP;
+  __shared__ uint64_t RO[RCAP * W], RI[RCAP * W];
+  __shared__ uint64_t rg[4];
+  const uint64_t i0 = blockIdx.x * (uint64_t)TILE;
+  const uint64_t i1 = i0 + TILE < E.n ? i0 + TILE : E.n;
+  if (threadIdx.x < 4) {
+    // Zo lower bounds of the first and last sources, Zi upper bounds of
+    // their hi3 keys
+    const Key<W> x = key_load<W>(E.keys + ((threadIdx.x & 1) ? i1 - 1 : i0) * W);
+    uint64_t r;
+    if (threadIdx.x < 2) {
+      uint64_t a, b;
+      sv_bounds2<W, true>(Zo, key_shr<W>(x, 2), Zi, place_hi3<W>(x), &a, &b);
+      r = a;
+    } else {
+      uint64_t a, b;
+      sv_bounds2<W, true>(Zo, key_shr<W>(x, 2), Zi, place_hi3<W>(x), &a, &b);
+      r = b;
+    }
+    rg[threadIdx.x] = r;
+  }
+  __syncthreads();
+  const uint64_t o0 = rg[0], o1 = rg[1], z0 = rg[2], z1 = rg[3];
+  const bool so = o1 - o0 <= (uint64_t)RCAP, si = z1 - z0 <= (uint64_t)RCAP;
+  if (so)
+    for (uint32_t j = threadIdx.x; j < (uint32_t)(o1 - o0); j += SDBG_BLOCK)
+      key_store<W>(RO + (uint64_t)j * W, key_load_g<W>(Zo.keys + (o0 + j) * W));
+  if (si)
+    for (uint32_t j = threadIdx.x; j < (uint32_t)(z1 - z0); j += SDBG_BLOCK)
+      key_store<W>(RI + (uint64_t)j * W, key_load_g<W>(Zi.keys + (z0 + j) * W));
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) {
+    const uint64_t i = i0 + (uint64_t)q * SDBG_BLOCK + threadIdx.x;
+    if (i >= i1) continue;
+    const Key<W> x = key_load<W>(E.keys + i * W);
+    const Key<W> src = key_shr<W>(x, 2), hi3 = place_hi3<W>(x);
+    const uint64_t ro = so ? o0 + lds_bound<W, false>(RO, 0, (uint32_t)(o1 - o0), src)
+                           : glob_bound<W, false>(Zo.keys, o0, o1, src);
+    const uint64_t ri = si ? z0 + lds_bound<W, true>(RI, 0, (uint32_t)(z1 - z0), hi3)
+                           : glob_bound<W, true>(Zi.keys, z0, z1, hi3);
+    const uint64_t p = i + ro + ri;
+    const uint8_t f = fl[i];
+    Wb[p] = (uint8_t)(((x.w[W - 1] & 3) + 1) | ((f & 1) ? 8 : 0));
+    mult[p] = cnt[i];
+    rf[p] = (uint8_t)(((f & 8) ? 1 : 0) | 2);
+  }
 }
 
 template <int W>
@@ -572,7 +654,8 @@ struct Builder {
     DBuf<uint32_t> mult = c.buf<uint32_t>(m);
     {
       Stage st_(c, "place_real", n * (8 * W + 4 + 1) + n * 6);
-      k_place_real<W><<<grid1(n), SDBG_BLOCK, 0, c.s>>>(E, count, fl.get(), Zo, Zi, Wb.get(), mult.get(), rf.get());
+      k_place_real<W><<<(unsigned)ceil_div(n, PlaceTile<W>::TILE), SDBG_BLOCK, 0, c.s>>>(E, count, fl.get(), Zo, Zi,
+                                                                                        Wb.get(), mult.get(), rf.get());
       c.check_launch("place_real");
     }
     if (nzo) {

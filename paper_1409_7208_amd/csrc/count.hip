@@ -784,18 +784,21 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_compact(SegView v, uint64_t* con
                                                         const uint64_t* __restrict__ lpos, uint64_t* __restrict__ skeys,
                                                         uint32_t* __restrict__ scnt, uint64_t* __restrict__ lkeys,
                                                         uint32_t* __restrict__ lcnt) {
-  const uint64_t s = blockIdx.x;
+  // one wave per segment (a leaf writes a few hundred keys at most)
+  const uint64_t s = (uint64_t)blockIdx.x * SDBG_WAVES + (threadIdx.x >> 6);
+  if (s >= v.n) return;
+  const uint32_t lane = threadIdx.x & 63;
   const uint64_t off = v.off[s];
   const uint64_t* src = bufs[v.buf[s]] + off * W;
   const uint64_t a = nsolid[s], b = nlow ? nlow[s] : 0;
   const uint64_t ps = spos[s];
-  for (uint64_t i = threadIdx.x; i < a; i += SDBG_BLOCK) {
+  for (uint64_t i = lane; i < a; i += 64) {
     key_store<W>(skeys + (ps + i) * W, key_load_g<W>(src + i * W));
     scnt[ps + i] = cnt[off + i];
   }
   if (b) {
     const uint64_t pl = lpos[s];
-    for (uint64_t i = threadIdx.x; i < b; i += SDBG_BLOCK) {
+    for (uint64_t i = lane; i < b; i += 64) {
       key_store<W>(lkeys + (pl + i) * W, key_load_g<W>(src + (a + i) * W));
       lcnt[pl + i] = cnt[off + a + i];
     }
@@ -1827,7 +1830,8 @@ struct Counter {
     }
     if (L.n) {
       Stage st_(c, "compact", 2 * outb + L.n * 32);
-      k_compact<W><<<(unsigned)L.n, SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, cnt, nsolid.get(), spos.get(),
+      k_compact<W><<<(unsigned)ceil_div(L.n, SDBG_WAVES), SDBG_BLOCK, 0, c.s>>>(L.view(), d_bufs, cnt, nsolid.get(),
+                                                                             spos.get(),
                                                             want_low ? nlow.get() : nullptr, lpos.get(), skeys.get(),
                                                             scnt.get(), want_low ? lkeys.get() : nullptr,
                                                             want_low ? lcnt.get() : nullptr);
