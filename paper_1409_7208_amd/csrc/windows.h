@@ -33,7 +33,7 @@ struct ExArgs {
 };
 
 // Granularity of the window -> read table.
-constexpr uint64_t TR_GRAIN = 256;
+constexpr uint64_t TR_GRAIN = 64;
 
 DEV uint64_t find_read(const uint64_t* __restrict__ woff, uint64_t n_reads, uint64_t g) {
   uint64_t lo = 0, hi = n_reads;  // woff[lo] <= g < woff[hi]
