@@ -386,11 +386,36 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
     check_params(params);
     const uint32_t k = params->k, w = (uint32_t)sdbg::key_words((int)k);
     sdbg::Ctx c(params->stream);
-    std::vector<std::vector<uint64_t>> off(n_sets);
-    std::vector<uint64_t> occ(n_sets);
-    for (uint64_t s = 0; s < n_sets; ++s) {
-      off[s] = host_offsets(c, &sets[s]);
-      occ[s] = occ_bound(off[s], k);
+    // Per set: bases and occurrence bound.  Host sets are checked on the
+    // host; device sets on the device (one read-back for all of them), so
+    // their offsets never travel to the host.
+    std::vector<std::vector<uint64_t>> off(n_sets);  // host sets only
+    std::vector<uint64_t> occ(n_sets, 0), nbases(n_sets, 0);
+    {
+      sdbg::DBuf<unsigned long long> st = c.buf<unsigned long long>(3 * n_sets);
+      uint64_t n_dev = 0;
+      for (uint64_t s = 0; s < n_sets; ++s) {
+        if (sets[s].on_device && sets[s].n_reads) {
+          SDBG_CHECK(sets[s].offsets, SDBG_E_INVAL, "null offsets");
+          if (!n_dev++) sdbg::fill<uint64_t>(reinterpret_cast<uint64_t*>(st.get()), 3 * n_sets, 0, c);
+          sdbg::offsets_summary(sets[s].offsets, sets[s].n_reads, k, st.get() + 3 * s, c);
+        } else {
+          off[s] = host_offsets(c, &sets[s]);
+          occ[s] = occ_bound(off[s], k);
+          nbases[s] = off[s].back();
+        }
+      }
+      if (n_dev) {
+        std::vector<unsigned long long> h(3 * n_sets);
+        c.d2h(h.data(), st.get(), 3 * n_sets);
+        for (uint64_t s = 0; s < n_sets; ++s) {
+          if (!(sets[s].on_device && sets[s].n_reads)) continue;
+          SDBG_CHECK(h[3 * s] == 0, SDBG_E_INVAL, "offsets[0] must be 0 and offsets must be non-decreasing");
+          occ[s] = h[3 * s + 1];
+          nbases[s] = h[3 * s + 2];
+          SDBG_CHECK(nbases[s] == 0 || sets[s].seq, SDBG_E_INVAL, "null seq");
+        }
+      }
     }
     const bool shared = !(params->mercy && params->d >= 2);
     sdbg::CountParams P{(int)k, params->d, params->mercy != 0, (int)params->prefix_len, params->mem_budget};
@@ -415,7 +440,7 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
         {
           sdbg::DevReads R{};
           R.n_reads = sets[s0].n_reads;
-          R.n_bases = off[s0].back();
+          R.n_bases = nbases[s0];
           sdbg::DBuf<uint8_t> seq_d = c.buf<uint8_t>(R.n_bases + 16);
           sdbg::DBuf<uint64_t> off_d = c.buf<uint64_t>(R.n_reads + 1);
           if (R.n_bases) {
@@ -424,7 +449,10 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
             else
               c.h2d(seq_d.get(), sets[s0].seq, R.n_bases);
           }
-          c.h2d(off_d.get(), off[s0].data(), R.n_reads + 1);
+          if (sets[s0].on_device && R.n_reads)
+            c.d2d(off_d.get(), sets[s0].offsets, R.n_reads + 1);
+          else
+            c.h2d(off_d.get(), off[s0].data(), R.n_reads + 1);
           R.seq = seq_d.get();
           R.offsets = off_d.get();
           sdbg::count_solid(R, P, c, &eo);
@@ -439,32 +467,39 @@ int sdbg_batch_run(const sdbg_reads* sets, uint64_t n_sets, const sdbg_params* p
       uint64_t s1 = s0, keys = 0, bases = 0, reads = 0;
       while (s1 < n_sets && occ[s1] <= max_keys && keys + occ[s1] <= max_keys) {
         keys += occ[s1];
-        bases += off[s1].back();
+        bases += nbases[s1];
         reads += sets[s1].n_reads;
         ++s1;
       }
       std::vector<sdbg::EdgesOut> outs;
       {
         sdbg::DBuf<uint8_t> seq_d = c.buf<uint8_t>(bases + 16);
-        std::vector<uint64_t> ho(reads + 1), rb(s1 - s0 + 1);
+        sdbg::DBuf<uint64_t> off_d = c.buf<uint64_t>(reads + 1);
+        std::vector<uint64_t> rb(s1 - s0 + 1);
+        std::vector<std::vector<uint64_t>> ho;  // rebased offsets of host sets, kept until the copies are done
         uint64_t rp = 0, bp = 0;
         for (uint64_t s = s0; s < s1; ++s) {
           rb[s - s0] = rp;
-          const uint64_t nb = off[s].back();
-          for (uint64_t i = 0; i < sets[s].n_reads; ++i) ho[rp + i] = bp + off[s][i];
+          const uint64_t nb = nbases[s];
+          const uint64_t nr = sets[s].n_reads;
+          if (sets[s].on_device && nr) {
+            sdbg::offsets_rebase(sets[s].offsets, nr, bp, off_d.get() + rp, c);
+          } else if (nr) {
+            ho.emplace_back(nr);
+            for (uint64_t i = 0; i < nr; ++i) ho.back()[i] = bp + off[s][i];
+            c.h2d(off_d.get() + rp, ho.back().data(), nr);
+          }
           if (nb) {
             if (sets[s].on_device)
               c.d2d(seq_d.get() + bp, sets[s].seq, nb);
             else
               c.h2d(seq_d.get() + bp, sets[s].seq, nb);
           }
-          rp += sets[s].n_reads;
+          rp += nr;
           bp += nb;
         }
-        ho[reads] = bp;
+        sdbg::fill<uint64_t>(off_d.get() + reads, 1, bp, c);
         rb[s1 - s0] = rp;
-        sdbg::DBuf<uint64_t> off_d = c.buf<uint64_t>(reads + 1);
-        c.h2d(off_d.get(), ho.data(), reads + 1);
         sdbg::DevReads R{seq_d.get(), off_d.get(), reads, bases};
         try {
           sdbg::count_solid_sets(R, rb, P, c, &outs);

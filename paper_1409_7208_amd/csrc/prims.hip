@@ -125,6 +125,50 @@ bool nondecreasing(const uint64_t* off, uint64_t n, Ctx& c) {
   return c.d2h_one(flag.get()) == 0;
 }
 
+__global__ void k_off_summary(const uint64_t* __restrict__ off, uint64_t n, uint32_t k,
+                              unsigned long long* __restrict__ st) {
+  __shared__ unsigned long long part[2];
+  if (threadIdx.x < 2) part[threadIdx.x] = 0;
+  __syncthreads();
+  unsigned long long bad = 0, occ = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint64_t a = off[i], b = off[i + 1];
+    if (b < a) {
+      bad = 1;
+    } else if (b - a > k) {
+      occ += 2 * (b - a - k);
+    }
+  }
+  if (bad) atomicOr(&part[0], 1ull);
+  if (occ) atomicAdd(&part[1], occ);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (part[0] || (blockIdx.x == 0 && off[0] != 0)) atomicOr(&st[0], 1ull);
+    if (part[1]) atomicAdd(&st[1], part[1]);
+    if (blockIdx.x == 0) st[2] = off[n];
+  }
+}
+
+void offsets_summary(const uint64_t* off, uint64_t n, uint32_t k, unsigned long long* st, Ctx& c) {
+  uint64_t blocks = ceil_div(n, SDBG_BLOCK);
+  if (blocks > 1024) blocks = 1024;
+  if (blocks == 0) blocks = 1;
+  k_off_summary<<<(unsigned)blocks, SDBG_BLOCK, 0, c.s>>>(off, n, k, st);
+  c.check_launch("offsets summary");
+}
+
+__global__ void k_off_rebase(const uint64_t* __restrict__ off, uint64_t n, uint64_t base, uint64_t* __restrict__ out) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = off[i] + base;
+}
+
+void offsets_rebase(const uint64_t* off, uint64_t n, uint64_t base, uint64_t* out, Ctx& c) {
+  if (!n) return;
+  k_off_rebase<<<(unsigned)ceil_div(n, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(off, n, base, out);
+  c.check_launch("offsets rebase");
+}
+
 template void scan_excl<uint64_t, uint64_t>(const uint64_t*, uint64_t*, uint64_t, uint64_t*, Ctx&);
 template void scan_excl<uint32_t, uint32_t>(const uint32_t*, uint32_t*, uint64_t, uint64_t*, Ctx&);
 template void scan_excl<uint32_t, uint64_t>(const uint32_t*, uint64_t*, uint64_t, uint64_t*, Ctx&);

@@ -222,3 +222,25 @@ def test_autotune_writes_only_its_struct():
         assert t.mercy_shift == 3 and list(t.reserved) == [0, 0]
     finally:
         sdbg.tune_set(None)
+
+
+def test_batch_rejects_bad_device_offsets():
+    """Offsets of device-resident sets are checked on the device: a first
+    offset other than 0, or offsets that decrease, give SDBG_E_INVAL and no
+    outputs."""
+    import torch
+
+    good = synth.random_small(20, 30, 60, 300, 0.0, 5)
+    seq, off = to_device(good)
+    for case in ("first", "decreasing"):
+        o = off.clone()
+        if case == "first":
+            o[0] = 5
+        else:
+            o[3] = o[4] + 7  # offsets[3] > offsets[4]
+        with pytest.raises(sdbg.SdbgError):
+            sdbg.batch_run([(seq, off), (seq, o)], 21, 2, False)
+    torch.cuda.synchronize()
+    res = sdbg.batch_run([(seq, off)], 21, 2, False)
+    _check_against_oracle([good], res, 21, 2, False)
+    _close(res)
