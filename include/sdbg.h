@@ -350,6 +350,40 @@ int sdbg_navigate(const sdbg_index *index, int op, const uint64_t *rows, uint64_
  * nothing. */
 int sdbg_remove_tips(sdbg_graph *g, const sdbg_index *index, uint32_t max_len, uint64_t *n_removed, void *stream);
 
+/* Unitigs of a graph's valid edges (Section 2, fourth paragraph, and its
+ * Fig. 1: contigs of one k feed the graph of the next; the paper gives no
+ * construction, so this is the reading implemented).  Degrees count valid
+ * edges only (g->valid after any cleaning).  A unitig is a maximal path
+ * whose inner nodes have in-degree 1 and out-degree 1; every valid edge lies
+ * on exactly one.  A unitig starts at an edge whose source node is not
+ * (in 1, out 1); a cycle of such nodes starts at its smallest row.  Unitig
+ * u, of len[u] edges, spells the k-mer of its first edge's source node and
+ * then each edge's label (k + len[u] bases; for a cycle the last k repeat
+ * the first k); mult[u] is the sum of its edges' mult.  Unitigs are listed
+ * by the row of their first edge, ascending.  seq and offsets form a read
+ * set on the device (sdbg_reads with on_device = 1), so the unitigs of one k
+ * can be counted with the reads at the next.  index must have been built
+ * on g (SDBG_E_INVAL otherwise).  The result lives in device memory;
+ * release it with sdbg_free.  Working memory: about 32 bytes per row, twice
+ * that if the valid edges hold cycles. */
+typedef struct sdbg_unitigs {
+  uint32_t k, reserved;
+  uint64_t n;          /* unitigs */
+  uint64_t n_cycles;   /* of which are cycles */
+  uint64_t n_bases;    /* offsets[n] */
+  uint64_t *first_row; /* n: row of the first edge */
+  uint64_t *len;       /* n: edges */
+  uint64_t *mult;      /* n: sum of mult over its edges */
+  uint64_t *offsets;   /* n + 1: unitig u is seq[offsets[u] .. offsets[u+1]) */
+  uint8_t *seq;        /* n_bases: 'A', 'C', 'G', 'T' */
+} sdbg_unitigs;
+int sdbg_unitigs_build(const sdbg_graph *g, const sdbg_index *index, sdbg_unitigs **out, void *stream);
+
+/* Copies a unitig set to caller buffers of n, n, n, n + 1 words and n_bases
+ * bytes; any pointer may be NULL to skip that array. */
+int sdbg_unitigs_to_host(const sdbg_unitigs *u, uint64_t *first_row, uint64_t *len, uint64_t *mult,
+                         uint64_t *offsets, uint8_t *seq);
+
 /* Wraps host arrays (n*w key words ascending and unique, n counts) into a
  * library-owned device edge set, e.g. to build a graph from edges computed
  * elsewhere. */

@@ -689,6 +689,8 @@ void sdbg_free(void* obj) {
       delete g;
     } else if (kind == kIndex) {
       free_index(obj);
+    } else if (kind == kUnitigs) {
+      free_unitigs(obj);
     }
   } catch (...) {
   }

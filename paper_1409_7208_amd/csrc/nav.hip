@@ -180,6 +180,29 @@ DEV uint64_t in_row(const Nav& v, uint64_t u, int c) {
   return select_cls(v, c - 1, N.rank(u) - N.rank(v.F[c]));
 }
 
+// The k-mer of non-dummy node u: put(j, base) for j = 0..k-1.  Walks back
+// one base per step through the entering rows until k bases are known or
+// a node entered by its dummy row, whose k-mer is in tip_seq.
+template <typename Put>
+DEV void node_kmer(const Nav& v, uint64_t u, Put put) {
+  uint64_t cur = u;
+  for (int s = 0; s < v.k; ++s) {
+    const int cc = block_of(v, cur);
+    put(v.k - 1 - s, (uint64_t)(cc - 1));  // base k-1-s of the node
+    if (s + 1 == v.k) break;
+    const uint64_t j = in_row(v, cur, cc);
+    if (bit(v.tip, j)) {  // cur has no incoming edge: its k-mer is stored
+      const uint64_t tr = tip_bits(v).rank(j);
+      for (int i = s; i < v.k; ++i) {  // node base i - s = base i of cur
+        const uint64_t b = 2 * ((uint64_t)v.k * tr + i);
+        put(i - s, (v.tip_seq[b >> 6] >> (b & 63)) & 3);
+      }
+      break;
+    }
+    cur = node_of(v, j);
+  }
+}
+
 __global__ void k_counts(const uint8_t* __restrict__ W, const uint64_t* __restrict__ last,
                          const uint64_t* __restrict__ tip, uint64_t m, uint64_t nb, uint64_t* __restrict__ p_last,
                          uint64_t* __restrict__ p_nt, uint64_t* __restrict__ p_tip, uint64_t* __restrict__ p_cls) {
@@ -270,29 +293,13 @@ __global__ void k_nav(Nav v, int op, const uint64_t* __restrict__ q, uint64_t n,
       out[t] = bit(v.tip, u) ? NONE : node_of(v, in_row(v, u, c));
     } else if (op == OP_INDEG) {
       out[t] = nav_indeg(v, u);
-    } else {  // OP_LABEL: walk back, one base per step, until k bases or a dummy row
-      uint64_t w[4] = {0, 0, 0, 0};
-      auto put = [&](int pos, uint64_t b) { w[(2 * pos) >> 6] |= b << ((2 * pos) & 63); };
+    } else {  // OP_LABEL
       if (bit(v.tip, u)) {
         for (int j = 0; j < lw; ++j) out[t * lw + j] = NONE;
         return;
       }
-      uint64_t cur = u;
-      for (int s = 0; s < v.k; ++s) {
-        const int cc = block_of(v, cur);
-        put(v.k - 1 - s, (uint64_t)(cc - 1));  // base k-1-s of the node
-        if (s + 1 == v.k) break;
-        const uint64_t j = in_row(v, cur, cc);
-        if (bit(v.tip, j)) {  // cur has no incoming edge: its k-mer is stored
-          const uint64_t tr = tip_bits(v).rank(j);
-          for (int i = s; i < v.k; ++i) {  // node base i - s = base i of cur
-            const uint64_t b = 2 * ((uint64_t)v.k * tr + i);
-            put(i - s, (v.tip_seq[b >> 6] >> (b & 63)) & 3);
-          }
-          break;
-        }
-        cur = node_of(v, j);
-      }
+      uint64_t w[4] = {0, 0, 0, 0};
+      node_kmer(v, u, [&](int pos, uint64_t b) { w[(2 * pos) >> 6] |= b << ((2 * pos) & 63); });
       for (int j = 0; j < lw; ++j) out[t * lw + j] = w[j];
     }
   }
@@ -357,6 +364,226 @@ __global__ void k_remove_tips(Nav v, uint64_t* __restrict__ valid, uint32_t max_
   if (cleared) atomicAdd(n_removed, cleared);
 }
 
+// Unitigs of the valid edges (the contigs that Section 2, fourth paragraph
+// and Fig. 1, carry from one k to the next; the paper gives no
+// construction, so this is the reading implemented): maximal paths whose
+// inner nodes have in- and out-degree 1, degrees counted over valid edges.
+// An edge continues the unitig of its predecessor iff its source node is
+// (in 1, out 1); the predecessor is then that node's one valid entering
+// edge.  Ranks along each unitig come from pointer jumping over the
+// predecessor links (a row's link jumps to its link's link each round, in
+// two buffers so that every round reads the previous one), which needs
+// about log2 of the longest unitig rounds over the rows; a row whose link
+// reaches a unitig's first edge is resolved: it holds that edge and its
+// distance from it.  Cycles of (in 1, out 1) nodes have no first edge: once
+// a round resolves nothing new, the remaining rows lie on cycles, each
+// cycle is opened at its smallest row (the minimum over the cycle by
+// doubling) and the jumping resumes.
+
+constexpr uint64_t DONE = 1ull << 63;  // anc[i] flag: i resolved, anc = first edge of its unitig
+
+// Valid rows of node u (its last row); *only = one of them.
+DEV uint32_t valid_out(const Nav& v, const uint64_t* valid, uint64_t u, uint64_t* only) {
+  const uint64_t p = prev_one(v.last, u);
+  uint32_t n = 0;
+  for (uint64_t r = p == NONE ? 0 : p + 1; r <= u; ++r)
+    if (bit(valid, r)) {
+      ++n;
+      *only = r;
+    }
+  return n;
+}
+
+// Valid rows entering node u (its last row); *only = one of them.
+DEV uint32_t valid_in(const Nav& v, const uint64_t* valid, uint64_t u, uint64_t* only) {
+  if (bit(v.tip, u)) return 0;  // a dummy node
+  const int c = block_of(v, u);
+  const uint64_t j = in_row(v, u, c);
+  if (bit(v.tip, j)) return 0;  // entered by its dummy row only
+  uint32_t n = 0;
+  if (bit(valid, j)) {
+    n = 1;
+    *only = j;
+  }
+  for (uint64_t p = j + 1; p < v.m; ++p) {  // flagged c-rows up to the next unflagged one
+    const uint8_t w = v.W[p];
+    if (w == (uint8_t)c) break;
+    if (w == (uint8_t)(c | 8) && bit(valid, p)) {
+      ++n;
+      *only = p;
+    }
+  }
+  return n;
+}
+
+// Predecessor of valid row i on its unitig, or NONE if i starts one.
+DEV uint64_t unitig_pred(const Nav& v, const uint64_t* valid, uint64_t i) {
+  const uint64_t u = node_of(v, i);
+  uint64_t o = NONE, in = NONE;
+  if (valid_out(v, valid, u, &o) != 1) return NONE;
+  if (valid_in(v, valid, u, &in) != 1) return NONE;
+  return in;
+}
+
+// Wave-aggregated add of x to *n.
+DEV void wave_add(unsigned long long* n, uint64_t x) {
+#pragma unroll
+  for (int o = 32; o; o >>= 1) x += __shfl_xor(x, o);
+  if ((threadIdx.x & 63) == 0 && x) atomicAdd(n, (unsigned long long)x);
+}
+
+// anc = predecessor (unresolved) or the row itself | DONE (a first edge);
+// NONE for rows that are not valid edges.  *n_open += unresolved rows.
+__global__ void k_ut_init(Nav v, const uint64_t* __restrict__ valid, uint64_t* __restrict__ anc,
+                          uint64_t* __restrict__ dist, unsigned long long* __restrict__ n_open) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t open = 0;
+  if (i < v.m) {
+    if (!bit(valid, i)) {
+      anc[i] = NONE;
+      dist[i] = 0;
+    } else {
+      const uint64_t p = unitig_pred(v, valid, i);
+      anc[i] = p == NONE ? (i | DONE) : p;
+      dist[i] = p == NONE ? 0 : 1;
+      open = p != NONE;
+    }
+  }
+  wave_add(n_open, open);
+}
+
+// One round of pointer jumping from (a0, d0) into (a1, d1).
+__global__ void k_ut_jump(uint64_t m, const uint64_t* __restrict__ a0, const uint64_t* __restrict__ d0,
+                          uint64_t* __restrict__ a1, uint64_t* __restrict__ d1,
+                          unsigned long long* __restrict__ n_open) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t open = 0;
+  if (i < m) {
+    const uint64_t x = a0[i];
+    if (x == NONE || (x & DONE)) {
+      a1[i] = x;
+      d1[i] = d0[i];
+    } else {
+      const uint64_t y = a0[x];
+      a1[i] = y;
+      d1[i] = d0[i] + d0[x];
+      open = !(y & DONE);
+    }
+  }
+  wave_add(n_open, open);
+}
+
+// Unresolved rows (on cycles): link = predecessor, mn = the row itself.
+__global__ void k_cyc_init(Nav v, const uint64_t* __restrict__ valid, const uint64_t* __restrict__ anc,
+                           uint64_t* __restrict__ link, uint64_t* __restrict__ mn) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= v.m) return;
+  const uint64_t x = anc[i];
+  if (x == NONE || (x & DONE)) {
+    link[i] = NONE;
+    return;
+  }
+  link[i] = unitig_pred(v, valid, i);
+  mn[i] = i;
+}
+
+// mn1 = min over the 2^(r+1) rows ending at i along the cycle.
+__global__ void k_cyc_min(uint64_t m, const uint64_t* __restrict__ l0, const uint64_t* __restrict__ mn0,
+                          uint64_t* __restrict__ l1, uint64_t* __restrict__ mn1) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t x = l0[i];
+  if (x == NONE) {
+    l1[i] = NONE;
+    return;
+  }
+  const uint64_t a = mn0[i], b = mn0[x];
+  mn1[i] = a < b ? a : b;
+  l1[i] = l0[x];
+}
+
+// Each cycle's smallest row becomes its first edge; the others link to
+// their predecessors again.
+__global__ void k_cyc_open(uint64_t m, const uint64_t* __restrict__ link, const uint64_t* __restrict__ mn,
+                           const Nav v, const uint64_t* __restrict__ valid, uint64_t* __restrict__ anc,
+                           uint64_t* __restrict__ dist, unsigned long long* __restrict__ n_cycles) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t opened = 0;
+  if (i < m && link[i] != NONE) {
+    if (mn[i] == i) {
+      anc[i] = i | DONE;
+      dist[i] = 0;
+      opened = 1;
+    } else {
+      anc[i] = unitig_pred(v, valid, i);
+      dist[i] = 1;
+    }
+  }
+  wave_add(n_cycles, opened);
+}
+
+// First edges per 64-row word (one wave per word): bits and counts.
+__global__ void k_ut_heads(uint64_t m, const uint64_t* __restrict__ anc, uint64_t* __restrict__ hb,
+                           uint64_t* __restrict__ hc) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const bool h = i < m && anc[i] == (i | DONE);
+  const uint64_t b = __ballot(h);
+  if ((threadIdx.x & 63) == 0 && i < m) {
+    hb[i >> 6] = b;
+    hc[i >> 6] = __popcll(b);
+  }
+}
+
+DEV uint64_t head_rank(const uint64_t* hb, const uint64_t* hcum, uint64_t h) {
+  const uint64_t w = h >> 6, r = h & 63;
+  return hcum[w] + (r ? (uint64_t)__popcll(hb[w] & ((1ull << r) - 1)) : 0);
+}
+
+// Per valid row: its unitig's first row, length (max distance + 1) and
+// multiplicity (sum of mult).
+__global__ void k_ut_sums(uint64_t m, const uint64_t* __restrict__ anc, const uint64_t* __restrict__ dist,
+                          const uint32_t* __restrict__ mult, const uint64_t* __restrict__ hb,
+                          const uint64_t* __restrict__ hcum, uint64_t* __restrict__ first,
+                          unsigned long long* __restrict__ len, unsigned long long* __restrict__ msum) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t x = anc[i];
+  if (x == NONE) return;
+  const uint64_t h = x & ~DONE;
+  const uint64_t u = head_rank(hb, hcum, h);
+  if (h == i) first[u] = i;
+  atomicMax(len + u, (unsigned long long)(dist[i] + 1));
+  atomicAdd(msum + u, (unsigned long long)mult[i]);
+}
+
+// offsets[u] += k * u (offsets hold the exclusive scan of the lengths).
+__global__ void k_ut_offsets(uint64_t n, uint32_t k, uint64_t* __restrict__ off) {
+  const uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (u <= n) off[u] += (uint64_t)k * u;
+}
+
+// Base k + dist of a unitig is the label of its edge at that distance.
+__global__ void k_ut_edge_bases(uint64_t m, uint32_t k, const uint8_t* __restrict__ W,
+                                const uint64_t* __restrict__ anc, const uint64_t* __restrict__ dist,
+                                const uint64_t* __restrict__ hb, const uint64_t* __restrict__ hcum,
+                                const uint64_t* __restrict__ off, uint8_t* __restrict__ seq) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t x = anc[i];
+  if (x == NONE) return;
+  const uint64_t u = head_rank(hb, hcum, x & ~DONE);
+  seq[off[u] + k + dist[i]] = "ACGT"[(W[i] & 7) - 1];
+}
+
+// The first k bases of a unitig: the k-mer of its first edge's source node.
+__global__ void k_ut_node_bases(Nav v, uint64_t n, const uint64_t* __restrict__ first,
+                                const uint64_t* __restrict__ off, uint8_t* __restrict__ seq) {
+  const uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  uint8_t* out = seq + off[u];
+  node_kmer(v, node_of(v, first[u]), [&](int pos, uint64_t b) { out[pos] = "ACGT"[b]; });
+}
+
 }  // namespace
 
 // The index borrows the graph's arrays and owns its counts.
@@ -374,6 +601,16 @@ void free_index(void* p) {
   pool_free(ix->counts);
   pool_free(ix->sel);
   delete ix;
+}
+
+void free_unitigs(void* p) {
+  auto* u = static_cast<sdbg_unitigs*>(p);
+  pool_free(u->first_row);
+  pool_free(u->len);
+  pool_free(u->mult);
+  pool_free(u->offsets);
+  pool_free(u->seq);
+  delete u;
 }
 }  // namespace sdbg_abi
 
@@ -479,6 +716,133 @@ int sdbg_remove_tips(sdbg_graph* g, const sdbg_index* index, uint32_t max_len, u
     unsigned long long h = 0;
     c.d2h(&h, cnt.get(), 1);
     if (n_removed) *n_removed = h;
+    return SDBG_OK;
+  });
+}
+
+int sdbg_unitigs_build(const sdbg_graph* g, const sdbg_index* index, sdbg_unitigs** out, void* stream) {
+  using namespace sdbg;
+  return sdbg_abi::guarded([&]() -> int {
+    SDBG_CHECK(g && index && out, SDBG_E_INVAL, "null argument");
+    *out = nullptr;
+    SDBG_CHECK(sdbg_abi::reg_kind(g) == sdbg_abi::kGraph, SDBG_E_INVAL, "not a graph returned by this library");
+    SDBG_CHECK(sdbg_abi::reg_kind(index) == sdbg_abi::kIndex, SDBG_E_INVAL, "not an index returned by this library");
+    const NavIndex* ix = reinterpret_cast<const NavIndex*>(index);
+    SDBG_CHECK(ix->v.W == g->W && ix->v.m == g->m, SDBG_E_INVAL, "the index was not built on this graph");
+    const Nav& v = ix->v;
+    const uint64_t m = g->m, nw = ceil_div(m, 64);
+    SDBG_CHECK(ceil_div(m, SDBG_BLOCK) < (1ull << 31), SDBG_E_INVAL, "graph too large");
+    Ctx c(stream);
+    const unsigned grid = (unsigned)ceil_div(m ? m : 1, SDBG_BLOCK);
+    DBuf<uint64_t> a0 = c.buf<uint64_t>(m), a1 = c.buf<uint64_t>(m), d0 = c.buf<uint64_t>(m),
+                   d1 = c.buf<uint64_t>(m);
+    uint64_t* A[2] = {a0.get(), a1.get()};
+    uint64_t* D[2] = {d0.get(), d1.get()};
+    DBuf<unsigned long long> cnt = c.buf<unsigned long long>(2);  // open rows, cycles
+    uint64_t* cnt64 = reinterpret_cast<uint64_t*>(cnt.get());
+    fill<uint64_t>(cnt64, 2, 0, c);
+    int cur = 0;
+    uint64_t open = 0, n_cycles = 0;
+    if (m) {
+      k_ut_init<<<grid, SDBG_BLOCK, 0, c.s>>>(v, g->valid, A[0], D[0], cnt.get());
+      c.check_launch("unitig links");
+      open = c.d2h_one(cnt64);
+    }
+    // jumping rounds until every row is resolved or a round resolves none
+    auto jump = [&]() {
+      while (open) {
+        fill<uint64_t>(cnt64, 1, 0, c);
+        k_ut_jump<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], D[cur], A[cur ^ 1], D[cur ^ 1], cnt.get());
+        c.check_launch("unitig jump");
+        cur ^= 1;
+        const uint64_t now = c.d2h_one(cnt64);
+        if (now == open) break;
+        open = now;
+      }
+    };
+    jump();
+    if (open) {  // the open rows lie on cycles: open each at its smallest row
+      DBuf<uint64_t> l0 = c.buf<uint64_t>(m), l1 = c.buf<uint64_t>(m), n0 = c.buf<uint64_t>(m),
+                     n1 = c.buf<uint64_t>(m);
+      uint64_t* L[2] = {l0.get(), l1.get()};
+      uint64_t* N[2] = {n0.get(), n1.get()};
+      k_cyc_init<<<grid, SDBG_BLOCK, 0, c.s>>>(v, g->valid, A[cur], L[0], N[0]);
+      c.check_launch("cycle links");
+      int cc = 0;
+      for (uint64_t span = 1; span < open; span <<= 1, cc ^= 1) {
+        k_cyc_min<<<grid, SDBG_BLOCK, 0, c.s>>>(m, L[cc], N[cc], L[cc ^ 1], N[cc ^ 1]);
+        c.check_launch("cycle minimum");
+      }
+      // the jumped links still mark the cycle rows (they never reach NONE)
+      k_cyc_open<<<grid, SDBG_BLOCK, 0, c.s>>>(m, L[cc], N[cc], v, g->valid, A[cur], D[cur], cnt.get() + 1);
+      c.check_launch("cycle open");
+      n_cycles = c.d2h_one(cnt64 + 1);
+      open -= n_cycles;
+      jump();
+      SDBG_CHECK(open == 0, SDBG_E_HIP, "unitig ranking did not converge");
+    }
+    // first edges, ranked in row order
+    DBuf<uint64_t> hb = c.buf<uint64_t>(nw ? nw : 1), hcum = c.buf<uint64_t>(nw + 1);
+    if (nw) {
+      k_ut_heads<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], hb.get(), hcum.get());
+      c.check_launch("unitig heads");
+    }
+    scan_excl<uint64_t, uint64_t>(hcum.get(), hcum.get(), nw, hcum.get() + nw, c);
+    const uint64_t n = c.d2h_one(hcum.get() + nw);
+    DBuf<uint64_t> first = c.buf<uint64_t>(n ? n : 1), len = c.buf<uint64_t>(n ? n : 1),
+                   msum = c.buf<uint64_t>(n ? n : 1), off = c.buf<uint64_t>(n + 1);
+    fill<uint64_t>(len.get(), n, 0, c);
+    fill<uint64_t>(msum.get(), n, 0, c);
+    if (m) {
+      k_ut_sums<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], D[cur], g->mult, hb.get(), hcum.get(), first.get(),
+                                              reinterpret_cast<unsigned long long*>(len.get()),
+                                              reinterpret_cast<unsigned long long*>(msum.get()));
+      c.check_launch("unitig sums");
+    }
+    scan_excl<uint64_t, uint64_t>(len.get(), off.get(), n, off.get() + n, c);
+    k_ut_offsets<<<(unsigned)ceil_div(n + 1, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(n, g->k, off.get());
+    c.check_launch("unitig offsets");
+    const uint64_t n_bases = c.d2h_one(off.get() + n);
+    DBuf<uint8_t> seq = c.buf<uint8_t>(n_bases ? n_bases : 1);
+    if (m) {
+      k_ut_edge_bases<<<grid, SDBG_BLOCK, 0, c.s>>>(m, g->k, g->W, A[cur], D[cur], hb.get(), hcum.get(),
+                                                    off.get(), seq.get());
+      c.check_launch("unitig edge bases");
+    }
+    if (n) {
+      k_ut_node_bases<<<(unsigned)ceil_div(n, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(v, n, first.get(), off.get(),
+                                                                                seq.get());
+      c.check_launch("unitig node bases");
+    }
+    c.sync();
+    auto* u = new sdbg_unitigs();
+    u->k = g->k;
+    u->n = n;
+    u->n_cycles = n_cycles;
+    u->n_bases = n_bases;
+    u->first_row = first.release_ownership();
+    u->len = len.release_ownership();
+    u->mult = msum.release_ownership();
+    u->offsets = off.release_ownership();
+    u->seq = seq.release_ownership();
+    sdbg_abi::reg_add(u, sdbg_abi::kUnitigs);
+    *out = u;
+    return SDBG_OK;
+  });
+}
+
+int sdbg_unitigs_to_host(const sdbg_unitigs* u, uint64_t* first_row, uint64_t* len, uint64_t* mult,
+                         uint64_t* offsets, uint8_t* seq) {
+  using namespace sdbg;
+  return sdbg_abi::guarded([&]() -> int {
+    SDBG_CHECK(u && sdbg_abi::reg_kind(u) == sdbg_abi::kUnitigs, SDBG_E_INVAL,
+               "not a unitig set returned by this library");
+    Ctx c(nullptr);
+    if (first_row) c.d2h(first_row, u->first_row, u->n);
+    if (len) c.d2h(len, u->len, u->n);
+    if (mult) c.d2h(mult, u->mult, u->n);
+    if (offsets) c.d2h(offsets, u->offsets, u->n + 1);
+    if (seq) c.d2h(seq, u->seq, u->n_bases);
     return SDBG_OK;
   });
 }

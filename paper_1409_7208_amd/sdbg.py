@@ -78,6 +78,21 @@ class _Graph(ctypes.Structure):
     ]
 
 
+class _Unitigs(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("n", ctypes.c_uint64),
+        ("n_cycles", ctypes.c_uint64),
+        ("n_bases", ctypes.c_uint64),
+        ("first_row", ctypes.c_void_p),
+        ("len", ctypes.c_void_p),
+        ("mult", ctypes.c_void_p),
+        ("offsets", ctypes.c_void_p),
+        ("seq", ctypes.c_void_p),
+    ]
+
+
 _lib = None
 
 
@@ -255,9 +270,22 @@ class Graph:
             pass
 
 
+@dataclasses.dataclass
+class DeviceReads:
+    """A read set already in device memory, given by raw pointers (e.g. the
+    unitigs of a graph); `owner` keeps the memory alive."""
+
+    seq_ptr: int | None
+    offsets_ptr: int
+    n_reads: int
+    owner: object = None
+
+
 def _reads_struct(seq, offsets):
     """torch device tensors -> device pointers; numpy -> host pointers."""
     keep = []
+    if isinstance(seq, DeviceReads):
+        return _Reads(seq.seq_ptr, seq.offsets_ptr, seq.n_reads, 1, 0), [seq]
     if hasattr(seq, "data_ptr"):
         assert seq.is_cuda and offsets.is_cuda, "torch inputs must be device tensors"
         assert seq.dtype.itemsize == 1 and offsets.dtype.itemsize == 8
@@ -363,10 +391,78 @@ class Index:
         _check(lib.sdbg_remove_tips(self._graph._p, self._h, max_len, ctypes.byref(n), _stream_ptr(stream)))
         return n.value
 
+    def unitigs(self, stream=None) -> "Unitigs":
+        """Unitigs of the indexed graph's valid edges (sdbg_unitigs_build)."""
+        lib = load()
+        if not getattr(lib, "_unitig_api", False):
+            P = ctypes.POINTER
+            lib.sdbg_unitigs_build.argtypes = [P(_Graph), ctypes.c_void_p, P(P(_Unitigs)), ctypes.c_void_p]
+            lib.sdbg_unitigs_build.restype = ctypes.c_int
+            lib.sdbg_unitigs_to_host.argtypes = [P(_Unitigs)] + [ctypes.c_void_p] * 5
+            lib.sdbg_unitigs_to_host.restype = ctypes.c_int
+            lib._unitig_api = True
+        out = ctypes.POINTER(_Unitigs)()
+        _check(lib.sdbg_unitigs_build(self._graph._p, self._h, ctypes.byref(out), _stream_ptr(stream)))
+        return Unitigs(out)
+
     def close(self):
         if self._h:
             load().sdbg_free(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class HostUnitigs:
+    k: int
+    n_cycles: int
+    first_row: np.ndarray
+    len: np.ndarray
+    mult: np.ndarray
+    offsets: np.ndarray
+    seq: np.ndarray  # bytes 'A', 'C', 'G', 'T'
+
+    def sequence(self, u: int) -> str:
+        return self.seq[self.offsets[u] : self.offsets[u + 1]].tobytes().decode()
+
+
+class Unitigs:
+    """Unitigs of a graph in device memory (owned)."""
+
+    def __init__(self, ptr):
+        self._p = ptr
+
+    @property
+    def raw(self) -> _Unitigs:
+        return self._p.contents
+
+    n = property(lambda s: s.raw.n)
+    n_cycles = property(lambda s: s.raw.n_cycles)
+    n_bases = property(lambda s: s.raw.n_bases)
+
+    def to_host(self) -> HostUnitigs:
+        r = self.raw
+        a = [np.zeros(r.n + 1, dtype=np.uint64) for _ in range(3)]
+        off = np.zeros(r.n + 1, dtype=np.uint64)
+        seq = np.zeros(r.n_bases + 1, dtype=np.uint8)
+        _check(load().sdbg_unitigs_to_host(self._p, a[0].ctypes.data, a[1].ctypes.data, a[2].ctypes.data,
+                                           off.ctypes.data, seq.ctypes.data))
+        return HostUnitigs(r.k, r.n_cycles, a[0][: r.n], a[1][: r.n], a[2][: r.n], off, seq[: r.n_bases])
+
+    def as_reads(self) -> DeviceReads:
+        """The unitigs as a device read set (for counting at another k)."""
+        r = self.raw
+        return DeviceReads(r.seq if r.n_bases else None, r.offsets, r.n, self)
+
+    def close(self):
+        if self._p:
+            load().sdbg_free(ctypes.cast(self._p, ctypes.c_void_p))
+            self._p = None
 
     def __del__(self):
         try:
