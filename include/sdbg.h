@@ -384,6 +384,33 @@ int sdbg_unitigs_build(const sdbg_graph *g, const sdbg_index *index, sdbg_unitig
 int sdbg_unitigs_to_host(const sdbg_unitigs *u, uint64_t *first_row, uint64_t *len, uint64_t *mult,
                          uint64_t *offsets, uint8_t *seq);
 
+/* Union of two edge sets of the same k (e.g. the solid edges of the reads
+ * and the edges of contigs): every key of either, ascending, with the two
+ * counts summed where a key is in both (SDBG_E_INVAL if a sum does not fit
+ * 32 bits).  n_mercy of the result is 0 and n_occ the sum of the two.
+ * Runs on params->stream (params may be NULL). */
+int sdbg_edges_union(const sdbg_edges *a, const sdbg_edges *b, const sdbg_params *params, sdbg_edges **out);
+
+/* Multiple k with contig feedback (Section 2, fourth paragraph, and Fig. 1:
+ * graphs are built from a small k to a large one, each is cleaned, and the
+ * contigs of one k go into the graph of the next; the reading implemented):
+ * for each k of ks (n_k values, ascending, each in [2, 127]):
+ *   1. E = solid edges of the reads (sdbg_count_solid with params' d, mercy,
+ *      prefix_len and mem_budget);
+ *   2. from the second k on, E = E united with every (k+1)-mer of the
+ *      previous k's unitigs, on both strands, with its count of occurrences
+ *      in them (sdbg_count_solid of the unitigs with d = 1, no mercy, then
+ *      sdbg_edges_union);
+ *   3. the graph of E is built, tips of at most tip_factor * k edges are
+ *      removed (sdbg_remove_tips; 0 keeps every edge) and the unitigs of the
+ *      valid edges are taken (sdbg_unitigs_build).
+ * *out = the unitigs of the last k (release with sdbg_free).  stats (may be
+ * NULL; 4 * n_k words): per k, the edges of E, the edges the unitigs added,
+ * the tip edges removed and the unitigs.  Every intermediate object is
+ * released before the call returns. */
+int sdbg_multi_k(const sdbg_reads *reads, const uint32_t *ks, uint32_t n_k, const sdbg_params *params,
+                 uint32_t tip_factor, uint64_t *stats, sdbg_unitigs **out);
+
 /* Wraps host arrays (n*w key words ascending and unique, n counts) into a
  * library-owned device edge set, e.g. to build a graph from edges computed
  * elsewhere. */

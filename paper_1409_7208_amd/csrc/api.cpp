@@ -283,6 +283,103 @@ int sdbg_build(const sdbg_edges* edges, const sdbg_params* params, sdbg_graph** 
   });
 }
 
+int sdbg_edges_union(const sdbg_edges* a, const sdbg_edges* b, const sdbg_params* params, sdbg_edges** out) {
+  return guarded([&]() -> int {
+    SDBG_CHECK(a && b && out, SDBG_E_INVAL, "null argument");
+    *out = nullptr;
+    SDBG_CHECK(reg_kind(a) == kEdges && reg_kind(b) == kEdges, SDBG_E_INVAL,
+               "not an edge set returned by this library");
+    SDBG_CHECK(a->k == b->k, SDBG_E_INVAL, "edge sets of different k");
+    sdbg::Ctx c(params ? params->stream : nullptr);
+    sdbg::EdgesOut eo;
+    sdbg::edges_union(a->keys, a->count, a->n, b->keys, b->count, b->n, (int)a->k, c, &eo);
+    c.sync();
+    sdbg::prof_flush();
+    eo.n_mercy = 0;
+    eo.n_occ = a->n_occ + b->n_occ;
+    *out = wrap_edges(eo, a->k);
+    return SDBG_OK;
+  });
+}
+
+int sdbg_multi_k(const sdbg_reads* reads, const uint32_t* ks, uint32_t n_k, const sdbg_params* params,
+                 uint32_t tip_factor, uint64_t* stats, sdbg_unitigs** out) {
+  // Objects of the iteration in flight, released on every exit.
+  struct Held {
+    void* p[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    ~Held() {
+      for (void* x : p) sdbg_free(x);
+    }
+  } h;
+  enum { kReadEdges, kContigEdges, kEdgesAll, kGraphI, kIndexI, kPrev };
+  const int rc = guarded([&]() -> int {
+    SDBG_CHECK(reads && ks && params && out && n_k > 0, SDBG_E_INVAL, "null argument");
+    *out = nullptr;
+    for (uint32_t i = 0; i < n_k; ++i) {
+      check_k(ks[i]);
+      SDBG_CHECK(i == 0 || ks[i] > ks[i - 1], SDBG_E_INVAL, "k values must ascend");
+    }
+    return SDBG_OK;
+  });
+  if (rc != SDBG_OK) return rc;
+  for (uint32_t i = 0; i < n_k; ++i) {
+    sdbg_params p = *params;
+    p.k = ks[i];
+    int r = sdbg_count_solid(reads, &p, reinterpret_cast<sdbg_edges**>(&h.p[kReadEdges]));
+    if (r != SDBG_OK) return r;
+    auto* re = static_cast<sdbg_edges*>(h.p[kReadEdges]);
+    const uint64_t n_read_edges = re->n;
+    auto* prev = static_cast<sdbg_unitigs*>(h.p[kPrev]);
+    if (prev && prev->n) {  // the contigs of the previous k: all their (k+1)-mers
+      sdbg_reads cr{prev->seq, prev->offsets, prev->n, 1, 0};
+      sdbg_params pc = p;
+      pc.d = 1;
+      pc.mercy = 0;
+      r = sdbg_count_solid(&cr, &pc, reinterpret_cast<sdbg_edges**>(&h.p[kContigEdges]));
+      if (r != SDBG_OK) return r;
+      r = sdbg_edges_union(re, static_cast<sdbg_edges*>(h.p[kContigEdges]), &p,
+                           reinterpret_cast<sdbg_edges**>(&h.p[kEdgesAll]));
+      if (r != SDBG_OK) return r;
+      sdbg_free(h.p[kReadEdges]);
+      sdbg_free(h.p[kContigEdges]);
+      h.p[kReadEdges] = h.p[kContigEdges] = nullptr;
+    } else {
+      h.p[kEdgesAll] = h.p[kReadEdges];
+      h.p[kReadEdges] = nullptr;
+    }
+    auto* e = static_cast<sdbg_edges*>(h.p[kEdgesAll]);
+    const uint64_t n_edges = e->n;
+    r = sdbg_build(e, &p, reinterpret_cast<sdbg_graph**>(&h.p[kGraphI]));
+    if (r != SDBG_OK) return r;
+    sdbg_free(h.p[kEdgesAll]);
+    h.p[kEdgesAll] = nullptr;
+    auto* g = static_cast<sdbg_graph*>(h.p[kGraphI]);
+    r = sdbg_index_build(g, &p, reinterpret_cast<sdbg_index**>(&h.p[kIndexI]));
+    if (r != SDBG_OK) return r;
+    auto* ix = static_cast<sdbg_index*>(h.p[kIndexI]);
+    uint64_t n_tips = 0;
+    r = sdbg_remove_tips(g, ix, tip_factor * ks[i], &n_tips, p.stream);
+    if (r != SDBG_OK) return r;
+    sdbg_unitigs* u = nullptr;
+    r = sdbg_unitigs_build(g, ix, &u, p.stream);
+    if (r != SDBG_OK) return r;
+    sdbg_free(h.p[kIndexI]);
+    sdbg_free(h.p[kGraphI]);
+    sdbg_free(h.p[kPrev]);
+    h.p[kIndexI] = h.p[kGraphI] = nullptr;
+    h.p[kPrev] = u;
+    if (stats) {
+      stats[4 * i + 0] = n_edges;
+      stats[4 * i + 1] = n_edges - n_read_edges;
+      stats[4 * i + 2] = n_tips;
+      stats[4 * i + 3] = u->n;
+    }
+  }
+  *out = static_cast<sdbg_unitigs*>(h.p[kPrev]);
+  h.p[kPrev] = nullptr;
+  return SDBG_OK;
+}
+
 // Graph builders of a batch: a few host threads, each on a stream of its
 // own, build the sets' graphs once every pass has counted, so that one
 // set's size read-backs overlap the other sets' kernels.  (Building next to

@@ -1375,8 +1375,8 @@ __global__ void k_rc_unpack(const uint64_t* __restrict__ R2, uint64_t n, uint64_
   key_store<W>(keys + i * W, out);
 }
 
-// Merge of two disjoint sorted key sets (with their counts) along the merge
-// path: output tile t covers positions [t*T, (t+1)*T); the split of each
+// Merge of two sorted key sets (with their counts) along the merge path
+// (equal keys, if any, come out next to each other, B's first): output tile t covers positions [t*T, (t+1)*T); the split of each
 // tile boundary between A and B is found by one binary search on the
 // cross diagonal, then a workgroup stages its A and B runs in LDS, each
 // thread merges a stretch of the tile's output along the same path, and the
@@ -1422,7 +1422,7 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_merge_tile(const uint64_t* __res
   lds_barrier();
   // each thread merges PT consecutive outputs of the tile into registers:
   // its start on the merge path by one search along its diagonal, then a
-  // sequential merge (the sets are disjoint, so there are no ties) ...
+  // sequential merge (on equal keys B's goes first, as in the split) ...
   static_assert(T % SDBG_BLOCK == 0, "whole outputs per thread");
   constexpr int PT = T / SDBG_BLOCK;
   const int n = nA + nB;
@@ -1463,6 +1463,35 @@ __global__ __launch_bounds__(SDBG_BLOCK) void k_merge_tile(const uint64_t* __res
     key_store_g<W>(E + (d0 + i) * W, key_load<W>(&la[i * W]));
     Ec[d0 + i] = lc[i];
   }
+}
+
+// Union of two edge sets (each ascending and unique): the merge along the
+// merge path above keeps equal keys next to each other (B's first), so
+// each key of the union starts a run of one or two; the first of a run
+// takes the run's summed count.
+template <int W>
+__global__ void k_union_heads(const uint64_t* __restrict__ E, uint64_t n, uint32_t* __restrict__ head) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  head[i] = i == 0 || !key_eq<W>(key_load<W>(E + (i - 1) * W), key_load<W>(E + i * W)) ? 1u : 0u;
+}
+
+template <int W>
+__global__ void k_union_scatter(const uint64_t* __restrict__ E, const uint32_t* __restrict__ Ec, uint64_t n,
+                                const uint64_t* __restrict__ pos, uint64_t* __restrict__ O, uint32_t* __restrict__ Oc,
+                                uint32_t* __restrict__ overflow) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Key<W> x = key_load<W>(E + i * W);
+  if (i > 0 && key_eq<W>(key_load<W>(E + (i - 1) * W), x)) return;
+  uint64_t sum = Ec[i];
+  if (i + 1 < n && key_eq<W>(key_load<W>(E + (i + 1) * W), x)) sum += Ec[i + 1];
+  if (sum > 0xFFFFFFFFull) {
+    atomicOr(overflow, 1u);
+    sum = 0xFFFFFFFFull;
+  }
+  key_store_g<W>(O + pos[i] * W, x);
+  Oc[pos[i]] = (uint32_t)sum;
 }
 
 }  // namespace sdbg
@@ -1866,7 +1895,7 @@ struct Counter {
     c.sync();
   }
 
-  // Merge of two disjoint sorted key sets with their counts.
+  // Merge of two sorted key sets with their counts.
   void merge_sets(const char* name, const uint64_t* A, const uint32_t* Ac, uint64_t nA, const uint64_t* B,
                   const uint32_t* Bc, uint64_t nB, DBuf<uint64_t>& E, DBuf<uint32_t>& Ec) {
     E = c.buf<uint64_t>((nA + nB) * W);
@@ -2468,6 +2497,56 @@ void count_solid_sets(const DevReads& r, const std::vector<uint64_t>& rb, const 
     case 2: Counter<2>(c).run_sets(r, rb, p, outs); break;
     case 3: Counter<3>(c).run_sets(r, rb, p, outs); break;
     case 4: Counter<4>(c).run_sets(r, rb, p, outs); break;
+    default: throw Error(-1, "k out of range");
+  }
+}
+
+template <int W>
+void edges_union_w(const uint64_t* A, const uint32_t* Ac, uint64_t nA, const uint64_t* B, const uint32_t* Bc,
+                   uint64_t nB, Ctx& c, EdgesOut* out) {
+  const uint64_t n = nA + nB;
+  if (n == 0) {
+    DBuf<uint64_t> O = c.buf<uint64_t>(W);
+    DBuf<uint32_t> Oc = c.buf<uint32_t>(1);
+    out->keys = O.release_ownership();
+    out->count = Oc.release_ownership();
+    out->n = 0;
+    return;
+  }
+  Counter<W> ct(c);
+  DBuf<uint64_t> E;
+  DBuf<uint32_t> Ec;
+  ct.merge_sets("union_merge", A, Ac, nA, B, Bc, nB, E, Ec);
+  DBuf<uint32_t> head = c.buf<uint32_t>(n);
+  DBuf<uint64_t> pos = c.buf<uint64_t>(n + 1);
+  DBuf<uint32_t> ovf = c.buf<uint32_t>(1);
+  fill<uint32_t>(ovf.get(), 1, 0u, c);
+  {
+    k_union_heads<W><<<(unsigned)ceil_div(n, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(E.get(), n, head.get());
+    c.check_launch("union heads");
+  }
+  scan_excl<uint32_t, uint64_t>(head.get(), pos.get(), n, pos.get() + n, c);
+  const uint64_t nu = c.d2h_one(pos.get() + n);
+  DBuf<uint64_t> O = c.buf<uint64_t>((nu ? nu : 1) * W);
+  DBuf<uint32_t> Oc = c.buf<uint32_t>(nu ? nu : 1);
+  {
+    k_union_scatter<W><<<(unsigned)ceil_div(n, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(E.get(), Ec.get(), n, pos.get(),
+                                                                                O.get(), Oc.get(), ovf.get());
+    c.check_launch("union scatter");
+  }
+  SDBG_CHECK(c.d2h_one(ovf.get()) == 0, -1, "a summed count does not fit 32 bits");
+  out->keys = O.release_ownership();
+  out->count = Oc.release_ownership();
+  out->n = nu;
+}
+
+void edges_union(const uint64_t* A, const uint32_t* Ac, uint64_t nA, const uint64_t* B, const uint32_t* Bc,
+                 uint64_t nB, int k, Ctx& c, EdgesOut* out) {
+  switch (key_words(k)) {
+    case 1: edges_union_w<1>(A, Ac, nA, B, Bc, nB, c, out); break;
+    case 2: edges_union_w<2>(A, Ac, nA, B, Bc, nB, c, out); break;
+    case 3: edges_union_w<3>(A, Ac, nA, B, Bc, nB, c, out); break;
+    case 4: edges_union_w<4>(A, Ac, nA, B, Bc, nB, c, out); break;
     default: throw Error(-1, "k out of range");
   }
 }

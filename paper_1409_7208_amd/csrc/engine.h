@@ -92,6 +92,10 @@ void count_solid(const DevReads& r, const CountParams& p, Ctx& c, EdgesOut* out)
 // off; outs[s] equals count_solid of set s alone.
 void count_solid_sets(const DevReads& r, const std::vector<uint64_t>& rb, const CountParams& p, Ctx& c,
                       std::vector<EdgesOut>* outs);
+// Union of two edge sets of the same k (ascending, unique): keys of either,
+// counts summed (an error if a sum does not fit 32 bits).
+void edges_union(const uint64_t* A, const uint32_t* Ac, uint64_t nA, const uint64_t* B, const uint32_t* Bc,
+                 uint64_t nB, int k, Ctx& c, EdgesOut* out);
 // check = false skips the order check for edge sets the library computed.
 void build_graph(const uint64_t* keys, const uint32_t* count, uint64_t n, int k, Ctx& c, GraphOut* out,
                  bool check = true);

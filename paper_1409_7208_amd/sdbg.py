@@ -147,6 +147,20 @@ def load(path: str | None = None):
     return lib
 
 
+def _unitig_api():
+    """The library with the unitig calls' signatures declared (pointers
+    must not pass through ctypes' default int conversion)."""
+    lib = load()
+    if not getattr(lib, "_unitig_api", False):
+        P = ctypes.POINTER
+        lib.sdbg_unitigs_build.argtypes = [P(_Graph), ctypes.c_void_p, P(P(_Unitigs)), ctypes.c_void_p]
+        lib.sdbg_unitigs_build.restype = ctypes.c_int
+        lib.sdbg_unitigs_to_host.argtypes = [P(_Unitigs)] + [ctypes.c_void_p] * 5
+        lib.sdbg_unitigs_to_host.restype = ctypes.c_int
+        lib._unitig_api = True
+    return lib
+
+
 def _check(rc: int):
     if rc != SDBG_OK:
         raise SdbgError(rc, load().sdbg_last_error().decode(errors="replace"))
@@ -393,14 +407,7 @@ class Index:
 
     def unitigs(self, stream=None) -> "Unitigs":
         """Unitigs of the indexed graph's valid edges (sdbg_unitigs_build)."""
-        lib = load()
-        if not getattr(lib, "_unitig_api", False):
-            P = ctypes.POINTER
-            lib.sdbg_unitigs_build.argtypes = [P(_Graph), ctypes.c_void_p, P(P(_Unitigs)), ctypes.c_void_p]
-            lib.sdbg_unitigs_build.restype = ctypes.c_int
-            lib.sdbg_unitigs_to_host.argtypes = [P(_Unitigs)] + [ctypes.c_void_p] * 5
-            lib.sdbg_unitigs_to_host.restype = ctypes.c_int
-            lib._unitig_api = True
+        lib = _unitig_api()
         out = ctypes.POINTER(_Unitigs)()
         _check(lib.sdbg_unitigs_build(self._graph._p, self._h, ctypes.byref(out), _stream_ptr(stream)))
         return Unitigs(out)
@@ -450,7 +457,7 @@ class Unitigs:
         a = [np.zeros(r.n + 1, dtype=np.uint64) for _ in range(3)]
         off = np.zeros(r.n + 1, dtype=np.uint64)
         seq = np.zeros(r.n_bases + 1, dtype=np.uint8)
-        _check(load().sdbg_unitigs_to_host(self._p, a[0].ctypes.data, a[1].ctypes.data, a[2].ctypes.data,
+        _check(_unitig_api().sdbg_unitigs_to_host(self._p, a[0].ctypes.data, a[1].ctypes.data, a[2].ctypes.data,
                                            off.ctypes.data, seq.ctypes.data))
         return HostUnitigs(r.k, r.n_cycles, a[0][: r.n], a[1][: r.n], a[2][: r.n], off, seq[: r.n_bases])
 
@@ -469,6 +476,44 @@ class Unitigs:
             self.close()
         except Exception:
             pass
+
+
+def edges_union(a: Edges, b: Edges, stream=None) -> Edges:
+    """Keys of either edge set with summed counts (sdbg_edges_union)."""
+    lib = load()
+    if not getattr(lib, "_union_api", False):
+        P = ctypes.POINTER
+        lib.sdbg_edges_union.argtypes = [P(_Edges), P(_Edges), P(_Params), P(P(_Edges))]
+        lib.sdbg_edges_union.restype = ctypes.c_int
+        lib._union_api = True
+    p = _Params(a.k, 0, 0, 0, 0, _stream_ptr(stream))
+    out = ctypes.POINTER(_Edges)()
+    _check(lib.sdbg_edges_union(a._p, b._p, ctypes.byref(p), ctypes.byref(out)))
+    return Edges(out)
+
+
+def multi_k(seq, offsets, ks, d: int = 2, mercy: bool = True, tip_factor: int = 2, prefix_len: int = 8,
+            mem_budget: int = 0, stream=None) -> tuple[Unitigs, np.ndarray]:
+    """Graphs from the smallest k to the largest, each cleaned of tips, the
+    unitigs of one k counted into the next (sdbg_multi_k).  Returns the last
+    k's unitigs and per-k stats (edges, edges added by the unitigs, tip
+    edges removed, unitigs)."""
+    lib = load()
+    if not getattr(lib, "_multik_api", False):
+        P = ctypes.POINTER
+        lib.sdbg_multi_k.argtypes = [P(_Reads), ctypes.c_void_p, ctypes.c_uint32, P(_Params), ctypes.c_uint32,
+                                     ctypes.c_void_p, P(P(_Unitigs))]
+        lib.sdbg_multi_k.restype = ctypes.c_int
+        lib._multik_api = True
+    r, keep = _reads_struct(seq, offsets)
+    kk = np.ascontiguousarray(ks, dtype=np.uint32)
+    stats = np.zeros(4 * len(kk), dtype=np.uint64)
+    p = _Params(0, d, 1 if mercy else 0, prefix_len, mem_budget, _stream_ptr(stream))
+    out = ctypes.POINTER(_Unitigs)()
+    _check(lib.sdbg_multi_k(ctypes.byref(r), kk.ctypes.data, len(kk), ctypes.byref(p), tip_factor,
+                            stats.ctypes.data, ctypes.byref(out)))
+    del keep
+    return Unitigs(out), stats.reshape(len(kk), 4)
 
 
 def batch_run(sets, k: int, d: int = 2, mercy: bool = False, build: bool = True, prefix_len: int = 8,
