@@ -384,6 +384,33 @@ int sdbg_unitigs_build(const sdbg_graph *g, const sdbg_index *index, sdbg_unitig
 int sdbg_unitigs_to_host(const sdbg_unitigs *u, uint64_t *first_row, uint64_t *len, uint64_t *mult,
                          uint64_t *offsets, uint8_t *seq);
 
+/* Bubble merging and low-local-coverage removal (Section 2, fourth
+ * paragraph, lists them with tip removal as the cleaning of each graph and
+ * notes that the second suits the uneven depth of metagenomes; it defines
+ * neither, so these are the readings implemented).  u must be the unitigs
+ * of g's current valid edges (sdbg_unitigs_build after the last change to
+ * g->valid; a unitig whose path no longer matches is skipped); index must
+ * have been built on g.  Unitig u runs from s(u), the source node of its
+ * first edge, to t(u), the node its last edge enters; cycles and unitigs of
+ * more than max_len edges take part in neither call.
+ *   sdbg_merge_bubbles: unitigs sharing s and t form a group; in a group of
+ *     two or more, all but the one of highest mean multiplicity (mult / len,
+ *     compared exactly as mult(a) * len(b) against mult(b) * len(a); ties
+ *     to the smaller first row) are removed.
+ *   sdbg_remove_low_coverage: the neighbouring edges of u are the valid
+ *     edges other than its first and last that leave or enter s(u) or t(u);
+ *     u is removed if it has one and its mean multiplicity is below
+ *     ratio_permille / 1000 of theirs (exactly: mult(u) * count * 1000 <
+ *     ratio_permille * len(u) * sum of their mult).
+ * Every removal of a call is decided on g as given, then the valid bits of
+ * the removed unitigs' edges are cleared (in place, on `stream`; the call
+ * returns when it is done).  *n_removed (may be NULL) = valid bits cleared.
+ * Take the unitigs again before the next call. */
+int sdbg_merge_bubbles(sdbg_graph *g, const sdbg_index *index, const sdbg_unitigs *u, uint32_t max_len,
+                       uint64_t *n_removed, void *stream);
+int sdbg_remove_low_coverage(sdbg_graph *g, const sdbg_index *index, const sdbg_unitigs *u, uint32_t max_len,
+                             uint32_t ratio_permille, uint64_t *n_removed, void *stream);
+
 /* Union of two edge sets of the same k (e.g. the solid edges of the reads
  * and the edges of contigs): every key of either, ascending, with the two
  * counts summed where a key is in both (SDBG_E_INVAL if a sum does not fit

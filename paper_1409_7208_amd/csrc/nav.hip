@@ -584,6 +584,162 @@ __global__ void k_ut_node_bases(Nav v, uint64_t n, const uint64_t* __restrict__ 
   node_kmer(v, node_of(v, first[u]), [&](int pos, uint64_t b) { out[pos] = "ACGT"[b]; });
 }
 
+// Bubble merging and low-local-coverage removal (Section 2, fourth
+// paragraph, lists both among the cleaning steps, without definitions; the
+// readings implemented).  Both take the unitigs of the current valid edges;
+// unitig u runs from s(u), the source node of its first edge, to t(u), the
+// node its last edge enters; cycles take part in neither.
+//  * Bubbles: unitigs of at most max_len edges sharing s and t form a group;
+//    all but the one of highest mean multiplicity (mult(a) * len(b) against
+//    mult(b) * len(a); ties to the smaller first row) are removed.  The
+//    unitigs leaving a branching node are exactly its valid rows, so each
+//    unitig compares itself with the unitigs of its start node's other rows.
+//  * Low local coverage: the neighbouring edges of a unitig of at most
+//    max_len edges are the valid edges other than its first and last that
+//    leave or enter s or t; it is removed if there is one and
+//    mult * count * 1000 < ratio_permille * len * (sum of their mult).
+// One thread per unitig decides from the graph as given (a flag per
+// unitig); a second launch walks the flagged unitigs and clears their
+// valid bits, so every removal of a call is decided before any is made.
+
+// f(row) for each valid row leaving node x (its last row).
+template <typename F>
+DEV void for_valid_out(const Nav& v, const uint64_t* valid, uint64_t x, F f) {
+  const uint64_t p = prev_one(v.last, x);
+  for (uint64_t r = p == NONE ? 0 : p + 1; r <= x; ++r)
+    if (bit(valid, r)) f(r);
+}
+
+// f(row) for each valid row entering node x.
+template <typename F>
+DEV void for_valid_in(const Nav& v, const uint64_t* valid, uint64_t x, F f) {
+  if (bit(v.tip, x)) return;
+  const int c = block_of(v, x);
+  const uint64_t j = in_row(v, x, c);
+  if (bit(v.tip, j)) return;
+  if (bit(valid, j)) f(j);
+  for (uint64_t p = j + 1; p < v.m; ++p) {
+    const uint8_t w = v.W[p];
+    if (w == (uint8_t)c) break;
+    if (w == (uint8_t)(c | 8) && bit(valid, p)) f(p);
+  }
+}
+
+// Node entered by the last of the n edges of the unitig whose first row is
+// r (*last = that edge's row), or NONE if the valid edges do not form such
+// a path (a unitig set of another state of the graph).
+DEV uint64_t unitig_end(const Nav& v, const uint64_t* valid, uint64_t r, uint64_t n, uint64_t* last) {
+  for (uint64_t j = 1; j < n; ++j) {
+    const uint64_t x = nav_forward(v, r);
+    if (x == NONE) return NONE;
+    uint64_t o = NONE;
+    if (valid_out(v, valid, x, &o) != 1) return NONE;
+    r = o;
+  }
+  *last = r;
+  return nav_forward(v, r);
+}
+
+// Start node of unitig u if it may take part (at most max_len edges, first
+// row valid, not a cycle), else NONE.
+DEV uint64_t cleaning_start(const Nav& v, const uint64_t* valid, uint64_t r0, uint64_t len, uint32_t max_len) {
+  if (len == 0 || len > max_len || r0 >= v.m || !bit(valid, r0)) return NONE;
+  const uint64_t s = node_of(v, r0);
+  uint64_t o;
+  if (valid_in(v, valid, s, &o) == 1 && valid_out(v, valid, s, &o) == 1) return NONE;  // a cycle
+  return s;
+}
+
+// Index of the unitig whose first row is r (first[] ascending), or NONE.
+DEV uint64_t unitig_of_first(const uint64_t* first, uint64_t n, uint64_t r) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (first[mid] < r)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < n && first[lo] == r ? lo : NONE;
+}
+
+typedef unsigned __int128 u128;
+
+__global__ void k_bubble_flags(Nav v, const uint64_t* __restrict__ valid, const uint64_t* __restrict__ first,
+                               const uint64_t* __restrict__ len, const uint64_t* __restrict__ umult, uint64_t n,
+                               uint32_t max_len, uint8_t* __restrict__ flag) {
+  const uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  flag[u] = 0;
+  const uint64_t r0 = first[u], L = len[u];
+  const uint64_t s = cleaning_start(v, valid, r0, L, max_len);
+  if (s == NONE) return;
+  uint64_t last;
+  const uint64_t t = unitig_end(v, valid, r0, L, &last);
+  if (t == NONE) return;
+  bool beaten = false;
+  for_valid_out(v, valid, s, [&](uint64_t r) {
+    if (beaten || r == r0) return;
+    const uint64_t w = unitig_of_first(first, n, r);
+    if (w == NONE || len[w] > max_len) return;
+    uint64_t l2;
+    if (unitig_end(v, valid, r, len[w], &l2) != t) return;
+    const u128 a = (u128)umult[w] * L, b = (u128)umult[u] * len[w];
+    beaten = a > b || (a == b && r < r0);
+  });
+  flag[u] = beaten ? 1 : 0;
+}
+
+__global__ void k_low_cov_flags(Nav v, const uint64_t* __restrict__ valid, const uint32_t* __restrict__ mult,
+                                const uint64_t* __restrict__ first, const uint64_t* __restrict__ len,
+                                const uint64_t* __restrict__ umult, uint64_t n, uint32_t max_len,
+                                uint32_t ratio_permille, uint8_t* __restrict__ flag) {
+  const uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  flag[u] = 0;
+  const uint64_t r0 = first[u], L = len[u];
+  const uint64_t s = cleaning_start(v, valid, r0, L, max_len);
+  if (s == NONE) return;
+  uint64_t last;
+  const uint64_t t = unitig_end(v, valid, r0, L, &last);
+  if (t == NONE) return;
+  uint64_t sum = 0, cnt = 0;
+  auto add = [&](uint64_t r) {
+    if (r == r0 || r == last) return;
+    sum += mult[r];
+    ++cnt;
+  };
+  for_valid_out(v, valid, s, add);
+  for_valid_in(v, valid, s, add);
+  if (t != s) {
+    for_valid_out(v, valid, t, add);
+    for_valid_in(v, valid, t, add);
+  }
+  flag[u] = cnt && (u128)umult[u] * cnt * 1000 < (u128)ratio_permille * L * sum ? 1 : 0;
+}
+
+// Clears the valid bits of the flagged unitigs' edges.
+__global__ void k_clear_flagged(Nav v, uint64_t* __restrict__ valid, const uint64_t* __restrict__ first,
+                                const uint64_t* __restrict__ len, const uint8_t* __restrict__ flag, uint64_t n,
+                                unsigned long long* __restrict__ n_removed) {
+  const uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t cleared = 0;
+  if (u < n && flag[u]) {
+    uint64_t r = first[u];
+    for (uint64_t j = 0; j < len[u]; ++j) {
+      const unsigned long long m = 1ull << (r & 63);
+      const unsigned long long old = atomicAnd(reinterpret_cast<unsigned long long*>(valid + (r >> 6)), ~m);
+      cleared += (old & m) ? 1 : 0;
+      if (j + 1 == len[u]) break;
+      const uint64_t x = nav_forward(v, r);  // an inner node: its one valid row is the next edge
+      uint64_t o = NONE;
+      if (x == NONE || valid_out(v, valid, x, &o) != 1) break;
+      r = o;
+    }
+  }
+  wave_add(n_removed, cleared);
+}
+
 }  // namespace
 
 // The index borrows the graph's arrays and owns its counts.
@@ -845,6 +1001,58 @@ int sdbg_unitigs_to_host(const sdbg_unitigs* u, uint64_t* first_row, uint64_t* l
     if (seq) c.d2h(seq, u->seq, u->n_bases);
     return SDBG_OK;
   });
+}
+
+}  // extern "C"
+
+// Shared body of the two unitig-based cleaning calls.
+static int clean_by_unitigs(sdbg_graph* g, const sdbg_index* index, const sdbg_unitigs* u, uint32_t max_len,
+                            int low_cov, uint32_t ratio_permille, uint64_t* n_removed, void* stream) {
+  using namespace sdbg;
+  return sdbg_abi::guarded([&]() -> int {
+    SDBG_CHECK(g && index && u, SDBG_E_INVAL, "null argument");
+    SDBG_CHECK(sdbg_abi::reg_kind(g) == sdbg_abi::kGraph, SDBG_E_INVAL, "not a graph returned by this library");
+    SDBG_CHECK(sdbg_abi::reg_kind(index) == sdbg_abi::kIndex, SDBG_E_INVAL, "not an index returned by this library");
+    SDBG_CHECK(sdbg_abi::reg_kind(u) == sdbg_abi::kUnitigs, SDBG_E_INVAL,
+               "not a unitig set returned by this library");
+    const NavIndex* ix = reinterpret_cast<const NavIndex*>(index);
+    SDBG_CHECK(ix->v.W == g->W && ix->v.m == g->m, SDBG_E_INVAL, "the index was not built on this graph");
+    SDBG_CHECK(u->k == g->k, SDBG_E_INVAL, "unitigs of another k");
+    Ctx c(stream);
+    DBuf<unsigned long long> cnt = c.buf<unsigned long long>(1);
+    fill<uint64_t>(reinterpret_cast<uint64_t*>(cnt.get()), 1, 0, c);
+    if (u->n && max_len) {
+      SDBG_CHECK(ceil_div(u->n, SDBG_BLOCK) < (1ull << 31), SDBG_E_INVAL, "too many unitigs");
+      const unsigned grid = (unsigned)ceil_div(u->n, SDBG_BLOCK);
+      DBuf<uint8_t> flag = c.buf<uint8_t>(u->n);
+      if (low_cov)
+        k_low_cov_flags<<<grid, SDBG_BLOCK, 0, c.s>>>(ix->v, g->valid, g->mult, u->first_row, u->len, u->mult, u->n,
+                                                      max_len, ratio_permille, flag.get());
+      else
+        k_bubble_flags<<<grid, SDBG_BLOCK, 0, c.s>>>(ix->v, g->valid, u->first_row, u->len, u->mult, u->n, max_len,
+                                                     flag.get());
+      c.check_launch(low_cov ? "low coverage flags" : "bubble flags");
+      k_clear_flagged<<<grid, SDBG_BLOCK, 0, c.s>>>(ix->v, g->valid, u->first_row, u->len, flag.get(), u->n,
+                                                    cnt.get());
+      c.check_launch("clear flagged unitigs");
+    }
+    unsigned long long h = 0;
+    c.d2h(&h, cnt.get(), 1);
+    if (n_removed) *n_removed = h;
+    return SDBG_OK;
+  });
+}
+
+extern "C" {
+
+int sdbg_merge_bubbles(sdbg_graph* g, const sdbg_index* index, const sdbg_unitigs* u, uint32_t max_len,
+                       uint64_t* n_removed, void* stream) {
+  return clean_by_unitigs(g, index, u, max_len, 0, 0, n_removed, stream);
+}
+
+int sdbg_remove_low_coverage(sdbg_graph* g, const sdbg_index* index, const sdbg_unitigs* u, uint32_t max_len,
+                             uint32_t ratio_permille, uint64_t* n_removed, void* stream) {
+  return clean_by_unitigs(g, index, u, max_len, 1, ratio_permille, n_removed, stream);
 }
 
 }  // extern "C"

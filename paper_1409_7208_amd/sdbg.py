@@ -412,6 +412,39 @@ class Index:
         _check(lib.sdbg_unitigs_build(self._graph._p, self._h, ctypes.byref(out), _stream_ptr(stream)))
         return Unitigs(out)
 
+    def merge_bubbles(self, unitigs: "Unitigs", max_len: int, stream=None) -> int:
+        """Removes all but the best branch of every bubble of unitigs of at
+        most max_len edges (sdbg_merge_bubbles); returns the edges removed.
+        unitigs must be those of the graph's current valid edges."""
+        return self._clean(unitigs, max_len, None, stream)
+
+    def remove_low_coverage(self, unitigs: "Unitigs", max_len: int, ratio_permille: int, stream=None) -> int:
+        """Removes unitigs of at most max_len edges whose mean multiplicity
+        is below ratio_permille / 1000 of their neighbouring edges' mean
+        (sdbg_remove_low_coverage); returns the edges removed."""
+        return self._clean(unitigs, max_len, ratio_permille, stream)
+
+    def _clean(self, unitigs, max_len, ratio_permille, stream):
+        lib = _unitig_api()
+        if not getattr(lib, "_clean_api", False):
+            P = ctypes.POINTER
+            lib.sdbg_merge_bubbles.argtypes = [P(_Graph), ctypes.c_void_p, P(_Unitigs), ctypes.c_uint32,
+                                               P(ctypes.c_uint64), ctypes.c_void_p]
+            lib.sdbg_merge_bubbles.restype = ctypes.c_int
+            lib.sdbg_remove_low_coverage.argtypes = [P(_Graph), ctypes.c_void_p, P(_Unitigs), ctypes.c_uint32,
+                                                     ctypes.c_uint32, P(ctypes.c_uint64), ctypes.c_void_p]
+            lib.sdbg_remove_low_coverage.restype = ctypes.c_int
+            lib._clean_api = True
+        n = ctypes.c_uint64()
+        if ratio_permille is None:
+            rc = lib.sdbg_merge_bubbles(self._graph._p, self._h, unitigs._p, max_len, ctypes.byref(n),
+                                        _stream_ptr(stream))
+        else:
+            rc = lib.sdbg_remove_low_coverage(self._graph._p, self._h, unitigs._p, max_len, ratio_permille,
+                                              ctypes.byref(n), _stream_ptr(stream))
+        _check(rc)
+        return n.value
+
     def close(self):
         if self._h:
             load().sdbg_free(self._h)
