@@ -164,15 +164,38 @@ def large_k_rates(steps: int):
                      "gmer_s": round(gms, 3), "bytes_per_occ": round(step_bytes / r[0], 1),
                      "step_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
         log(f"large k={k}: {ms:.1f} ms/step, {gms:.2f} Gmer/s")
+    multi = multi_k_run(sdbg, torch, seq, off, stream)
     del seq, off
     torch.cuda.synchronize()
-    return rows
+    return rows, multi
+
+
+def multi_k_run(sdbg, torch, seq, off, stream, ks=(21, 41, 61, 81, 99)):
+    """One pass of the multi-k workflow over the large-k workload: per k the
+    reads' solid edges (mercy on) united with the previous k's unitigs,
+    graph, tips, bubbles and low-coverage unitigs of at most 2k edges
+    removed (ratio 0.2), unitigs (HIP events)."""
+    ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ea.record(stream)
+    u, st = sdbg.multi_k(seq, off, list(ks), d=2, mercy=True, tip_factor=2, bubble_factor=2, low_cov_factor=2,
+                         low_cov_permille=200, stream=stream)
+    eb.record(stream)
+    torch.cuda.synchronize()
+    ms = ea.elapsed_time(eb)
+    out = {"ks": list(ks), "ms": round(ms, 1), "unitigs": int(u.n), "bases": int(u.n_bases),
+           "clean": {"tip_factor": 2, "bubble_factor": 2, "low_cov_factor": 2, "low_cov_permille": 200},
+           "per_k": [{"k": k, "edges": int(a), "from_unitigs": int(b), "tip_edges": int(c), "bubble_edges": int(d),
+                      "low_cov_edges": int(e), "unitigs": int(f)} for k, (a, b, c, d, e, f) in zip(ks, st.tolist())]}
+    u.close()
+    log(f"multi-k {list(ks)}: {ms:.0f} ms, {out['unitigs']} unitigs at k={ks[-1]}; per k {st.tolist()}")
+    return out
 
 
 def navigation_rates(sdbg, torch, seq, off, rs, stream):
-    """Navigation index build, tip removal (paths of at most 2k edges) and
-    random forward queries on one graph of the workload, outside the timed
-    steps (HIP events on the call stream)."""
+    """Navigation index build, tip removal (paths of at most 2k edges),
+    unitigs of the cleaned graph and random forward queries on one graph of
+    the workload, outside the timed steps (HIP events on the call stream)."""
     e = sdbg.count_solid(seq, off, rs.k, rs.d, rs.mercy, stream=stream)
     g = sdbg.build(e, stream=stream)
     e.close()
@@ -184,6 +207,16 @@ def navigation_rates(sdbg, torch, seq, off, rs, stream):
     removed = ix.remove_tips(2 * rs.k, stream=stream)
     ec.record(stream)
     torch.cuda.synchronize()
+    eu0, eu1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    eu0.record(stream)
+    u = ix.unitigs(stream=stream)
+    eu1.record(stream)
+    torch.cuda.synchronize()
+    hl = u.to_host()
+    unitigs = {"unitigs_ms": round(eu0.elapsed_time(eu1), 3), "unitigs": int(u.n), "cycles": int(u.n_cycles),
+               "bases": int(u.n_bases), "longest_edges": int(hl.len.max()) if u.n else 0}
+    u.close()
+    del hl
     rows = torch.randint(0, int(g.raw.m), (1 << 24,), device="cuda:0", dtype=torch.int64)
     outq = torch.empty_like(rows)
     ed, ee = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -194,8 +227,9 @@ def navigation_rates(sdbg, torch, seq, off, rs, stream):
     torch.cuda.synchronize()
     clean = {"index_ms": round(ea.elapsed_time(eb), 3), "remove_tips_ms": round(eb.elapsed_time(ec), 3),
              "tip_max_len": 2 * rs.k, "tip_edges_removed": int(removed),
-             "forward_queries_per_s": round((1 << 24) / (ed.elapsed_time(ee) * 1e-3), 1)}
+             "forward_queries_per_s": round((1 << 24) / (ed.elapsed_time(ee) * 1e-3), 1), **unitigs}
     log(f"index {clean['index_ms']} ms, tip removal {clean['remove_tips_ms']} ms ({removed} edges), "
+        f"unitigs {unitigs['unitigs_ms']} ms ({unitigs['unitigs']}, longest {unitigs['longest_edges']} edges), "
         f"{clean['forward_queries_per_s'] / 1e9:.2f} G forward queries/s")
     ix.close()
     g.close()
@@ -574,10 +608,10 @@ def main():
     if not args.no_nav:
         clean = navigation_rates(sdbg, torch, seq, off, rs, stream)
 
-    large = None
+    large = multi = None
     if not args.no_large_k and args.workload == "metagenome" and args.scale == 1.0:
         del seq, off
-        large = large_k_rates(args.large_k_steps)
+        large, multi = large_k_rates(args.large_k_steps)
 
     cpu = None
     if not args.no_cpu:
@@ -610,6 +644,7 @@ def main():
         out["host_input_gmer_s"] = round(host_rate, 3)
     if large is not None:
         out["large_k"] = large
+        out["multi_k"] = multi
     if clean is not None:
         out["navigation"] = clean
     print(json.dumps(out), flush=True)

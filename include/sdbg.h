@@ -418,25 +418,38 @@ int sdbg_remove_low_coverage(sdbg_graph *g, const sdbg_index *index, const sdbg_
  * Runs on params->stream (params may be NULL). */
 int sdbg_edges_union(const sdbg_edges *a, const sdbg_edges *b, const sdbg_params *params, sdbg_edges **out);
 
+/* Cleaning of each graph of sdbg_multi_k: maximal lengths in edges as
+ * multiples of k (0 skips the step) and the low-coverage ratio. */
+typedef struct sdbg_clean_params {
+  uint32_t tip_factor;       /* tips of at most tip_factor * k edges */
+  uint32_t bubble_factor;    /* bubbles of unitigs of at most bubble_factor * k edges */
+  uint32_t low_cov_factor;   /* unitigs of at most low_cov_factor * k edges ... */
+  uint32_t low_cov_permille; /* ... below low_cov_permille / 1000 of their neighbours' mean */
+} sdbg_clean_params;
+
 /* Multiple k with contig feedback (Section 2, fourth paragraph, and Fig. 1:
- * graphs are built from a small k to a large one, each is cleaned, and the
- * contigs of one k go into the graph of the next; the reading implemented):
- * for each k of ks (n_k values, ascending, each in [2, 127]):
+ * graphs are built from a small k to a large one, each is cleaned of tips,
+ * bubbles and low local coverage, and the contigs of one k go into the graph
+ * of the next; the reading implemented): for each k of ks (n_k values,
+ * ascending, each in [2, 127]):
  *   1. E = solid edges of the reads (sdbg_count_solid with params' d, mercy,
  *      prefix_len and mem_budget);
  *   2. from the second k on, E = E united with every (k+1)-mer of the
  *      previous k's unitigs, on both strands, with its count of occurrences
  *      in them (sdbg_count_solid of the unitigs with d = 1, no mercy, then
  *      sdbg_edges_union);
- *   3. the graph of E is built, tips of at most tip_factor * k edges are
- *      removed (sdbg_remove_tips; 0 keeps every edge) and the unitigs of the
- *      valid edges are taken (sdbg_unitigs_build).
+ *   3. the graph of E is built and cleaned: tips (sdbg_remove_tips), then
+ *      bubbles (sdbg_merge_bubbles) and then low local coverage
+ *      (sdbg_remove_low_coverage), each on the unitigs of the edges left,
+ *      with the limits of *clean;
+ *   4. the unitigs of the remaining valid edges are taken.
  * *out = the unitigs of the last k (release with sdbg_free).  stats (may be
- * NULL; 4 * n_k words): per k, the edges of E, the edges the unitigs added,
- * the tip edges removed and the unitigs.  Every intermediate object is
- * released before the call returns. */
+ * NULL; 6 * n_k words): per k, the edges of E, the edges the unitigs added,
+ * and the edges removed as tips, in bubbles and for low coverage, then the
+ * unitigs.  Every intermediate object is released before the call
+ * returns. */
 int sdbg_multi_k(const sdbg_reads *reads, const uint32_t *ks, uint32_t n_k, const sdbg_params *params,
-                 uint32_t tip_factor, uint64_t *stats, sdbg_unitigs **out);
+                 const sdbg_clean_params *clean, uint64_t *stats, sdbg_unitigs **out);
 
 /* Wraps host arrays (n*w key words ascending and unique, n counts) into a
  * library-owned device edge set, e.g. to build a graph from edges computed

@@ -10,8 +10,12 @@ ascending order,
 2. from the second k on, every (k+1)-mer of the previous k's unitigs, on
    both strands, joins E with its count of occurrences in them (count_solid
    of the unitigs with d = 1, no mercy), counts of keys in both summed;
-3. tips of at most tip_factor * k edges are removed (oracle/tips.py) and
-   the unitigs of the remaining edges are taken (oracle/unitigs.py).
+3. tips of at most tip_factor * k edges are removed (oracle/tips.py), then
+   bubbles of unitigs of at most bubble_factor * k edges and then unitigs
+   of at most low_cov_factor * k edges below low_cov_permille / 1000 of
+   their neighbours' mean multiplicity (oracle/cleaning.py; a factor of 0
+   skips the step);
+4. the unitigs of the remaining edges are taken (oracle/unitigs.py).
 
 Composes the oracle's own pieces; nothing here comes from the device path.
 """
@@ -21,6 +25,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import count_solid
+from .cleaning import bubbles, low_coverage
 from .tips import key_to_edge, removed_tips
 from .unitigs import unitigs
 
@@ -38,10 +43,11 @@ def _union(a_keys, a_cnt, b_keys, b_cnt):
     return np.array(order, dtype=np.uint64).reshape(len(order), w), np.array([tot[t] for t in order], dtype=np.uint64)
 
 
-def multi_k(seq, offsets, ks, d: int = 2, mercy: bool = True, tip_factor: int = 2):
+def multi_k(seq, offsets, ks, d: int = 2, mercy: bool = True, tip_factor: int = 2, bubble_factor: int = 0,
+            low_cov_factor: int = 0, low_cov_permille: int = 0):
     """Returns (the last k's unitigs as (first edge, edges, multiplicity,
-    sequence) tuples, per-k stats [edges, edges added by the unitigs, tip
-    edges removed, unitigs])."""
+    sequence) tuples, per-k stats [edges, edges added by the unitigs, edges
+    removed as tips, in bubbles and for low coverage, unitigs])."""
     prev = None
     stats = []
     res = []
@@ -54,8 +60,18 @@ def multi_k(seq, offsets, ks, d: int = 2, mercy: bool = True, tip_factor: int = 
             keys, cnt = _union(keys, cnt, ce.keys, ce.counts)
         edges = [key_to_edge(row, k) for row in np.asarray(keys, dtype=np.uint64).reshape(len(cnt), -1)]
         gone = removed_tips(edges, tip_factor * k) if tip_factor else set()
-        res = unitigs(edges, cnt, [x not in gone for x in edges])
-        stats.append([len(edges), len(edges) - n_read, len(gone), len(res)])
+        valid = [x not in gone for x in edges]
+        n_bub = n_low = 0
+        if bubble_factor:
+            b = bubbles(edges, cnt, valid, k, bubble_factor * k)
+            valid = [ok and x not in b for x, ok in zip(edges, valid)]
+            n_bub = len(b)
+        if low_cov_factor:
+            lo = low_coverage(edges, cnt, valid, k, low_cov_factor * k, low_cov_permille)
+            valid = [ok and x not in lo for x, ok in zip(edges, valid)]
+            n_low = len(lo)
+        res = unitigs(edges, cnt, valid)
+        stats.append([len(edges), len(edges) - n_read, len(gone), n_bub, n_low, len(res)])
         text = "".join(r[3] for r in res).encode()
         off = np.zeros(len(res) + 1, dtype=np.uint64)
         off[1:] = np.cumsum([len(r[3]) for r in res])

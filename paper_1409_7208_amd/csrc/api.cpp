@@ -303,17 +303,17 @@ int sdbg_edges_union(const sdbg_edges* a, const sdbg_edges* b, const sdbg_params
 }
 
 int sdbg_multi_k(const sdbg_reads* reads, const uint32_t* ks, uint32_t n_k, const sdbg_params* params,
-                 uint32_t tip_factor, uint64_t* stats, sdbg_unitigs** out) {
+                 const sdbg_clean_params* clean, uint64_t* stats, sdbg_unitigs** out) {
   // Objects of the iteration in flight, released on every exit.
   struct Held {
-    void* p[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    void* p[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     ~Held() {
       for (void* x : p) sdbg_free(x);
     }
   } h;
-  enum { kReadEdges, kContigEdges, kEdgesAll, kGraphI, kIndexI, kPrev };
+  enum { kReadEdges, kContigEdges, kEdgesAll, kGraphI, kIndexI, kPrev, kCur };
   const int rc = guarded([&]() -> int {
-    SDBG_CHECK(reads && ks && params && out && n_k > 0, SDBG_E_INVAL, "null argument");
+    SDBG_CHECK(reads && ks && params && clean && out && n_k > 0, SDBG_E_INVAL, "null argument");
     *out = nullptr;
     for (uint32_t i = 0; i < n_k; ++i) {
       check_k(ks[i]);
@@ -357,9 +357,22 @@ int sdbg_multi_k(const sdbg_reads* reads, const uint32_t* ks, uint32_t n_k, cons
     r = sdbg_index_build(g, &p, reinterpret_cast<sdbg_index**>(&h.p[kIndexI]));
     if (r != SDBG_OK) return r;
     auto* ix = static_cast<sdbg_index*>(h.p[kIndexI]);
-    uint64_t n_tips = 0;
-    r = sdbg_remove_tips(g, ix, tip_factor * ks[i], &n_tips, p.stream);
+    uint64_t n_tips = 0, n_bubble = 0, n_low = 0;
+    r = sdbg_remove_tips(g, ix, clean->tip_factor * ks[i], &n_tips, p.stream);
     if (r != SDBG_OK) return r;
+    // bubbles, then low local coverage, each on the unitigs of the edges left
+    for (int step = 0; step < 2; ++step) {
+      const uint32_t f = step == 0 ? clean->bubble_factor : clean->low_cov_factor;
+      if (f == 0) continue;
+      r = sdbg_unitigs_build(g, ix, reinterpret_cast<sdbg_unitigs**>(&h.p[kCur]), p.stream);
+      if (r != SDBG_OK) return r;
+      auto* cu = static_cast<sdbg_unitigs*>(h.p[kCur]);
+      r = step == 0 ? sdbg_merge_bubbles(g, ix, cu, f * ks[i], &n_bubble, p.stream)
+                    : sdbg_remove_low_coverage(g, ix, cu, f * ks[i], clean->low_cov_permille, &n_low, p.stream);
+      if (r != SDBG_OK) return r;
+      sdbg_free(h.p[kCur]);
+      h.p[kCur] = nullptr;
+    }
     sdbg_unitigs* u = nullptr;
     r = sdbg_unitigs_build(g, ix, &u, p.stream);
     if (r != SDBG_OK) return r;
@@ -369,10 +382,13 @@ int sdbg_multi_k(const sdbg_reads* reads, const uint32_t* ks, uint32_t n_k, cons
     h.p[kIndexI] = h.p[kGraphI] = nullptr;
     h.p[kPrev] = u;
     if (stats) {
-      stats[4 * i + 0] = n_edges;
-      stats[4 * i + 1] = n_edges - n_read_edges;
-      stats[4 * i + 2] = n_tips;
-      stats[4 * i + 3] = u->n;
+      uint64_t* st = stats + 6 * (uint64_t)i;
+      st[0] = n_edges;
+      st[1] = n_edges - n_read_edges;
+      st[2] = n_tips;
+      st[3] = n_bubble;
+      st[4] = n_low;
+      st[5] = u->n;
     }
   }
   *out = static_cast<sdbg_unitigs*>(h.p[kPrev]);

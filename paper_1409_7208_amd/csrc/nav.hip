@@ -159,7 +159,13 @@ DEV uint64_t select_cls(const Nav& v, int s, uint64_t r) {
   }
   const uint8_t want = (uint8_t)((s >> 2) << 3 | ((s & 3) + 1));
   uint64_t left = r - c[lo];
-  for (uint64_t i = lo << 6;; ++i)
+  uint64_t i = lo << 6;
+  for (;; i += 8) {  // eight rows at a time up to the word that holds it
+    const uint64_t n = (uint64_t)count_bytes_eq(w8(v, i), want);
+    if (n > left) break;
+    left -= n;
+  }
+  for (;; ++i)
     if (v.W[i] == want && left-- == 0) return i;
 }
 
@@ -435,9 +441,10 @@ DEV void wave_add(unsigned long long* n, uint64_t x) {
 // anc = predecessor (unresolved) or the row itself | DONE (a first edge);
 // NONE for rows that are not valid edges.  *n_open += unresolved rows.
 __global__ void k_ut_init(Nav v, const uint64_t* __restrict__ valid, uint64_t* __restrict__ anc,
-                          uint64_t* __restrict__ dist, unsigned long long* __restrict__ n_open) {
+                          uint64_t* __restrict__ dist, unsigned long long* __restrict__ n_open,
+                          unsigned long long* __restrict__ n_valid) {
   const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  uint64_t open = 0;
+  uint64_t open = 0, ok = 0;
   if (i < v.m) {
     if (!bit(valid, i)) {
       anc[i] = NONE;
@@ -447,9 +454,11 @@ __global__ void k_ut_init(Nav v, const uint64_t* __restrict__ valid, uint64_t* _
       anc[i] = p == NONE ? (i | DONE) : p;
       dist[i] = p == NONE ? 0 : 1;
       open = p != NONE;
+      ok = 1;
     }
   }
   wave_add(n_open, open);
+  wave_add(n_valid, ok);
 }
 
 // One round of pointer jumping from (a0, d0) into (a1, d1).
@@ -471,6 +480,138 @@ __global__ void k_ut_jump(uint64_t m, const uint64_t* __restrict__ a0, const uin
     }
   }
   wave_add(n_open, open);
+}
+
+// Ones of the bit vector hb before position h (hcum: its counts per word,
+// exclusive scan).
+DEV uint64_t head_rank(const uint64_t* hb, const uint64_t* hcum, uint64_t h) {
+  const uint64_t w = h >> 6, r = h & 63;
+  return hcum[w] + (r ? (uint64_t)__popcll(hb[w] & ((1ull << r) - 1)) : 0);
+}
+
+// Splitters shorten the jumping: every first edge and about one valid row
+// in SPLIT_INV (by a hash of the row) is a splitter; each splitter walks the
+// successor links to the next splitter, labelling the rows it passes with
+// its index and their distance from it; pointer jumping then runs over the
+// splitters alone, and every row adds its distance to its splitter's.
+constexpr int SPLIT_SHIFT = 6;  // one row in 64
+
+DEV bool hashed_splitter(uint64_t i) { return ((i * 0x9E3779B97F4A7C15ull) >> (64 - SPLIT_SHIFT)) == 0; }
+
+// succ[pred[i]] = i for rows with a predecessor (succ filled with NONE).
+__global__ void k_ut_succ(uint64_t m, const uint64_t* __restrict__ anc, uint64_t* __restrict__ succ) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t x = anc[i];
+  if (x != NONE && !(x & DONE)) succ[x] = i;
+}
+
+// Splitter bits and counts per 64-row word (one wave per word).
+__global__ void k_ut_split_mark(uint64_t m, const uint64_t* __restrict__ anc, uint64_t* __restrict__ sb,
+                                uint64_t* __restrict__ sc) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  bool sp = false;
+  if (i < m) {
+    const uint64_t x = anc[i];
+    sp = x != NONE && ((x & DONE) || hashed_splitter(i));
+  }
+  const uint64_t b = __ballot(sp);
+  if ((threadIdx.x & 63) == 0 && i < m) {
+    sb[i >> 6] = b;
+    sc[i >> 6] = __popcll(b);
+  }
+}
+
+// slist[rank] = splitter row.
+__global__ void k_ut_split_list(uint64_t m, const uint64_t* __restrict__ sb, const uint64_t* __restrict__ scum,
+                                uint64_t* __restrict__ slist) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= m || !bit(sb, i)) return;
+  slist[head_rank(sb, scum, i)] = i;
+}
+
+// Splitter j walks to the next splitter: rows passed get lab = j and their
+// distance from it; the next splitter t gets spred[t] = j and sdist[t] = its
+// distance.  Segment j (the splitter and the rows it labels) has seglen[j]
+// rows (TAIL set if it ends its unitig) and segsum[j] = their sum of mult.
+// *n_walked += rows labelled.
+constexpr uint64_t TAIL = 1ull << 63;
+
+__global__ void k_ut_split_walk(uint64_t ns, const uint64_t* __restrict__ slist, const uint64_t* __restrict__ sb,
+                                const uint64_t* __restrict__ scum, const uint64_t* __restrict__ succ,
+                                const uint32_t* __restrict__ mult, uint64_t* __restrict__ lab,
+                                uint64_t* __restrict__ off, uint64_t* __restrict__ spred, uint64_t* __restrict__ sdist,
+                                uint64_t* __restrict__ seglen, uint64_t* __restrict__ segsum,
+                                unsigned long long* __restrict__ n_walked) {
+  const uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t walked = 0;
+  if (j < ns) {
+    const uint64_t s0 = slist[j];
+    uint64_t r = succ[s0], o = 1, sum = mult[s0];
+    while (r != NONE && !bit(sb, r)) {
+      lab[r] = j;
+      off[r] = o;
+      sum += mult[r];
+      r = succ[r];
+      ++o;
+      ++walked;
+    }
+    if (r != NONE) {
+      const uint64_t t = head_rank(sb, scum, r);
+      spred[t] = j;
+      sdist[t] = o;
+    }
+    seglen[j] = o | (r == NONE ? TAIL : 0);
+    segsum[j] = sum;
+  }
+  wave_add(n_walked, walked);
+}
+
+// Splitter-level start of the jumping: anc = spred or self | DONE.
+__global__ void k_ut_split_init(uint64_t ns, const uint64_t* __restrict__ spred, const uint64_t* __restrict__ sdist,
+                                uint64_t* __restrict__ anc, uint64_t* __restrict__ dist,
+                                unsigned long long* __restrict__ n_open) {
+  const uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t open = 0;
+  if (j < ns) {
+    const uint64_t p = spred[j];
+    anc[j] = p == NONE ? (j | DONE) : p;
+    dist[j] = p == NONE ? 0 : sdist[j];
+    open = p != NONE;
+  }
+  wave_add(n_open, open);
+}
+
+// Per splitter (once ranked): its segment's mult into its unitig's sum;
+// the tail segment sets the unitig's length, the first one its first row.
+__global__ void k_ut_split_sums(uint64_t ns, const uint64_t* __restrict__ slist, const uint64_t* __restrict__ sanc,
+                                const uint64_t* __restrict__ sdst, const uint64_t* __restrict__ seglen,
+                                const uint64_t* __restrict__ segsum, const uint64_t* __restrict__ hb,
+                                const uint64_t* __restrict__ hcum, uint64_t* __restrict__ first,
+                                uint64_t* __restrict__ len, unsigned long long* __restrict__ msum) {
+  const uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (j >= ns) return;
+  const uint64_t h = slist[sanc[j] & ~DONE];
+  const uint64_t u = head_rank(hb, hcum, h);
+  atomicAdd(msum + u, (unsigned long long)segsum[j]);
+  if (seglen[j] & TAIL) len[u] = sdst[j] + (seglen[j] & ~TAIL);
+  if (sanc[j] == (j | DONE)) first[u] = slist[j];
+}
+
+// Base k + distance of each valid row's unitig, from its splitter.
+__global__ void k_ut_split_bases(uint64_t m, uint32_t k, const uint8_t* __restrict__ W,
+                                 const uint64_t* __restrict__ anc0, const uint64_t* __restrict__ sb,
+                                 const uint64_t* __restrict__ scum, const uint64_t* __restrict__ slist,
+                                 const uint64_t* __restrict__ sanc, const uint64_t* __restrict__ sdst,
+                                 const uint64_t* __restrict__ lab, const uint64_t* __restrict__ offr,
+                                 const uint64_t* __restrict__ hb, const uint64_t* __restrict__ hcum,
+                                 const uint64_t* __restrict__ off, uint8_t* __restrict__ seq) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= m || anc0[i] == NONE) return;
+  const bool sp = bit(sb, i);
+  const uint64_t j = sp ? head_rank(sb, scum, i) : lab[i];
+  const uint64_t u = head_rank(hb, hcum, slist[sanc[j] & ~DONE]);
+  seq[off[u] + k + sdst[j] + (sp ? 0 : offr[i])] = "ACGT"[(W[i] & 7) - 1];
 }
 
 // Unresolved rows (on cycles): link = predecessor, mn = the row itself.
@@ -532,11 +673,6 @@ __global__ void k_ut_heads(uint64_t m, const uint64_t* __restrict__ anc, uint64_
     hb[i >> 6] = b;
     hc[i >> 6] = __popcll(b);
   }
-}
-
-DEV uint64_t head_rank(const uint64_t* hb, const uint64_t* hcum, uint64_t h) {
-  const uint64_t w = h >> 6, r = h & 63;
-  return hcum[w] + (r ? (uint64_t)__popcll(hb[w] & ((1ull << r) - 1)) : 0);
 }
 
 // Per valid row: its unitig's first row, length (max distance + 1) and
@@ -894,50 +1030,110 @@ int sdbg_unitigs_build(const sdbg_graph* g, const sdbg_index* index, sdbg_unitig
                    d1 = c.buf<uint64_t>(m);
     uint64_t* A[2] = {a0.get(), a1.get()};
     uint64_t* D[2] = {d0.get(), d1.get()};
-    DBuf<unsigned long long> cnt = c.buf<unsigned long long>(2);  // open rows, cycles
+    DBuf<unsigned long long> cnt = c.buf<unsigned long long>(3);  // open rows, cycles, valid rows
     uint64_t* cnt64 = reinterpret_cast<uint64_t*>(cnt.get());
-    fill<uint64_t>(cnt64, 2, 0, c);
+    fill<uint64_t>(cnt64, 3, 0, c);
     int cur = 0;
-    uint64_t open = 0, n_cycles = 0;
+    uint64_t open = 0, n_cycles = 0, n_valid = 0;
     if (m) {
-      k_ut_init<<<grid, SDBG_BLOCK, 0, c.s>>>(v, g->valid, A[0], D[0], cnt.get());
+      k_ut_init<<<grid, SDBG_BLOCK, 0, c.s>>>(v, g->valid, A[0], D[0], cnt.get(), cnt.get() + 2);
       c.check_launch("unitig links");
-      open = c.d2h_one(cnt64);
+      uint64_t h3[3];
+      c.d2h(h3, cnt64, 3);
+      open = h3[0];
+      n_valid = h3[2];
     }
-    // jumping rounds until every row is resolved or a round resolves none
-    auto jump = [&]() {
-      while (open) {
+    // Splitter ranking, for valid edges without cycles.  A[1] holds the
+    // successor links, D[1] each row's splitter and offr its distance from it.
+    DBuf<uint64_t> sb, scum, slist, seglen, segsum, offr, sa[2], sd[2];
+    uint64_t ns = 0;
+    int sc = 0;
+    bool by_splitters = false;
+    if (open) {
+      fill<uint64_t>(A[1], m, NONE, c);
+      k_ut_succ<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[0], A[1]);
+      sb = c.buf<uint64_t>(nw);
+      scum = c.buf<uint64_t>(nw + 1);
+      k_ut_split_mark<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[0], sb.get(), scum.get());
+      c.check_launch("unitig splitters");
+      scan_excl<uint64_t, uint64_t>(scum.get(), scum.get(), nw, scum.get() + nw, c);
+      ns = c.d2h_one(scum.get() + nw);
+    }
+    if (open && ns) {  // (no splitter at all: the open rows lie on cycles)
+      const unsigned sgrid = (unsigned)ceil_div(ns, SDBG_BLOCK);
+      slist = c.buf<uint64_t>(ns);
+      seglen = c.buf<uint64_t>(ns);
+      segsum = c.buf<uint64_t>(ns);
+      offr = c.buf<uint64_t>(m);
+      for (int q = 0; q < 2; ++q) {
+        sa[q] = c.buf<uint64_t>(ns);
+        sd[q] = c.buf<uint64_t>(ns);
+      }
+      DBuf<uint64_t> spred = c.buf<uint64_t>(ns), sdist = c.buf<uint64_t>(ns);
+      k_ut_split_list<<<grid, SDBG_BLOCK, 0, c.s>>>(m, sb.get(), scum.get(), slist.get());
+      fill<uint64_t>(spred.get(), ns, NONE, c);
+      fill<uint64_t>(cnt64, 1, 0, c);
+      k_ut_split_walk<<<sgrid, SDBG_BLOCK, 0, c.s>>>(ns, slist.get(), sb.get(), scum.get(), A[1], g->mult, D[1],
+                                                     offr.get(), spred.get(), sdist.get(), seglen.get(),
+                                                     segsum.get(), cnt.get());
+      c.check_launch("unitig splitter walks");
+      const uint64_t walked = c.d2h_one(cnt64);
+      if (walked + ns == n_valid) {  // every row reached: no cycle without a splitter
         fill<uint64_t>(cnt64, 1, 0, c);
-        k_ut_jump<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], D[cur], A[cur ^ 1], D[cur ^ 1], cnt.get());
-        c.check_launch("unitig jump");
-        cur ^= 1;
-        const uint64_t now = c.d2h_one(cnt64);
-        if (now == open) break;
-        open = now;
+        k_ut_split_init<<<sgrid, SDBG_BLOCK, 0, c.s>>>(ns, spred.get(), sdist.get(), sa[0].get(), sd[0].get(),
+                                                       cnt.get());
+        c.check_launch("unitig splitter links");
+        uint64_t sopen = c.d2h_one(cnt64);
+        while (sopen) {
+          fill<uint64_t>(cnt64, 1, 0, c);
+          k_ut_jump<<<sgrid, SDBG_BLOCK, 0, c.s>>>(ns, sa[sc].get(), sd[sc].get(), sa[sc ^ 1].get(),
+                                                   sd[sc ^ 1].get(), cnt.get());
+          c.check_launch("unitig splitter jump");
+          sc ^= 1;
+          const uint64_t now = c.d2h_one(cnt64);
+          if (now == sopen) break;  // a cycle of splitters
+          sopen = now;
+        }
+        by_splitters = sopen == 0;
       }
-    };
-    jump();
-    if (open) {  // the open rows lie on cycles: open each at its smallest row
-      DBuf<uint64_t> l0 = c.buf<uint64_t>(m), l1 = c.buf<uint64_t>(m), n0 = c.buf<uint64_t>(m),
-                     n1 = c.buf<uint64_t>(m);
-      uint64_t* L[2] = {l0.get(), l1.get()};
-      uint64_t* N[2] = {n0.get(), n1.get()};
-      k_cyc_init<<<grid, SDBG_BLOCK, 0, c.s>>>(v, g->valid, A[cur], L[0], N[0]);
-      c.check_launch("cycle links");
-      int cc = 0;
-      for (uint64_t span = 1; span < open; span <<= 1, cc ^= 1) {
-        k_cyc_min<<<grid, SDBG_BLOCK, 0, c.s>>>(m, L[cc], N[cc], L[cc ^ 1], N[cc ^ 1]);
-        c.check_launch("cycle minimum");
-      }
-      // the jumped links still mark the cycle rows (they never reach NONE)
-      k_cyc_open<<<grid, SDBG_BLOCK, 0, c.s>>>(m, L[cc], N[cc], v, g->valid, A[cur], D[cur], cnt.get() + 1);
-      c.check_launch("cycle open");
-      n_cycles = c.d2h_one(cnt64 + 1);
-      open -= n_cycles;
-      jump();
-      SDBG_CHECK(open == 0, SDBG_E_HIP, "unitig ranking did not converge");
     }
-    // first edges, ranked in row order
+    if (!by_splitters && open) {
+      // Jumping over every row (the valid edges hold cycles), from the links
+      // kernel's A[0] and D[0] ...
+      auto jump = [&]() {
+        while (open) {
+          fill<uint64_t>(cnt64, 1, 0, c);
+          k_ut_jump<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], D[cur], A[cur ^ 1], D[cur ^ 1], cnt.get());
+          c.check_launch("unitig jump");
+          cur ^= 1;
+          const uint64_t now = c.d2h_one(cnt64);
+          if (now == open) break;  // only cycles are left
+          open = now;
+        }
+      };
+      jump();
+      if (open) {  // ... then each cycle opened at its smallest row
+        DBuf<uint64_t> l0 = c.buf<uint64_t>(m), l1 = c.buf<uint64_t>(m), n0 = c.buf<uint64_t>(m),
+                       n1 = c.buf<uint64_t>(m);
+        uint64_t* L[2] = {l0.get(), l1.get()};
+        uint64_t* N[2] = {n0.get(), n1.get()};
+        k_cyc_init<<<grid, SDBG_BLOCK, 0, c.s>>>(v, g->valid, A[cur], L[0], N[0]);
+        c.check_launch("cycle links");
+        int cc = 0;
+        for (uint64_t span = 1; span < open; span <<= 1, cc ^= 1) {
+          k_cyc_min<<<grid, SDBG_BLOCK, 0, c.s>>>(m, L[cc], N[cc], L[cc ^ 1], N[cc ^ 1]);
+          c.check_launch("cycle minimum");
+        }
+        // the jumped links still mark the cycle rows (they never reach NONE)
+        k_cyc_open<<<grid, SDBG_BLOCK, 0, c.s>>>(m, L[cc], N[cc], v, g->valid, A[cur], D[cur], cnt.get() + 1);
+        c.check_launch("cycle open");
+        n_cycles = c.d2h_one(cnt64 + 1);
+        open -= n_cycles;
+        jump();
+        SDBG_CHECK(open == 0, SDBG_E_HIP, "unitig ranking did not converge");
+      }
+    }
+    // first edges, ranked in row order (A[cur]: a first edge holds itself | DONE)
     DBuf<uint64_t> hb = c.buf<uint64_t>(nw ? nw : 1), hcum = c.buf<uint64_t>(nw + 1);
     if (nw) {
       k_ut_heads<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], hb.get(), hcum.get());
@@ -949,7 +1145,12 @@ int sdbg_unitigs_build(const sdbg_graph* g, const sdbg_index* index, sdbg_unitig
                    msum = c.buf<uint64_t>(n ? n : 1), off = c.buf<uint64_t>(n + 1);
     fill<uint64_t>(len.get(), n, 0, c);
     fill<uint64_t>(msum.get(), n, 0, c);
-    if (m) {
+    if (by_splitters) {
+      k_ut_split_sums<<<(unsigned)ceil_div(ns, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(
+          ns, slist.get(), sa[sc].get(), sd[sc].get(), seglen.get(), segsum.get(), hb.get(), hcum.get(), first.get(),
+          len.get(), reinterpret_cast<unsigned long long*>(msum.get()));
+      c.check_launch("unitig sums");
+    } else if (m) {
       k_ut_sums<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], D[cur], g->mult, hb.get(), hcum.get(), first.get(),
                                               reinterpret_cast<unsigned long long*>(len.get()),
                                               reinterpret_cast<unsigned long long*>(msum.get()));
@@ -960,7 +1161,12 @@ int sdbg_unitigs_build(const sdbg_graph* g, const sdbg_index* index, sdbg_unitig
     c.check_launch("unitig offsets");
     const uint64_t n_bases = c.d2h_one(off.get() + n);
     DBuf<uint8_t> seq = c.buf<uint8_t>(n_bases ? n_bases : 1);
-    if (m) {
+    if (by_splitters) {
+      k_ut_split_bases<<<grid, SDBG_BLOCK, 0, c.s>>>(m, g->k, g->W, A[0], sb.get(), scum.get(), slist.get(),
+                                                     sa[sc].get(), sd[sc].get(), D[1], offr.get(), hb.get(),
+                                                     hcum.get(), off.get(), seq.get());
+      c.check_launch("unitig edge bases");
+    } else if (m) {
       k_ut_edge_bases<<<grid, SDBG_BLOCK, 0, c.s>>>(m, g->k, g->W, A[cur], D[cur], hb.get(), hcum.get(),
                                                     off.get(), seq.get());
       c.check_launch("unitig edge bases");

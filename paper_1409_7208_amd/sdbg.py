@@ -525,28 +525,35 @@ def edges_union(a: Edges, b: Edges, stream=None) -> Edges:
     return Edges(out)
 
 
-def multi_k(seq, offsets, ks, d: int = 2, mercy: bool = True, tip_factor: int = 2, prefix_len: int = 8,
-            mem_budget: int = 0, stream=None) -> tuple[Unitigs, np.ndarray]:
-    """Graphs from the smallest k to the largest, each cleaned of tips, the
-    unitigs of one k counted into the next (sdbg_multi_k).  Returns the last
-    k's unitigs and per-k stats (edges, edges added by the unitigs, tip
-    edges removed, unitigs)."""
+class _Clean(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in ("tip_factor", "bubble_factor", "low_cov_factor", "low_cov_permille")]
+
+
+def multi_k(seq, offsets, ks, d: int = 2, mercy: bool = True, tip_factor: int = 2, bubble_factor: int = 2,
+            low_cov_factor: int = 2, low_cov_permille: int = 200, prefix_len: int = 8, mem_budget: int = 0,
+            stream=None) -> tuple[Unitigs, np.ndarray]:
+    """Graphs from the smallest k to the largest, each cleaned (tips,
+    bubbles, low local coverage; limits in multiples of k, 0 skips a step),
+    the unitigs of one k counted into the next (sdbg_multi_k).  Returns the
+    last k's unitigs and per-k stats (edges, edges added by the unitigs,
+    edges removed as tips, in bubbles and for low coverage, unitigs)."""
     lib = load()
     if not getattr(lib, "_multik_api", False):
         P = ctypes.POINTER
-        lib.sdbg_multi_k.argtypes = [P(_Reads), ctypes.c_void_p, ctypes.c_uint32, P(_Params), ctypes.c_uint32,
+        lib.sdbg_multi_k.argtypes = [P(_Reads), ctypes.c_void_p, ctypes.c_uint32, P(_Params), P(_Clean),
                                      ctypes.c_void_p, P(P(_Unitigs))]
         lib.sdbg_multi_k.restype = ctypes.c_int
         lib._multik_api = True
     r, keep = _reads_struct(seq, offsets)
     kk = np.ascontiguousarray(ks, dtype=np.uint32)
-    stats = np.zeros(4 * len(kk), dtype=np.uint64)
+    stats = np.zeros(6 * len(kk), dtype=np.uint64)
     p = _Params(0, d, 1 if mercy else 0, prefix_len, mem_budget, _stream_ptr(stream))
+    cl = _Clean(tip_factor, bubble_factor, low_cov_factor, low_cov_permille)
     out = ctypes.POINTER(_Unitigs)()
-    _check(lib.sdbg_multi_k(ctypes.byref(r), kk.ctypes.data, len(kk), ctypes.byref(p), tip_factor,
+    _check(lib.sdbg_multi_k(ctypes.byref(r), kk.ctypes.data, len(kk), ctypes.byref(p), ctypes.byref(cl),
                             stats.ctypes.data, ctypes.byref(out)))
     del keep
-    return Unitigs(out), stats.reshape(len(kk), 4)
+    return Unitigs(out), stats.reshape(len(kk), 6)
 
 
 def batch_run(sets, k: int, d: int = 2, mercy: bool = False, build: bool = True, prefix_len: int = 8,

@@ -66,17 +66,22 @@ def test_multi_k_bridges_reads():
     g = _genome(random.Random(3), 300)
     _, seq, off = _reads(g)
     want, wst = multik.multi_k(seq, off, [15, 31], d=1, mercy=False)
-    u, st = sdbg.multi_k(seq, off, [15, 31], d=1, mercy=False)
+    u, st = sdbg.multi_k(seq, off, [15, 31], d=1, mercy=False, bubble_factor=0, low_cov_factor=0)
     _compare(u, want, wst, st)
     u.close()
 
 
-@pytest.mark.parametrize("ks", [[21, 41, 61], [31, 81]])
-def test_multi_k_workload(ks):
+@pytest.mark.parametrize("ks,clean", [
+    ([21, 41, 61], (2, 2, 2, 200)),
+    ([31, 81], (2, 0, 0, 0)),
+    ([25, 45], (1, 3, 3, 600)),
+])
+def test_multi_k_workload(ks, clean):
     rs = synth.metagenome(0.002, k=ks[0])
-    want, wst = multik.multi_k(rs.seq, rs.offsets, ks, d=2, mercy=True)
+    want, wst = multik.multi_k(rs.seq, rs.offsets, ks, 2, True, *clean)
     seq, off = to_device(rs)
-    u, st = sdbg.multi_k(seq, off, ks, d=2, mercy=True)
-    say(f"ks={ks}: per k [edges, added by unitigs, tip edges, unitigs] = {st.tolist()}")
+    u, st = sdbg.multi_k(seq, off, ks, d=2, mercy=True, tip_factor=clean[0], bubble_factor=clean[1],
+                         low_cov_factor=clean[2], low_cov_permille=clean[3])
+    say(f"ks={ks} clean={clean}: per k [edges, from unitigs, tips, bubbles, low cov, unitigs] = {st.tolist()}")
     _compare(u, want, wst, st)
     u.close()

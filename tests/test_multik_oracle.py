@@ -13,7 +13,7 @@ import numpy as np
 
 import brute
 import oracle
-from oracle import multik, tips
+from oracle import cleaning, multik, tips
 from oracle import unitigs as U
 
 
@@ -78,4 +78,13 @@ def test_single_k_is_count_tips_unitigs():
     edges = [tips.key_to_edge(row, k) for row in e.keys]
     gone = tips.removed_tips(edges, 2 * k)
     assert res == U.unitigs(edges, e.counts, [x not in gone for x in edges])
-    assert st.tolist() == [[len(edges), 0, len(gone), len(res)]]
+    assert st.tolist() == [[len(edges), 0, len(gone), 0, 0, len(res)]]
+    # with bubbles and low coverage: tips, then bubbles, then low coverage
+    res2, st2 = multik.multi_k(seq, off, [k], 2, True, 2, 2, 2, 400)
+    valid = [x not in gone for x in edges]
+    b = cleaning.bubbles(edges, e.counts, valid, k, 2 * k)
+    valid = [ok and x not in b for x, ok in zip(edges, valid)]
+    lo = cleaning.low_coverage(edges, e.counts, valid, k, 2 * k, 400)
+    valid = [ok and x not in lo for x, ok in zip(edges, valid)]
+    assert res2 == U.unitigs(edges, e.counts, valid)
+    assert st2.tolist() == [[len(edges), 0, len(gone), len(b), len(lo), len(res2)]]
