@@ -451,6 +451,29 @@ typedef struct sdbg_clean_params {
 int sdbg_multi_k(const sdbg_reads *reads, const uint32_t *ks, uint32_t n_k, const sdbg_params *params,
                  const sdbg_clean_params *clean, uint64_t *stats, sdbg_unitigs **out);
 
+/* Burrows-Wheeler transform of a read set (Section 2, second paragraph:
+ * the construction adapts CX1, whose core is sorting every suffix of every
+ * read; the paper gives no details, so this is the multi-string BWT).  Read
+ * r is followed by its own end marker $_r, smaller than every base, with
+ * $_r < $_s for r < s.  Each read of length L has L + 1 suffixes (the last
+ * is $_r alone); n = total bases + n_reads.  Sorted in that order, sa[i] is
+ * the text position of the i-th suffix, where read r's suffix at offset j
+ * (0 <= j <= L) is position offsets[r] + r + j, and bwt[i] is the character
+ * before it in its read ('A', 'C', 'G', 'T', upper case), or '$' for a
+ * suffix that starts its read.  Reads must hold only bases (either case;
+ * SDBG_E_INVAL otherwise) and n + n_reads must stay below 2^32.  Runs on
+ * params->stream (params may be NULL); the result lives in device memory
+ * (release with sdbg_free). */
+typedef struct sdbg_bwt {
+  uint64_t n, n_reads;
+  uint8_t *bwt; /* n characters */
+  uint64_t *sa; /* n text positions */
+} sdbg_bwt;
+int sdbg_read_bwt(const sdbg_reads *reads, const sdbg_params *params, sdbg_bwt **out);
+
+/* Copies a BWT to caller buffers of n bytes and n words (either may be NULL). */
+int sdbg_bwt_to_host(const sdbg_bwt *b, uint8_t *bwt, uint64_t *sa);
+
 /* Wraps host arrays (n*w key words ascending and unique, n counts) into a
  * library-owned device edge set, e.g. to build a graph from edges computed
  * elsewhere. */

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsdbg.so")
-SOURCES = ["runtime.cpp", "api.cpp", "server.cpp", "prims.hip", "count.hip", "build.hip", "noalloc.hip", "nav.hip"]
+SOURCES = ["runtime.cpp", "api.cpp", "server.cpp", "prims.hip", "count.hip", "build.hip", "noalloc.hip", "nav.hip", "bwt.hip"]
 ARCH = os.environ.get("SDBG_OFFLOAD_ARCH", "gfx950")
 
 

@@ -35,11 +35,12 @@ int guarded(F&& f) {
 }
 
 // Object kinds of the registry (sdbg_free releases any registered object).
-enum ObjKind { kEdges = 1, kGraph = 2, kIndex = 3, kUnitigs = 4 };
+enum ObjKind { kEdges = 1, kGraph = 2, kIndex = 3, kUnitigs = 4, kBwt = 5 };
 void reg_add(void* p, int kind);
 int reg_kind(const void* p);
 void free_index(void* p);    // navigation index (nav.hip)
 void free_unitigs(void* p);  // unitig set (nav.hip)
+void free_bwt(void* p);      // read-set BWT (bwt.hip)
 
 void check_k(uint32_t k);
 void check_params(const sdbg_params* p);

@@ -804,6 +804,8 @@ void sdbg_free(void* obj) {
       free_index(obj);
     } else if (kind == kUnitigs) {
       free_unitigs(obj);
+    } else if (kind == kBwt) {
+      free_bwt(obj);
     }
   } catch (...) {
   }

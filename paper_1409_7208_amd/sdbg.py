@@ -556,6 +556,37 @@ def multi_k(seq, offsets, ks, d: int = 2, mercy: bool = True, tip_factor: int = 
     return Unitigs(out), stats.reshape(len(kk), 6)
 
 
+class _Bwt(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("n_reads", ctypes.c_uint64), ("bwt", ctypes.c_void_p),
+                ("sa", ctypes.c_void_p)]
+
+
+def read_bwt(seq, offsets, stream=None) -> tuple[np.ndarray, np.ndarray]:
+    """Multi-string BWT of a read set (sdbg_read_bwt): returns (bwt bytes,
+    suffix array of text positions), copied to the host."""
+    lib = load()
+    if not getattr(lib, "_bwt_api", False):
+        P = ctypes.POINTER
+        lib.sdbg_read_bwt.argtypes = [P(_Reads), P(_Params), P(P(_Bwt))]
+        lib.sdbg_read_bwt.restype = ctypes.c_int
+        lib.sdbg_bwt_to_host.argtypes = [P(_Bwt), ctypes.c_void_p, ctypes.c_void_p]
+        lib.sdbg_bwt_to_host.restype = ctypes.c_int
+        lib._bwt_api = True
+    r, keep = _reads_struct(seq, offsets)
+    p = _Params(0, 0, 0, 0, 0, _stream_ptr(stream))
+    out = ctypes.POINTER(_Bwt)()
+    _check(lib.sdbg_read_bwt(ctypes.byref(r), ctypes.byref(p), ctypes.byref(out)))
+    del keep
+    try:
+        n = out.contents.n
+        b = np.zeros(n + 1, dtype=np.uint8)
+        sa = np.zeros(n + 1, dtype=np.uint64)
+        _check(lib.sdbg_bwt_to_host(out, b.ctypes.data, sa.ctypes.data))
+    finally:
+        lib.sdbg_free(ctypes.cast(out, ctypes.c_void_p))
+    return b[:n], sa[:n]
+
+
 def batch_run(sets, k: int, d: int = 2, mercy: bool = False, build: bool = True, prefix_len: int = 8,
               mem_budget: int = 0, stream=None) -> list[tuple[Edges, Graph | None]]:
     """Batched form: sets is a sequence of (seq, offsets) pairs (device
