@@ -237,6 +237,22 @@ def navigation_rates(sdbg, torch, seq, off, rs, stream):
     return clean
 
 
+def bwt_rate(sdbg, torch, seq, off, stream):
+    """The read-set BWT (every suffix of the workload's reads sorted, on the
+    device; the result is not copied back), HIP events on the call stream."""
+    sdbg.read_bwt(seq, off, stream=stream, to_host=False)  # warm-up
+    ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ea.record(stream)
+    n = sdbg.read_bwt(seq, off, stream=stream, to_host=False)
+    eb.record(stream)
+    torch.cuda.synchronize()
+    ms = ea.elapsed_time(eb)
+    out = {"suffixes": int(n), "ms": round(ms, 1), "suffixes_per_s": round(n / (ms * 1e-3), 1)}
+    log(f"read BWT: {n} suffixes in {ms:.0f} ms ({out['suffixes_per_s'] / 1e9:.2f} G suffixes/s)")
+    return out
+
+
 def bench_batch(args):
     """Batched form against one plain call per set, on the same device-resident
     sets; both build the SdBG of every set."""
@@ -450,7 +466,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-large-k", action="store_true", help="skip the large-k figures (k = 21..99)")
     ap.add_argument("--large-k-steps", type=int, default=2)
-    ap.add_argument("--no-nav", action="store_true", help="skip the navigation index and tip removal figures")
+    ap.add_argument("--no-nav", action="store_true", help="skip the navigation, cleaning, unitig and read-BWT figures")
     ap.add_argument("--stages", action="store_true", help="print per-kernel breakdown to stderr")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (a reference kernel for hardware byte counters)")
@@ -604,9 +620,13 @@ def main():
                      "floor_bytes_per_occ": round(floor_b, 2),
                      "floor_frac": round(value * floor_b / HBM_PEAK_GBS, 4)}
 
-    clean = None
+    clean = bwt = None
     if not args.no_nav:
         clean = navigation_rates(sdbg, torch, seq, off, rs, stream)
+        try:
+            bwt = bwt_rate(sdbg, torch, seq, off, stream)
+        except sdbg.SdbgError as e:  # reads with non-base bytes have no BWT here
+            bwt = {"error": str(e)}
 
     large = multi = None
     if not args.no_large_k and args.workload == "metagenome" and args.scale == 1.0:
@@ -647,6 +667,7 @@ def main():
         out["multi_k"] = multi
     if clean is not None:
         out["navigation"] = clean
+        out["read_bwt"] = bwt
     print(json.dumps(out), flush=True)
 
 

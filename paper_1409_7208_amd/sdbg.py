@@ -561,9 +561,10 @@ class _Bwt(ctypes.Structure):
                 ("sa", ctypes.c_void_p)]
 
 
-def read_bwt(seq, offsets, stream=None) -> tuple[np.ndarray, np.ndarray]:
+def read_bwt(seq, offsets, stream=None, to_host: bool = True):
     """Multi-string BWT of a read set (sdbg_read_bwt): returns (bwt bytes,
-    suffix array of text positions), copied to the host."""
+    suffix array of text positions), copied to the host; with to_host False
+    the result is released on the device and only its length returned."""
     lib = load()
     if not getattr(lib, "_bwt_api", False):
         P = ctypes.POINTER
@@ -579,6 +580,8 @@ def read_bwt(seq, offsets, stream=None) -> tuple[np.ndarray, np.ndarray]:
     del keep
     try:
         n = out.contents.n
+        if not to_host:
+            return n
         b = np.zeros(n + 1, dtype=np.uint8)
         sa = np.zeros(n + 1, dtype=np.uint64)
         _check(lib.sdbg_bwt_to_host(out, b.ctypes.data, sa.ctypes.data))
