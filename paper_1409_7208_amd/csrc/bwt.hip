@@ -6,15 +6,18 @@
 // set is read 0, $_0, read 1, $_1, ..., so read r's suffix at offset j
 // (0 <= j <= len) is text position offsets[r] + r + j.
 //
-// The sort is prefix doubling on the device: the suffixes are first ranked
+// The sort is prefix doubling on the device: the suffixes are first sorted
 // by their first 21 characters (3 bits each, $ = 0 and everything after it
-// 0), then each round ranks them by twice as many characters from the pair
-// (rank of the first h, rank of the next h) -- or, for a suffix whose end
-// marker lies within its first h characters, (rank, read index), which
-// orders equal suffixes of different reads -- until every rank is distinct.
-// Each round sorts (key, position) pairs with a stable least-significant-
-// digit radix sort (8-bit digits; per 2048-element tile, a digit histogram,
-// then a scatter that ranks equal digits within each wave by ballots).
+// 0) into groups of equal prefixes, each named by the place of its first
+// suffix in the order.  Each further round re-sorts only the suffixes of
+// groups that still hold more than one, by (group of the first h
+// characters, group of the next h) -- or, for a suffix whose end marker
+// lies within its first h characters, (group, read index), which orders
+// equal suffixes of different reads -- and splits their groups in place,
+// until every group holds one suffix.  Each round sorts (key, position)
+// pairs with a stable least-significant-digit radix sort (8-bit digits; per
+// 2048-element tile, a digit histogram, then a scatter that ranks equal
+// digits within each wave by ballots).
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -69,17 +72,19 @@ __global__ void k_bwt_first_keys(const uint8_t* __restrict__ seq, const uint64_t
   val[p] = p;
 }
 
-// Doubling key of text position p from the ranks of the first h characters.
-__global__ void k_bwt_pair_keys(const uint64_t* __restrict__ off, const uint32_t* __restrict__ rid,
-                                const uint64_t* __restrict__ rank, uint64_t N, uint64_t n_reads, uint64_t h,
-                                uint64_t* __restrict__ key, uint64_t* __restrict__ val) {
-  const uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (p >= N) return;
-  const uint64_t r = rid[p];
+// Doubling key of unresolved suffix i (text position u[i]) from the group
+// starts of the first h characters: (group, group of the next h) or, when
+// its end marker lies within the first h, (group, read index).
+__global__ void k_bwt_pair_keys(const uint64_t* __restrict__ u, uint64_t m, const uint64_t* __restrict__ off,
+                                const uint32_t* __restrict__ rid, const uint64_t* __restrict__ grp, uint64_t N,
+                                uint64_t n_reads, uint64_t h, uint64_t* __restrict__ key, uint64_t* __restrict__ val) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t p = u[i], r = rid[p];
   const uint64_t end = off[r + 1] + r;  // position of $_r
-  const uint64_t second = end - p + 1 <= h ? r : n_reads + rank[p + h];
-  key[p] = rank[p] * (N + n_reads) + second;
-  val[p] = p;
+  const uint64_t second = end - p + 1 <= h ? r : n_reads + grp[p + h];
+  key[i] = grp[p] * (N + n_reads) + second;
+  val[i] = p;
 }
 
 // Digit counts of each tile, digit-major: hist[d * ntiles + tile].
@@ -147,11 +152,41 @@ __global__ void k_bwt_heads(const uint64_t* __restrict__ key, uint64_t n, uint32
   if (i < n) head[i] = i == 0 || key[i] != key[i - 1] ? 1u : 0u;
 }
 
-// rank[val[i]] = rank of sorted element i (heads before and at i, minus 1).
-__global__ void k_bwt_ranks(const uint32_t* __restrict__ head, const uint64_t* __restrict__ excl,
-                            const uint64_t* __restrict__ val, uint64_t n, uint64_t* __restrict__ rank) {
+// hidx[g] = index of the g-th head (g = heads before it); hidx[total] = m.
+__global__ void k_bwt_head_index(const uint32_t* __restrict__ head, const uint64_t* __restrict__ excl, uint64_t m,
+                                 uint64_t* __restrict__ hidx) {
   const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (i < n) rank[val[i]] = excl[i] + head[i] - 1;
+  if (i >= m) return;
+  if (head[i]) hidx[excl[i]] = i;
+  if (i == 0) hidx[excl[m]] = m;
+}
+
+// Sorted element i of the suffixes being refined (text position val[i];
+// upos[i] = its place in the suffix order, i itself in the first round):
+// its group starts at the place of its group's first element; it takes its
+// place in sa; flag = its group still holds more than one suffix.
+__global__ void k_bwt_refine(const uint64_t* __restrict__ val, const uint32_t* __restrict__ head,
+                             const uint64_t* __restrict__ excl, const uint64_t* __restrict__ hidx,
+                             const uint64_t* __restrict__ upos, uint64_t m, uint64_t* __restrict__ grp,
+                             uint64_t* __restrict__ sa, uint32_t* __restrict__ flag) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t g = excl[i] + head[i] - 1;
+  const uint64_t a = hidx[g], b = hidx[g + 1];
+  const uint64_t p = val[i];
+  grp[p] = upos ? upos[a] : a;
+  sa[upos ? upos[i] : i] = p;
+  flag[i] = b - a > 1 ? 1u : 0u;
+}
+
+// The suffixes of groups still shared, in order: positions and places.
+__global__ void k_bwt_compact(const uint64_t* __restrict__ val, const uint64_t* __restrict__ upos,
+                              const uint32_t* __restrict__ flag, const uint64_t* __restrict__ fpos, uint64_t m,
+                              uint64_t* __restrict__ u_out, uint64_t* __restrict__ upos_out) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= m || !flag[i]) return;
+  u_out[fpos[i]] = val[i];
+  upos_out[fpos[i]] = upos ? upos[i] : i;
 }
 
 // BWT character of sorted suffix i: the character before it in its read, or
@@ -242,32 +277,51 @@ int sdbg_read_bwt(const sdbg_reads* reads, const sdbg_params* params, sdbg_bwt**
       DBuf<uint32_t> rid = c.buf<uint32_t>(N);
       k_bwt_rid<<<grid_of(n_reads), SDBG_BLOCK, 0, c.s>>>(off, n_reads, rid.get());
       c.check_launch("bwt read of position");
+      // keys and positions of the suffixes being sorted (two buffers each),
+      // group start of every suffix, and the refinement's working arrays
       DBuf<uint64_t> ka = c.buf<uint64_t>(N), kb = c.buf<uint64_t>(N), va = c.buf<uint64_t>(N),
-                     vb = c.buf<uint64_t>(N), rank = c.buf<uint64_t>(N), excl = c.buf<uint64_t>(N + 1);
-      DBuf<uint32_t> head = c.buf<uint32_t>(N);
+                     vb = c.buf<uint64_t>(N), grp = c.buf<uint64_t>(N), ulist = c.buf<uint64_t>(N),
+                     upa = c.buf<uint64_t>(N), upb = c.buf<uint64_t>(N), excl = c.buf<uint64_t>(N + 1),
+                     hidx = c.buf<uint64_t>(N + 1), fpos = c.buf<uint64_t>(N + 1);
+      DBuf<uint32_t> head = c.buf<uint32_t>(N), flag = c.buf<uint32_t>(N);
       uint64_t *k0 = ka.get(), *k1 = kb.get(), *v0 = va.get(), *v1 = vb.get();
+      uint64_t *up = nullptr, *up_next = upa.get(), *up_spare = upb.get();
       k_bwt_first_keys<<<grid_of(N), SDBG_BLOCK, 0, c.s>>>(seq, off, rid.get(), N, k0, v0);
       c.check_launch("bwt first keys");
       int bits = 3 * FIRST_CHARS;
-      uint64_t h = FIRST_CHARS;
+      uint64_t h = FIRST_CHARS, m = N;  // m suffixes still to order (all, in the first round)
       for (int round = 0;; ++round) {
         SDBG_CHECK(round < 40, SDBG_E_HIP, "suffix ranking did not converge");
-        radix_sort_pairs(k0, v0, k1, v1, N, bits, c);
-        k_bwt_heads<<<grid_of(N), SDBG_BLOCK, 0, c.s>>>(k0, N, head.get());
+        radix_sort_pairs(k0, v0, k1, v1, m, bits, c);
+        const unsigned g = grid_of(m);
+        k_bwt_heads<<<g, SDBG_BLOCK, 0, c.s>>>(k0, m, head.get());
         c.check_launch("bwt heads");
-        scan_excl<uint32_t, uint64_t>(head.get(), excl.get(), N, excl.get() + N, c);
-        k_bwt_ranks<<<grid_of(N), SDBG_BLOCK, 0, c.s>>>(head.get(), excl.get(), v0, N, rank.get());
-        c.check_launch("bwt ranks");
-        if (c.d2h_one(excl.get() + N) == N) break;  // every suffix has its own rank
-        k_bwt_pair_keys<<<grid_of(N), SDBG_BLOCK, 0, c.s>>>(off, rid.get(), rank.get(), N, n_reads, h, k0, v0);
+        scan_excl<uint32_t, uint64_t>(head.get(), excl.get(), m, excl.get() + m, c);
+        k_bwt_head_index<<<g, SDBG_BLOCK, 0, c.s>>>(head.get(), excl.get(), m, hidx.get());
+        c.check_launch("bwt head index");
+        k_bwt_refine<<<g, SDBG_BLOCK, 0, c.s>>>(v0, head.get(), excl.get(), hidx.get(), up, m, grp.get(), sa.get(),
+                                                flag.get());
+        c.check_launch("bwt refine");
+        scan_excl<uint32_t, uint64_t>(flag.get(), fpos.get(), m, fpos.get() + m, c);
+        const uint64_t nm = c.d2h_one(fpos.get() + m);
+        if (nm == 0) break;  // every suffix has its own place
+        k_bwt_compact<<<g, SDBG_BLOCK, 0, c.s>>>(v0, up, flag.get(), fpos.get(), m, ulist.get(), up_next);
+        c.check_launch("bwt compact");
+        k_bwt_pair_keys<<<grid_of(nm), SDBG_BLOCK, 0, c.s>>>(ulist.get(), nm, off, rid.get(), grp.get(), N, n_reads,
+                                                            h, k0, v0);
         c.check_launch("bwt pair keys");
+        if (!up) {
+          up = up_next;
+          up_next = up_spare;
+        } else {
+          std::swap(up, up_next);
+        }
+        m = nm;
         bits = bits_of((N - 1) * (N + n_reads) + (N + n_reads - 1));
         h *= 2;
       }
-      k_bwt_chars<<<grid_of(N), SDBG_BLOCK, 0, c.s>>>(seq, off, rid.get(), v0, N, chars.get());
+      k_bwt_chars<<<grid_of(N), SDBG_BLOCK, 0, c.s>>>(seq, off, rid.get(), sa.get(), N, chars.get());
       c.check_launch("bwt chars");
-      // the sorted positions are in v0: keep them as the suffix array
-      c.d2d(sa.get(), v0, N);
     }
     c.sync();
     auto* b = new sdbg_bwt();
