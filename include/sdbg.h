@@ -364,8 +364,8 @@ int sdbg_remove_tips(sdbg_graph *g, const sdbg_index *index, uint32_t max_len, u
  * set on the device (sdbg_reads with on_device = 1), so the unitigs of one k
  * can be counted with the reads at the next.  index must have been built
  * on g (SDBG_E_INVAL otherwise).  The result lives in device memory;
- * release it with sdbg_free.  Working memory: about 32 bytes per row, twice
- * that if the valid edges hold cycles. */
+ * release it with sdbg_free.  Working memory: about 40 bytes per row, 32
+ * more if the valid edges hold cycles. */
 typedef struct sdbg_unitigs {
   uint32_t k, reserved;
   uint64_t n;          /* unitigs */
