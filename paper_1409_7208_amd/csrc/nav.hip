@@ -311,64 +311,6 @@ __global__ void k_nav(Nav v, int op, const uint64_t* __restrict__ q, uint64_t n,
   }
 }
 
-// Tip removal (Section 2, fourth paragraph, names it among the cleaning
-// steps and gives no definition; the reading used here): on the graph as
-// built, a forward tip is a path v0 -> ... -> vj (1 <= j <= max_len edges)
-// from a node with no incoming edge through nodes of in- and out-degree 1
-// (v0: out-degree 1) to a node vj with in-degree >= 2 or out-degree 0; a
-// backward tip is its mirror image, from a node with no outgoing edge back
-// to a node with out-degree >= 2 or in-degree 0.  One thread per row: a
-// dummy row starts a forward walk at the node it enters, a '$' row a
-// backward walk at its node.  The walk is taken once to decide and, for a
-// tip, again to clear the valid bits of its edges; validity is not read,
-// so every tip is found on the graph as built and all are removed at once.
-// n_removed counts the valid bits cleared.
-__global__ void k_remove_tips(Nav v, uint64_t* __restrict__ valid, uint32_t max_len,
-                              unsigned long long* __restrict__ n_removed) {
-  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (i >= v.m) return;
-  const bool fwd = bit(v.tip, i), bwd = (v.W[i] & 7) == 0;
-  if (!fwd && !bwd) return;
-  uint32_t len = 0;
-  bool tip = false;
-  if (fwd) {
-    // a node of out-degree 1 has one row, its last row, which is its edge
-    uint64_t cur = nav_forward(v, i);
-    while (len < max_len && nav_outdeg(v, cur) == 1) {
-      cur = nav_forward(v, cur);
-      ++len;
-      const uint64_t in = nav_indeg(v, cur);
-      if (in >= 2 || nav_outdeg(v, cur) == 0) {
-        tip = true;
-        break;
-      }
-      if (in != 1) break;
-    }
-  } else {
-    uint64_t cur = i;  // a node of out-degree 0 has one row, its '$' row
-    while (len < max_len && nav_indeg(v, cur) == 1) {
-      cur = node_of(v, in_row(v, cur, block_of(v, cur)));
-      ++len;
-      const uint64_t out = nav_outdeg(v, cur);
-      if (out >= 2 || nav_indeg(v, cur) == 0) {
-        tip = true;
-        break;
-      }
-      if (out != 1) break;
-    }
-  }
-  if (!tip) return;
-  unsigned long long cleared = 0;
-  uint64_t cur = fwd ? nav_forward(v, i) : i;
-  for (uint32_t s = 0; s < len; ++s) {
-    const uint64_t row = fwd ? cur : in_row(v, cur, block_of(v, cur));
-    const unsigned long long bitm = 1ull << (row & 63);
-    const unsigned long long old = atomicAnd(reinterpret_cast<unsigned long long*>(valid + (row >> 6)), ~bitm);
-    cleared += (old & bitm) ? 1 : 0;
-    cur = fwd ? nav_forward(v, cur) : node_of(v, row);
-  }
-  if (cleared) atomicAdd(n_removed, cleared);
-}
 
 // Unitigs of the valid edges (the contigs that Section 2, fourth paragraph
 // and Fig. 1, carry from one k to the next; the paper gives no
@@ -533,7 +475,8 @@ __global__ void k_ut_split_list(uint64_t m, const uint64_t* __restrict__ sb, con
 // Splitter j walks to the next splitter: rows passed get lab = j and their
 // distance from it; the next splitter t gets spred[t] = j and sdist[t] = its
 // distance.  Segment j (the splitter and the rows it labels) has seglen[j]
-// rows (TAIL set if it ends its unitig) and segsum[j] = their sum of mult.
+// rows (TAIL set if it ends its unitig), segsum[j] = their sum of mult and
+// seglast[j] = its last row.
 // *n_walked += rows labelled.
 constexpr uint64_t TAIL = 1ull << 63;
 
@@ -542,16 +485,17 @@ __global__ void k_ut_split_walk(uint64_t ns, const uint64_t* __restrict__ slist,
                                 const uint32_t* __restrict__ mult, uint64_t* __restrict__ lab,
                                 uint64_t* __restrict__ off, uint64_t* __restrict__ spred, uint64_t* __restrict__ sdist,
                                 uint64_t* __restrict__ seglen, uint64_t* __restrict__ segsum,
-                                unsigned long long* __restrict__ n_walked) {
+                                uint64_t* __restrict__ seglast, unsigned long long* __restrict__ n_walked) {
   const uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   uint64_t walked = 0;
   if (j < ns) {
     const uint64_t s0 = slist[j];
-    uint64_t r = succ[s0], o = 1, sum = mult[s0];
+    uint64_t r = succ[s0], o = 1, sum = mult[s0], prev = s0;
     while (r != NONE && !bit(sb, r)) {
       lab[r] = j;
       off[r] = o;
       sum += mult[r];
+      prev = r;
       r = succ[r];
       ++o;
       ++walked;
@@ -563,6 +507,7 @@ __global__ void k_ut_split_walk(uint64_t ns, const uint64_t* __restrict__ slist,
     }
     seglen[j] = o | (r == NONE ? TAIL : 0);
     segsum[j] = sum;
+    seglast[j] = prev;
   }
   wave_add(n_walked, walked);
 }
@@ -583,18 +528,23 @@ __global__ void k_ut_split_init(uint64_t ns, const uint64_t* __restrict__ spred,
 }
 
 // Per splitter (once ranked): its segment's mult into its unitig's sum;
-// the tail segment sets the unitig's length, the first one its first row.
+// the tail segment sets the unitig's length and last row, the first one its
+// first row.
 __global__ void k_ut_split_sums(uint64_t ns, const uint64_t* __restrict__ slist, const uint64_t* __restrict__ sanc,
                                 const uint64_t* __restrict__ sdst, const uint64_t* __restrict__ seglen,
-                                const uint64_t* __restrict__ segsum, const uint64_t* __restrict__ hb,
-                                const uint64_t* __restrict__ hcum, uint64_t* __restrict__ first,
-                                uint64_t* __restrict__ len, unsigned long long* __restrict__ msum) {
+                                const uint64_t* __restrict__ segsum, const uint64_t* __restrict__ seglast,
+                                const uint64_t* __restrict__ hb, const uint64_t* __restrict__ hcum,
+                                uint64_t* __restrict__ first, uint64_t* __restrict__ len,
+                                unsigned long long* __restrict__ msum, uint64_t* __restrict__ last) {
   const uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (j >= ns) return;
   const uint64_t h = slist[sanc[j] & ~DONE];
   const uint64_t u = head_rank(hb, hcum, h);
   atomicAdd(msum + u, (unsigned long long)segsum[j]);
-  if (seglen[j] & TAIL) len[u] = sdst[j] + (seglen[j] & ~TAIL);
+  if (seglen[j] & TAIL) {
+    len[u] = sdst[j] + (seglen[j] & ~TAIL);
+    last[u] = seglast[j];
+  }
   if (sanc[j] == (j | DONE)) first[u] = slist[j];
 }
 
@@ -690,6 +640,19 @@ __global__ void k_ut_sums(uint64_t m, const uint64_t* __restrict__ anc, const ui
   if (h == i) first[u] = i;
   atomicMax(len + u, (unsigned long long)(dist[i] + 1));
   atomicAdd(msum + u, (unsigned long long)mult[i]);
+}
+
+// last[u] = the row at distance len[u] - 1 of unitig u (rows ranked by
+// jumping over every row).
+__global__ void k_ut_last(uint64_t m, const uint64_t* __restrict__ anc, const uint64_t* __restrict__ dist,
+                          const uint64_t* __restrict__ hb, const uint64_t* __restrict__ hcum,
+                          const uint64_t* __restrict__ len, uint64_t* __restrict__ last) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t x = anc[i];
+  if (x == NONE) return;
+  const uint64_t u = head_rank(hb, hcum, x & ~DONE);
+  if (dist[i] + 1 == len[u]) last[u] = i;
 }
 
 // offsets[u] += k * u (offsets hold the exclusive scan of the lengths).
@@ -854,8 +817,9 @@ __global__ void k_low_cov_flags(Nav v, const uint64_t* __restrict__ valid, const
   flag[u] = cnt && (u128)umult[u] * cnt * 1000 < (u128)ratio_permille * L * sum ? 1 : 0;
 }
 
-// Clears the valid bits of the flagged unitigs' edges.
-__global__ void k_clear_flagged(Nav v, uint64_t* __restrict__ valid, const uint64_t* __restrict__ first,
+// Clears the valid bits of the flagged unitigs' edges; the unitigs are
+// those of the rows set in `walk` (valid itself, or every real row).
+__global__ void k_clear_flagged(Nav v, const uint64_t* walk, uint64_t* valid, const uint64_t* __restrict__ first,
                                 const uint64_t* __restrict__ len, const uint8_t* __restrict__ flag, uint64_t n,
                                 unsigned long long* __restrict__ n_removed) {
   const uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -867,13 +831,52 @@ __global__ void k_clear_flagged(Nav v, uint64_t* __restrict__ valid, const uint6
       const unsigned long long old = atomicAnd(reinterpret_cast<unsigned long long*>(valid + (r >> 6)), ~m);
       cleared += (old & m) ? 1 : 0;
       if (j + 1 == len[u]) break;
-      const uint64_t x = nav_forward(v, r);  // an inner node: its one valid row is the next edge
+      const uint64_t x = nav_forward(v, r);  // an inner node: its one row of `walk` is the next edge
       uint64_t o = NONE;
-      if (x == NONE || valid_out(v, valid, x, &o) != 1) break;
+      if (x == NONE || valid_out(v, walk, x, &o) != 1) break;
       r = o;
     }
   }
   wave_add(n_removed, cleared);
+}
+
+// Tip removal (Section 2, fourth paragraph, names it among the cleaning
+// steps and gives no definition; the reading used here): on the graph as
+// built, a forward tip is a path v0 -> ... -> vj (1 <= j <= max_len edges)
+// from a node with no incoming edge through nodes of in- and out-degree 1
+// (v0: out-degree 1) to a node vj with in-degree >= 2 or out-degree 0; a
+// backward tip is its mirror image, from a node with no outgoing edge back
+// to a node with out-degree >= 2 or in-degree 0.  Such a path is exactly a
+// unitig of the graph as built (every real row) whose ends have those
+// degrees, so the tips are found on the unitigs of the real rows: one
+// thread per unitig looks at its two end nodes, and the flagged unitigs'
+// edges are cleared from the validity vector.  Validity is not read, so
+// every tip is found on the graph as built and all are removed at once.
+
+// Rows that are real edges (a label and no tip bit), one wave per word.
+__global__ void k_real_rows(Nav v, uint64_t* __restrict__ real) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const bool r = i < v.m && (v.W[i] & 7) != 0 && !bit(v.tip, i);
+  const uint64_t b = __ballot(r);
+  if ((threadIdx.x & 63) == 0 && i < v.m) real[i >> 6] = b;
+}
+
+// flag[u] = unitig u of the real rows is a tip of at most max_len edges.
+__global__ void k_tip_flags(Nav v, const uint64_t* __restrict__ real, const uint64_t* __restrict__ first,
+                            const uint64_t* __restrict__ last, const uint64_t* __restrict__ len, uint64_t n,
+                            uint32_t max_len, uint8_t* __restrict__ flag) {
+  const uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  flag[u] = 0;
+  if (len[u] > max_len) return;
+  const uint64_t s = node_of(v, first[u]), t = nav_forward(v, last[u]);
+  uint64_t o;
+  const uint32_t out_s = valid_out(v, real, s, &o), in_s = valid_in(v, real, s, &o);
+  if (in_s == 1 && out_s == 1) return;  // a cycle
+  const uint32_t out_t = valid_out(v, real, t, &o), in_t = valid_in(v, real, t, &o);
+  const bool fwd = in_s == 0 && out_s == 1 && (in_t >= 2 || out_t == 0);
+  const bool bwd = out_t == 0 && in_t == 1 && (out_s >= 2 || in_s == 0);
+  flag[u] = fwd || bwd ? 1 : 0;
 }
 
 }  // namespace
@@ -884,6 +887,193 @@ struct NavIndex {
   uint64_t* counts = nullptr;  // c_last, c_nt, c_tip, then c_cls
   uint32_t* sel = nullptr;     // select directories: node ends, then classes 0..3
 };
+
+}  // namespace sdbg
+
+namespace sdbg {
+
+// Unitigs of the rows set in `valid` (real rows of g; the graph's validity
+// or every real row), ranked as described above; with_seq = false stops
+// after the first rows, lengths, multiplicities and last rows.
+struct UnitigCore {
+  uint64_t n = 0, n_cycles = 0, n_bases = 0;
+  DBuf<uint64_t> first, len, msum, last, off;
+  DBuf<uint8_t> seq;
+};
+
+static void unitig_core(const NavIndex* ix, const sdbg_graph* g, const uint64_t* valid, bool with_seq, Ctx& c,
+                        UnitigCore* out) {
+  const Nav& v = ix->v;
+  const uint64_t m = g->m, nw = ceil_div(m, 64);
+  SDBG_CHECK(ceil_div(m, SDBG_BLOCK) < (1ull << 31), SDBG_E_INVAL, "graph too large");
+  const unsigned grid = (unsigned)ceil_div(m ? m : 1, SDBG_BLOCK);
+  DBuf<uint64_t> a0 = c.buf<uint64_t>(m), a1 = c.buf<uint64_t>(m), d0 = c.buf<uint64_t>(m),
+                 d1 = c.buf<uint64_t>(m);
+  uint64_t* A[2] = {a0.get(), a1.get()};
+  uint64_t* D[2] = {d0.get(), d1.get()};
+  DBuf<unsigned long long> cnt = c.buf<unsigned long long>(3);  // open rows, cycles, valid rows
+  uint64_t* cnt64 = reinterpret_cast<uint64_t*>(cnt.get());
+  fill<uint64_t>(cnt64, 3, 0, c);
+  int cur = 0;
+  uint64_t open = 0, n_cycles = 0, n_valid = 0;
+  if (m) {
+    k_ut_init<<<grid, SDBG_BLOCK, 0, c.s>>>(v, valid, A[0], D[0], cnt.get(), cnt.get() + 2);
+    c.check_launch("unitig links");
+    uint64_t h3[3];
+    c.d2h(h3, cnt64, 3);
+    open = h3[0];
+    n_valid = h3[2];
+  }
+  // Splitter ranking, for valid edges without cycles.  A[1] holds the
+  // successor links, D[1] each row's splitter and offr its distance from it.
+  DBuf<uint64_t> sb, scum, slist, seglen, segsum, seglast, offr, sa[2], sd[2];
+  uint64_t ns = 0;
+  int sc = 0;
+  bool by_splitters = false;
+  if (open) {
+    fill<uint64_t>(A[1], m, NONE, c);
+    k_ut_succ<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[0], A[1]);
+    sb = c.buf<uint64_t>(nw);
+    scum = c.buf<uint64_t>(nw + 1);
+    k_ut_split_mark<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[0], sb.get(), scum.get());
+    c.check_launch("unitig splitters");
+    scan_excl<uint64_t, uint64_t>(scum.get(), scum.get(), nw, scum.get() + nw, c);
+    ns = c.d2h_one(scum.get() + nw);
+  }
+  if (open && ns) {  // (no splitter at all: the open rows lie on cycles)
+    const unsigned sgrid = (unsigned)ceil_div(ns, SDBG_BLOCK);
+    slist = c.buf<uint64_t>(ns);
+    seglen = c.buf<uint64_t>(ns);
+    segsum = c.buf<uint64_t>(ns);
+    seglast = c.buf<uint64_t>(ns);
+    offr = c.buf<uint64_t>(m);
+    for (int q = 0; q < 2; ++q) {
+      sa[q] = c.buf<uint64_t>(ns);
+      sd[q] = c.buf<uint64_t>(ns);
+    }
+    DBuf<uint64_t> spred = c.buf<uint64_t>(ns), sdist = c.buf<uint64_t>(ns);
+    k_ut_split_list<<<grid, SDBG_BLOCK, 0, c.s>>>(m, sb.get(), scum.get(), slist.get());
+    fill<uint64_t>(spred.get(), ns, NONE, c);
+    fill<uint64_t>(cnt64, 1, 0, c);
+    k_ut_split_walk<<<sgrid, SDBG_BLOCK, 0, c.s>>>(ns, slist.get(), sb.get(), scum.get(), A[1], g->mult, D[1],
+                                                   offr.get(), spred.get(), sdist.get(), seglen.get(),
+                                                   segsum.get(), seglast.get(), cnt.get());
+    c.check_launch("unitig splitter walks");
+    const uint64_t walked = c.d2h_one(cnt64);
+    if (walked + ns == n_valid) {  // every row reached: no cycle without a splitter
+      fill<uint64_t>(cnt64, 1, 0, c);
+      k_ut_split_init<<<sgrid, SDBG_BLOCK, 0, c.s>>>(ns, spred.get(), sdist.get(), sa[0].get(), sd[0].get(),
+                                                     cnt.get());
+      c.check_launch("unitig splitter links");
+      uint64_t sopen = c.d2h_one(cnt64);
+      while (sopen) {
+        fill<uint64_t>(cnt64, 1, 0, c);
+        k_ut_jump<<<sgrid, SDBG_BLOCK, 0, c.s>>>(ns, sa[sc].get(), sd[sc].get(), sa[sc ^ 1].get(),
+                                                 sd[sc ^ 1].get(), cnt.get());
+        c.check_launch("unitig splitter jump");
+        sc ^= 1;
+        const uint64_t now = c.d2h_one(cnt64);
+        if (now == sopen) break;  // a cycle of splitters
+        sopen = now;
+      }
+      by_splitters = sopen == 0;
+    }
+  }
+  if (!by_splitters && open) {
+    // Jumping over every row (the valid edges hold cycles), from the links
+    // kernel's A[0] and D[0] ...
+    auto jump = [&]() {
+      while (open) {
+        fill<uint64_t>(cnt64, 1, 0, c);
+        k_ut_jump<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], D[cur], A[cur ^ 1], D[cur ^ 1], cnt.get());
+        c.check_launch("unitig jump");
+        cur ^= 1;
+        const uint64_t now = c.d2h_one(cnt64);
+        if (now == open) break;  // only cycles are left
+        open = now;
+      }
+    };
+    jump();
+    if (open) {  // ... then each cycle opened at its smallest row
+      DBuf<uint64_t> l0 = c.buf<uint64_t>(m), l1 = c.buf<uint64_t>(m), n0 = c.buf<uint64_t>(m),
+                     n1 = c.buf<uint64_t>(m);
+      uint64_t* L[2] = {l0.get(), l1.get()};
+      uint64_t* N[2] = {n0.get(), n1.get()};
+      k_cyc_init<<<grid, SDBG_BLOCK, 0, c.s>>>(v, valid, A[cur], L[0], N[0]);
+      c.check_launch("cycle links");
+      int cc = 0;
+      for (uint64_t span = 1; span < open; span <<= 1, cc ^= 1) {
+        k_cyc_min<<<grid, SDBG_BLOCK, 0, c.s>>>(m, L[cc], N[cc], L[cc ^ 1], N[cc ^ 1]);
+        c.check_launch("cycle minimum");
+      }
+      // the jumped links still mark the cycle rows (they never reach NONE)
+      k_cyc_open<<<grid, SDBG_BLOCK, 0, c.s>>>(m, L[cc], N[cc], v, valid, A[cur], D[cur], cnt.get() + 1);
+      c.check_launch("cycle open");
+      n_cycles = c.d2h_one(cnt64 + 1);
+      open -= n_cycles;
+      jump();
+      SDBG_CHECK(open == 0, SDBG_E_HIP, "unitig ranking did not converge");
+    }
+  }
+  // first edges, ranked in row order (A[cur]: a first edge holds itself | DONE)
+  DBuf<uint64_t> hb = c.buf<uint64_t>(nw ? nw : 1), hcum = c.buf<uint64_t>(nw + 1);
+  if (nw) {
+    k_ut_heads<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], hb.get(), hcum.get());
+    c.check_launch("unitig heads");
+  }
+  scan_excl<uint64_t, uint64_t>(hcum.get(), hcum.get(), nw, hcum.get() + nw, c);
+  const uint64_t n = c.d2h_one(hcum.get() + nw);
+  DBuf<uint64_t>& first = out->first;
+  DBuf<uint64_t>& len = out->len;
+  DBuf<uint64_t>& msum = out->msum;
+  DBuf<uint64_t>& last = out->last;
+  first = c.buf<uint64_t>(n ? n : 1);
+  len = c.buf<uint64_t>(n ? n : 1);
+  msum = c.buf<uint64_t>(n ? n : 1);
+  last = c.buf<uint64_t>(n ? n : 1);
+  fill<uint64_t>(len.get(), n, 0, c);
+  fill<uint64_t>(msum.get(), n, 0, c);
+  if (by_splitters) {
+    k_ut_split_sums<<<(unsigned)ceil_div(ns, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(
+        ns, slist.get(), sa[sc].get(), sd[sc].get(), seglen.get(), segsum.get(), seglast.get(), hb.get(),
+        hcum.get(), first.get(), len.get(), reinterpret_cast<unsigned long long*>(msum.get()), last.get());
+    c.check_launch("unitig sums");
+  } else if (m) {
+    k_ut_sums<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], D[cur], g->mult, hb.get(), hcum.get(), first.get(),
+                                            reinterpret_cast<unsigned long long*>(len.get()),
+                                            reinterpret_cast<unsigned long long*>(msum.get()));
+    c.check_launch("unitig sums");
+    k_ut_last<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], D[cur], hb.get(), hcum.get(), len.get(), last.get());
+    c.check_launch("unitig last rows");
+  }
+  out->n = n;
+  out->n_cycles = n_cycles;
+  if (!with_seq) return;
+  DBuf<uint64_t>& off = out->off;
+  off = c.buf<uint64_t>(n + 1);
+  scan_excl<uint64_t, uint64_t>(len.get(), off.get(), n, off.get() + n, c);
+  k_ut_offsets<<<(unsigned)ceil_div(n + 1, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(n, g->k, off.get());
+  c.check_launch("unitig offsets");
+  const uint64_t n_bases = c.d2h_one(off.get() + n);
+  out->n_bases = n_bases;
+  DBuf<uint8_t>& seq = out->seq;
+  seq = c.buf<uint8_t>(n_bases ? n_bases : 1);
+  if (by_splitters) {
+    k_ut_split_bases<<<grid, SDBG_BLOCK, 0, c.s>>>(m, g->k, g->W, A[0], sb.get(), scum.get(), slist.get(),
+                                                   sa[sc].get(), sd[sc].get(), D[1], offr.get(), hb.get(),
+                                                   hcum.get(), off.get(), seq.get());
+    c.check_launch("unitig edge bases");
+  } else if (m) {
+    k_ut_edge_bases<<<grid, SDBG_BLOCK, 0, c.s>>>(m, g->k, g->W, A[cur], D[cur], hb.get(), hcum.get(),
+                                                  off.get(), seq.get());
+    c.check_launch("unitig edge bases");
+  }
+  if (n) {
+    k_ut_node_bases<<<(unsigned)ceil_div(n, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(v, n, first.get(), off.get(),
+                                                                              seq.get());
+    c.check_launch("unitig node bases");
+  }
+}
 
 }  // namespace sdbg
 
@@ -1001,9 +1191,21 @@ int sdbg_remove_tips(sdbg_graph* g, const sdbg_index* index, uint32_t max_len, u
     fill<uint64_t>(reinterpret_cast<uint64_t*>(cnt.get()), 1, 0, c);
     if (g->m && max_len) {
       SDBG_CHECK(ceil_div(g->m, SDBG_BLOCK) < (1ull << 31), SDBG_E_INVAL, "graph too large");
-      k_remove_tips<<<(unsigned)ceil_div(g->m, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(ix->v, g->valid, max_len,
-                                                                                  cnt.get());
-      c.check_launch("remove_tips");
+      DBuf<uint64_t> real = c.buf<uint64_t>(ceil_div(g->m, 64));
+      k_real_rows<<<(unsigned)ceil_div(g->m, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(ix->v, real.get());
+      c.check_launch("real rows");
+      UnitigCore uc;
+      unitig_core(ix, g, real.get(), false, c, &uc);
+      if (uc.n) {
+        const unsigned grid = (unsigned)ceil_div(uc.n, SDBG_BLOCK);
+        DBuf<uint8_t> flag = c.buf<uint8_t>(uc.n);
+        k_tip_flags<<<grid, SDBG_BLOCK, 0, c.s>>>(ix->v, real.get(), uc.first.get(), uc.last.get(), uc.len.get(),
+                                                  uc.n, max_len, flag.get());
+        c.check_launch("tip flags");
+        k_clear_flagged<<<grid, SDBG_BLOCK, 0, c.s>>>(ix->v, real.get(), g->valid, uc.first.get(), uc.len.get(),
+                                                      flag.get(), uc.n, cnt.get());
+        c.check_launch("clear tips");
+      }
     }
     unsigned long long h = 0;
     c.d2h(&h, cnt.get(), 1);
@@ -1021,172 +1223,20 @@ int sdbg_unitigs_build(const sdbg_graph* g, const sdbg_index* index, sdbg_unitig
     SDBG_CHECK(sdbg_abi::reg_kind(index) == sdbg_abi::kIndex, SDBG_E_INVAL, "not an index returned by this library");
     const NavIndex* ix = reinterpret_cast<const NavIndex*>(index);
     SDBG_CHECK(ix->v.W == g->W && ix->v.m == g->m, SDBG_E_INVAL, "the index was not built on this graph");
-    const Nav& v = ix->v;
-    const uint64_t m = g->m, nw = ceil_div(m, 64);
-    SDBG_CHECK(ceil_div(m, SDBG_BLOCK) < (1ull << 31), SDBG_E_INVAL, "graph too large");
     Ctx c(stream);
-    const unsigned grid = (unsigned)ceil_div(m ? m : 1, SDBG_BLOCK);
-    DBuf<uint64_t> a0 = c.buf<uint64_t>(m), a1 = c.buf<uint64_t>(m), d0 = c.buf<uint64_t>(m),
-                   d1 = c.buf<uint64_t>(m);
-    uint64_t* A[2] = {a0.get(), a1.get()};
-    uint64_t* D[2] = {d0.get(), d1.get()};
-    DBuf<unsigned long long> cnt = c.buf<unsigned long long>(3);  // open rows, cycles, valid rows
-    uint64_t* cnt64 = reinterpret_cast<uint64_t*>(cnt.get());
-    fill<uint64_t>(cnt64, 3, 0, c);
-    int cur = 0;
-    uint64_t open = 0, n_cycles = 0, n_valid = 0;
-    if (m) {
-      k_ut_init<<<grid, SDBG_BLOCK, 0, c.s>>>(v, g->valid, A[0], D[0], cnt.get(), cnt.get() + 2);
-      c.check_launch("unitig links");
-      uint64_t h3[3];
-      c.d2h(h3, cnt64, 3);
-      open = h3[0];
-      n_valid = h3[2];
-    }
-    // Splitter ranking, for valid edges without cycles.  A[1] holds the
-    // successor links, D[1] each row's splitter and offr its distance from it.
-    DBuf<uint64_t> sb, scum, slist, seglen, segsum, offr, sa[2], sd[2];
-    uint64_t ns = 0;
-    int sc = 0;
-    bool by_splitters = false;
-    if (open) {
-      fill<uint64_t>(A[1], m, NONE, c);
-      k_ut_succ<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[0], A[1]);
-      sb = c.buf<uint64_t>(nw);
-      scum = c.buf<uint64_t>(nw + 1);
-      k_ut_split_mark<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[0], sb.get(), scum.get());
-      c.check_launch("unitig splitters");
-      scan_excl<uint64_t, uint64_t>(scum.get(), scum.get(), nw, scum.get() + nw, c);
-      ns = c.d2h_one(scum.get() + nw);
-    }
-    if (open && ns) {  // (no splitter at all: the open rows lie on cycles)
-      const unsigned sgrid = (unsigned)ceil_div(ns, SDBG_BLOCK);
-      slist = c.buf<uint64_t>(ns);
-      seglen = c.buf<uint64_t>(ns);
-      segsum = c.buf<uint64_t>(ns);
-      offr = c.buf<uint64_t>(m);
-      for (int q = 0; q < 2; ++q) {
-        sa[q] = c.buf<uint64_t>(ns);
-        sd[q] = c.buf<uint64_t>(ns);
-      }
-      DBuf<uint64_t> spred = c.buf<uint64_t>(ns), sdist = c.buf<uint64_t>(ns);
-      k_ut_split_list<<<grid, SDBG_BLOCK, 0, c.s>>>(m, sb.get(), scum.get(), slist.get());
-      fill<uint64_t>(spred.get(), ns, NONE, c);
-      fill<uint64_t>(cnt64, 1, 0, c);
-      k_ut_split_walk<<<sgrid, SDBG_BLOCK, 0, c.s>>>(ns, slist.get(), sb.get(), scum.get(), A[1], g->mult, D[1],
-                                                     offr.get(), spred.get(), sdist.get(), seglen.get(),
-                                                     segsum.get(), cnt.get());
-      c.check_launch("unitig splitter walks");
-      const uint64_t walked = c.d2h_one(cnt64);
-      if (walked + ns == n_valid) {  // every row reached: no cycle without a splitter
-        fill<uint64_t>(cnt64, 1, 0, c);
-        k_ut_split_init<<<sgrid, SDBG_BLOCK, 0, c.s>>>(ns, spred.get(), sdist.get(), sa[0].get(), sd[0].get(),
-                                                       cnt.get());
-        c.check_launch("unitig splitter links");
-        uint64_t sopen = c.d2h_one(cnt64);
-        while (sopen) {
-          fill<uint64_t>(cnt64, 1, 0, c);
-          k_ut_jump<<<sgrid, SDBG_BLOCK, 0, c.s>>>(ns, sa[sc].get(), sd[sc].get(), sa[sc ^ 1].get(),
-                                                   sd[sc ^ 1].get(), cnt.get());
-          c.check_launch("unitig splitter jump");
-          sc ^= 1;
-          const uint64_t now = c.d2h_one(cnt64);
-          if (now == sopen) break;  // a cycle of splitters
-          sopen = now;
-        }
-        by_splitters = sopen == 0;
-      }
-    }
-    if (!by_splitters && open) {
-      // Jumping over every row (the valid edges hold cycles), from the links
-      // kernel's A[0] and D[0] ...
-      auto jump = [&]() {
-        while (open) {
-          fill<uint64_t>(cnt64, 1, 0, c);
-          k_ut_jump<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], D[cur], A[cur ^ 1], D[cur ^ 1], cnt.get());
-          c.check_launch("unitig jump");
-          cur ^= 1;
-          const uint64_t now = c.d2h_one(cnt64);
-          if (now == open) break;  // only cycles are left
-          open = now;
-        }
-      };
-      jump();
-      if (open) {  // ... then each cycle opened at its smallest row
-        DBuf<uint64_t> l0 = c.buf<uint64_t>(m), l1 = c.buf<uint64_t>(m), n0 = c.buf<uint64_t>(m),
-                       n1 = c.buf<uint64_t>(m);
-        uint64_t* L[2] = {l0.get(), l1.get()};
-        uint64_t* N[2] = {n0.get(), n1.get()};
-        k_cyc_init<<<grid, SDBG_BLOCK, 0, c.s>>>(v, g->valid, A[cur], L[0], N[0]);
-        c.check_launch("cycle links");
-        int cc = 0;
-        for (uint64_t span = 1; span < open; span <<= 1, cc ^= 1) {
-          k_cyc_min<<<grid, SDBG_BLOCK, 0, c.s>>>(m, L[cc], N[cc], L[cc ^ 1], N[cc ^ 1]);
-          c.check_launch("cycle minimum");
-        }
-        // the jumped links still mark the cycle rows (they never reach NONE)
-        k_cyc_open<<<grid, SDBG_BLOCK, 0, c.s>>>(m, L[cc], N[cc], v, g->valid, A[cur], D[cur], cnt.get() + 1);
-        c.check_launch("cycle open");
-        n_cycles = c.d2h_one(cnt64 + 1);
-        open -= n_cycles;
-        jump();
-        SDBG_CHECK(open == 0, SDBG_E_HIP, "unitig ranking did not converge");
-      }
-    }
-    // first edges, ranked in row order (A[cur]: a first edge holds itself | DONE)
-    DBuf<uint64_t> hb = c.buf<uint64_t>(nw ? nw : 1), hcum = c.buf<uint64_t>(nw + 1);
-    if (nw) {
-      k_ut_heads<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], hb.get(), hcum.get());
-      c.check_launch("unitig heads");
-    }
-    scan_excl<uint64_t, uint64_t>(hcum.get(), hcum.get(), nw, hcum.get() + nw, c);
-    const uint64_t n = c.d2h_one(hcum.get() + nw);
-    DBuf<uint64_t> first = c.buf<uint64_t>(n ? n : 1), len = c.buf<uint64_t>(n ? n : 1),
-                   msum = c.buf<uint64_t>(n ? n : 1), off = c.buf<uint64_t>(n + 1);
-    fill<uint64_t>(len.get(), n, 0, c);
-    fill<uint64_t>(msum.get(), n, 0, c);
-    if (by_splitters) {
-      k_ut_split_sums<<<(unsigned)ceil_div(ns, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(
-          ns, slist.get(), sa[sc].get(), sd[sc].get(), seglen.get(), segsum.get(), hb.get(), hcum.get(), first.get(),
-          len.get(), reinterpret_cast<unsigned long long*>(msum.get()));
-      c.check_launch("unitig sums");
-    } else if (m) {
-      k_ut_sums<<<grid, SDBG_BLOCK, 0, c.s>>>(m, A[cur], D[cur], g->mult, hb.get(), hcum.get(), first.get(),
-                                              reinterpret_cast<unsigned long long*>(len.get()),
-                                              reinterpret_cast<unsigned long long*>(msum.get()));
-      c.check_launch("unitig sums");
-    }
-    scan_excl<uint64_t, uint64_t>(len.get(), off.get(), n, off.get() + n, c);
-    k_ut_offsets<<<(unsigned)ceil_div(n + 1, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(n, g->k, off.get());
-    c.check_launch("unitig offsets");
-    const uint64_t n_bases = c.d2h_one(off.get() + n);
-    DBuf<uint8_t> seq = c.buf<uint8_t>(n_bases ? n_bases : 1);
-    if (by_splitters) {
-      k_ut_split_bases<<<grid, SDBG_BLOCK, 0, c.s>>>(m, g->k, g->W, A[0], sb.get(), scum.get(), slist.get(),
-                                                     sa[sc].get(), sd[sc].get(), D[1], offr.get(), hb.get(),
-                                                     hcum.get(), off.get(), seq.get());
-      c.check_launch("unitig edge bases");
-    } else if (m) {
-      k_ut_edge_bases<<<grid, SDBG_BLOCK, 0, c.s>>>(m, g->k, g->W, A[cur], D[cur], hb.get(), hcum.get(),
-                                                    off.get(), seq.get());
-      c.check_launch("unitig edge bases");
-    }
-    if (n) {
-      k_ut_node_bases<<<(unsigned)ceil_div(n, SDBG_BLOCK), SDBG_BLOCK, 0, c.s>>>(v, n, first.get(), off.get(),
-                                                                                seq.get());
-      c.check_launch("unitig node bases");
-    }
+    UnitigCore uc;
+    unitig_core(ix, g, g->valid, true, c, &uc);
     c.sync();
     auto* u = new sdbg_unitigs();
     u->k = g->k;
-    u->n = n;
-    u->n_cycles = n_cycles;
-    u->n_bases = n_bases;
-    u->first_row = first.release_ownership();
-    u->len = len.release_ownership();
-    u->mult = msum.release_ownership();
-    u->offsets = off.release_ownership();
-    u->seq = seq.release_ownership();
+    u->n = uc.n;
+    u->n_cycles = uc.n_cycles;
+    u->n_bases = uc.n_bases;
+    u->first_row = uc.first.release_ownership();
+    u->len = uc.len.release_ownership();
+    u->mult = uc.msum.release_ownership();
+    u->offsets = uc.off.release_ownership();
+    u->seq = uc.seq.release_ownership();
     sdbg_abi::reg_add(u, sdbg_abi::kUnitigs);
     *out = u;
     return SDBG_OK;
@@ -1238,8 +1288,8 @@ static int clean_by_unitigs(sdbg_graph* g, const sdbg_index* index, const sdbg_u
         k_bubble_flags<<<grid, SDBG_BLOCK, 0, c.s>>>(ix->v, g->valid, u->first_row, u->len, u->mult, u->n, max_len,
                                                      flag.get());
       c.check_launch(low_cov ? "low coverage flags" : "bubble flags");
-      k_clear_flagged<<<grid, SDBG_BLOCK, 0, c.s>>>(ix->v, g->valid, u->first_row, u->len, flag.get(), u->n,
-                                                    cnt.get());
+      k_clear_flagged<<<grid, SDBG_BLOCK, 0, c.s>>>(ix->v, g->valid, g->valid, u->first_row, u->len, flag.get(),
+                                                    u->n, cnt.get());
       c.check_launch("clear flagged unitigs");
     }
     unsigned long long h = 0;
