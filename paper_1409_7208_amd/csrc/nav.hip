@@ -319,11 +319,13 @@ __global__ void k_nav(Nav v, int op, const uint64_t* __restrict__ q, uint64_t n,
 // An edge continues the unitig of its predecessor iff its source node is
 // (in 1, out 1); the predecessor is then that node's one valid entering
 // edge.  Ranks along each unitig come from pointer jumping over the
-// predecessor links (a row's link jumps to its link's link each round, in
-// two buffers so that every round reads the previous one), which needs
-// about log2 of the longest unitig rounds over the rows; a row whose link
+// predecessor links (a link jumps to its link's link each round, in two
+// buffers so that every round reads the previous one; a row whose link
 // reaches a unitig's first edge is resolved: it holds that edge and its
-// distance from it.  Cycles of (in 1, out 1) nodes have no first edge: once
+// distance from it).  The jumping runs over splitters -- every first edge
+// and about one row in 64 -- after each splitter has walked the rows up to
+// the next one (below); only when the valid edges hold cycles of (in 1,
+// out 1) nodes, which have no first edge, does it run over every row: once
 // a round resolves nothing new, the remaining rows lie on cycles, each
 // cycle is opened at its smallest row (the minimum over the cycle by
 // doubling) and the jumping resumes.
