@@ -104,3 +104,47 @@ def test_tune_parameters_validated_on_host():
     assert sdbg.tune_get() == t
     sdbg.tune_set(None)
     assert sdbg.tune_get() == default
+
+
+def test_graph_and_bwt_calls_reject_bad_arguments_on_the_host():
+    """The unitig, cleaning, union, multi-k and BWT calls check their
+    arguments before any device work: null pointers, objects the library
+    never returned, and k values that do not ascend."""
+    _ensure_built()
+    sdbg.load()
+    lib = ctypes.CDLL(sdbg.LIB_PATH)  # own function objects: the binding's signatures stay as they are
+    lib.sdbg_last_error.restype = ctypes.c_char_p
+    V = ctypes.c_void_p
+    lib.sdbg_unitigs_build.argtypes = [V, V, V, V]
+    lib.sdbg_merge_bubbles.argtypes = [V, V, V, ctypes.c_uint32, V, V]
+    lib.sdbg_remove_low_coverage.argtypes = [V, V, V, ctypes.c_uint32, ctypes.c_uint32, V, V]
+    lib.sdbg_remove_tips.argtypes = [V, V, ctypes.c_uint32, V, V]
+    lib.sdbg_edges_union.argtypes = [V, V, V, V]
+    lib.sdbg_multi_k.argtypes = [V, V, ctypes.c_uint32, V, V, V, V]
+    lib.sdbg_read_bwt.argtypes = [V, V, V]
+    lib.sdbg_bwt_to_host.argtypes = [V, V, V]
+    lib.sdbg_unitigs_to_host.argtypes = [V, V, V, V, V, V]
+    out = V()
+    fake_g, fake_e = sdbg._Graph(), sdbg._Edges()
+    gp, ep = ctypes.addressof(fake_g), ctypes.addressof(fake_e)
+    assert lib.sdbg_unitigs_build(None, None, ctypes.byref(out), None) == -1
+    assert lib.sdbg_unitigs_build(gp, gp, ctypes.byref(out), None) == -1  # not library objects
+    assert lib.sdbg_merge_bubbles(gp, gp, gp, 10, None, None) == -1
+    assert lib.sdbg_remove_low_coverage(gp, gp, gp, 10, 200, None, None) == -1
+    assert lib.sdbg_remove_tips(gp, gp, 10, None, None) == -1
+    assert lib.sdbg_edges_union(ep, ep, None, ctypes.byref(out)) == -1
+    assert lib.sdbg_edges_union(None, ep, None, ctypes.byref(out)) == -1
+    r = sdbg._Reads(None, None, 0, 0, 0)
+    p = sdbg._Params(0, 2, 1, 8, 0, None)
+    cl = sdbg._Clean(2, 2, 2, 200)
+    ks = (ctypes.c_uint32 * 2)(41, 21)  # descending
+    assert lib.sdbg_multi_k(ctypes.byref(r), ks, 2, ctypes.byref(p), ctypes.byref(cl), None, ctypes.byref(out)) == -1
+    assert "ascend" in lib.sdbg_last_error().decode()
+    ks_bad = (ctypes.c_uint32 * 1)(200)  # k out of range
+    assert lib.sdbg_multi_k(ctypes.byref(r), ks_bad, 1, ctypes.byref(p), ctypes.byref(cl), None,
+                            ctypes.byref(out)) == -1
+    assert lib.sdbg_multi_k(ctypes.byref(r), ks, 2, ctypes.byref(p), None, None, ctypes.byref(out)) == -1
+    assert lib.sdbg_read_bwt(None, None, ctypes.byref(out)) == -1
+    assert lib.sdbg_bwt_to_host(gp, None, None) == -1
+    assert lib.sdbg_unitigs_to_host(gp, None, None, None, None, None) == -1
+    assert not out
